@@ -8,8 +8,11 @@ sharing code) are:
 
 * pivot: the column of largest remaining 2-norm; ties go to the smallest
   ORIGINAL column index;
-* pivoting moves columns by swaps (position j <-> position of the pivot), so the
-  full permutation J is the classical one of a column-pivoted QR;
+* the first k entries of J are the pivots in the order chosen; the remaining
+  entries J(k+1:n) list the other columns in increasing index order (the paper
+  fixes only that P moves the skeleton to the front; V* = [I T] P* does not
+  depend on how the residual columns are ordered as long as T follows J). The
+  elimination itself moves columns by swaps, as a column-pivoted QR does;
 * Householder sign: alpha = -sgn(x0) |x| with sgn(0) = +1; J, T and all errors
   are invariant to this choice (row signs of S cancel in S11^{-1} S12);
 * the remaining column norms are recomputed exactly at every step (no
@@ -39,8 +42,8 @@ def default_rank_tol(l: int, unit_roundoff: float = U64) -> float:
 
 @dataclass
 class CPQRResult:
-    J: np.ndarray            # int64, full permutation of 0..n-1, pivots first
-    S: np.ndarray            # k_out x n, rows of S in PIVOTED column order
+    J: np.ndarray            # int64, pivots in order, then the rest ascending
+    S: np.ndarray            # k_out x n, columns of S in the order of J
     k_out: int               # number of Householder steps taken
     pivot_norms: np.ndarray  # |x| of each pivot column at its step (= |S(j,j)|)
     gaps: np.ndarray         # (nu_1 - nu_2)/nu_1 at each step (best vs runner-up)
@@ -107,6 +110,10 @@ def cpqr(Y: np.ndarray, kmax: int, tol: float | None = None,
         Y[j + 1:, j] = 0.0
         pivot_norms.append(normx)
         j += 1
-    return CPQRResult(J=perm, S=Y[:j, :].copy(), k_out=j,
+    # present S by original column, then in the order [pivots, rest ascending]
+    S_orig = np.zeros((j, n))
+    S_orig[:, perm] = Y[:j, :]
+    J = np.concatenate([perm[:j], np.sort(perm[j:])])
+    return CPQRResult(J=J, S=S_orig[:, J], k_out=j,
                       pivot_norms=np.array(pivot_norms), gaps=np.array(gaps),
                       stop=stop, res_fro=res_fro)

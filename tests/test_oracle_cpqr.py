@@ -158,6 +158,18 @@ def test_power_of_two_scaling_is_bitwise_invariant():
     assert np.array_equal(a.S * 2.0 ** 7, b.S)
 
 
+def test_permutation_layout():
+    Y = _well_separated(10, 30, 28)
+    res = cpqr(Y, 6)
+    assert sorted(res.J) == list(range(30))
+    assert list(res.J[6:]) == sorted(res.J[6:])
+    # S columns follow J: S11 upper triangular, and Y(:,J) = Q1 S1 + residual
+    assert np.abs(np.tril(res.S[:, :6], -1)).max() == 0.0
+    Q = np.linalg.lstsq(res.S[:, :6].T, Y[:, res.J[:6]].T, rcond=None)[0].T
+    assert np.abs(Q.T @ Q - np.eye(6)).max() < 1e-12
+    assert np.abs(Q.T @ Y[:, res.J] - res.S).max() < 1e-12 * np.abs(Y).max()
+
+
 def test_unpivoted_mode_is_householder_qr():
     Y = synth.rng(27).standard_normal((12, 5))
     res = cpqr(Y, 5, pivot=False)
