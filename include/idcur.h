@@ -1,0 +1,167 @@
+/*
+ * idcur.h -- C ABI of the MI355X (gfx950) interpolative-decomposition / CUR
+ * library (libidcur.so).
+ *
+ * The operations follow Voronin & Martinsson, "Efficient Algorithms for CUR and
+ * Interpolative Matrix Decompositions":
+ *   idcur_id_col        column ID  A ~ A(:, J(1:k)) [I_k T] P*      (Section 2.3, Algorithm 1)
+ *   idcur_id_row        row ID     A ~ W A(I(1:k), :)                (remark closing Section 2.3)
+ *   idcur_id_two_sided  two-sided  A ~ W A(I(1:k), J(1:k)) V*        (Section 2.4, Algorithm 2)
+ *   idcur_cur           CUR-ID     A ~ C U R                         (Section 3, Algorithm 3)
+ * each deterministic (k steps of column-pivoted QR on A itself) or randomized
+ * (Section 5: Y = Omega A with an (k+p) x m Gaussian Omega, eq. (Y=OmegaA), then
+ * q orthonormalised power steps, Section 5.3, then k CPQR steps on Y).
+ *
+ * Conventions shared by every entry point
+ *   - All matrices are ROW-MAJOR with an explicit leading dimension (elements
+ *     between consecutive rows). A is m x n.
+ *   - Every array argument is a DEVICE pointer owned by the caller, except
+ *     where marked "host". The library never allocates or frees caller memory.
+ *   - Scratch memory is a caller-provided device workspace whose size comes from
+ *     idcur_workspace_bytes() for the same (op, dtype, m, n, opts).
+ *   - Indices are 0-based int32. J (length n) and I (length m) are full
+ *     permutations with the skeleton first: J[0..k-1] are the selected columns.
+ *   - Work is enqueued on the context's stream; calls return before the device
+ *     finishes. Argument errors are returned synchronously (nothing is enqueued).
+ *     Conditions found on the device (rank cap, non-finite data, a grid wait
+ *     that exceeded its spin limit) are written to a device status word that
+ *     idcur_sync_status() reads after synchronising the stream.
+ *   - Outputs are undefined when a call returns an error.
+ */
+#ifndef IDCUR_H
+#define IDCUR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct idcur_ctx idcur_ctx;
+
+typedef enum {
+  IDCUR_OK = 0,
+  IDCUR_EINVAL = -1,      /* invalid argument (sizes, rank, leading dimension, null pointer) */
+  IDCUR_EDTYPE = -2,      /* unsupported dtype / precision combination */
+  IDCUR_EWORKSPACE = -3,  /* workspace missing or smaller than idcur_workspace_bytes() */
+  IDCUR_EHIP = -4,        /* a HIP runtime call failed (message in idcur_last_error) */
+  IDCUR_ERANKCAP = -5,    /* device: tolerance not met within the rank cap */
+  IDCUR_ENONFINITE = -6,  /* device: NaN or Inf met in the column norms */
+  IDCUR_ETIMEOUT = -7     /* device: a grid-wide wait exceeded its spin limit */
+} idcur_status;
+
+typedef enum { IDCUR_F64 = 0, IDCUR_F32 = 1 } idcur_dtype;
+
+/* Input precision of the sketch and power-step GEMMs (accumulation is FP32). */
+typedef enum { IDCUR_PREC_NATIVE = 0, IDCUR_PREC_BF16 = 1, IDCUR_PREC_FP16 = 2 } idcur_prec;
+
+/* How the CPQR keeps the trailing column norms between pivots: downdated
+ * (nu^2 -= s^2, recomputed from the data when the downdate has cancelled) or
+ * recomputed exactly at every step. */
+typedef enum { IDCUR_NORMS_DOWNDATE = 0, IDCUR_NORMS_EXACT = 1 } idcur_norms;
+
+typedef enum {
+  IDCUR_OP_ID_COL = 0,
+  IDCUR_OP_ID_ROW = 1,
+  IDCUR_OP_TWO_SIDED = 2,
+  IDCUR_OP_CUR = 3
+} idcur_op;
+
+typedef struct {
+  int32_t k;          /* > 0: fixed rank, k < min(m, n). 0: tolerance mode.            */
+  int32_t kmax;       /* rank cap in tolerance mode (ignored when k > 0).               */
+  double tol;         /* tolerance mode: smallest k with |Y_res|_F <= tol |Y|_F
+                         (Section 3: continue the QR until |E| is below a threshold). */
+  double rank_tol;    /* stop early (exact rank deficiency, Section 2.3) when the
+                         largest remaining column norm <= rank_tol * largest initial
+                         norm; 0 selects 10 sqrt(l) u with u the unit roundoff of dtype */
+  int32_t p;          /* oversampling (Section 5.1); < 0: deterministic, Y = A.         */
+  int32_t q;          /* orthonormalised power steps (Section 5.3), >= 0.               */
+  uint64_t seed;      /* Philox4x32-10 key for Omega when omega == NULL.                */
+  const void* omega;  /* optional device Omega, l x m row-major (l = k+p, or kmax+p),
+                         leading dimension m, same dtype as A; NULL: generated.        */
+  int32_t prec;       /* idcur_prec of the sketch GEMMs.                                 */
+  int32_t norms;      /* idcur_norms.                                                    */
+} idcur_opts;
+
+/* Fill *opts with defaults: k = 0, kmax = 0, tol = 0, rank_tol = 0, p = -1
+ * (deterministic), q = 0, seed = 0, omega = NULL, NATIVE precision, downdated norms. */
+void idcur_opts_default(idcur_opts* opts /* host */);
+
+/* Create a context bound to `stream` (a hipStream_t, borrowed, may be NULL for the
+ * null stream). Allocates the context's small device status block on the current
+ * device. Returns IDCUR_EHIP if that fails. */
+idcur_status idcur_create(idcur_ctx** ctx /* host out */, void* stream);
+idcur_status idcur_set_stream(idcur_ctx* ctx, void* stream);
+idcur_status idcur_destroy(idcur_ctx* ctx);
+
+/* Message for the last error returned by a call on this context (host string,
+ * valid until the next call on the context). */
+const char* idcur_last_error(const idcur_ctx* ctx);
+
+/* Synchronise the context's stream, read and clear the device status word.
+ * Returns IDCUR_OK or one of the device conditions (ERANKCAP, ENONFINITE, ETIMEOUT). */
+idcur_status idcur_sync_status(idcur_ctx* ctx);
+
+/* Workspace size in bytes for one call of `op` (idcur_op) with these arguments. */
+idcur_status idcur_workspace_bytes(idcur_ctx* ctx, int32_t op, int32_t dtype, int64_t m, int64_t n,
+                                   const idcur_opts* opts /* host */, size_t* bytes /* host out */);
+
+/* Column ID (Section 2.3 eq. (S11T=S12), (column_approx_id2); Algorithm 1, or
+ * Algorithm 4 with the power scheme of Section 5.3 when opts->p >= 0).
+ *   A      m x n, leading dimension lda >= n.
+ *   k_out  device int32[1]: the rank produced (k, or less on exact rank
+ *          deficiency, or the tolerance-mode rank).
+ *   J      device int32[n]: column permutation, skeleton first.
+ *   T      device, dtype of A: k_out x (n - k_out) interpolation matrix, row r at
+ *          T + r*ldt; ldt >= n - k (fixed rank) or >= n (tolerance mode, where the
+ *          caller sizes T as kmax x n). Columns t >= ldt are never written: when
+ *          exact rank deficiency makes k_out < k, pass ldt >= n - k_out (ldt = n
+ *          always suffices) to receive all of T.
+ * V* = [I T] P* is not formed: V*(:, J[s]) = e_s, V*(:, J[k+t]) = T(:, t). */
+idcur_status idcur_id_col(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+                          const idcur_opts* opts, void* ws, size_t ws_bytes,
+                          int32_t* k_out, int32_t* J, void* T, int64_t ldt);
+
+/* Row ID (remark closing Section 2.3): the column ID of A^T, computed from A in
+ * place (no transposed copy). I (device int32[m]) is the row permutation, Tr the
+ * k_out x (m - k_out) row interpolation matrix (ldtr as ldt above with m for n);
+ * W = P [I_k; Tr^T] with row I[r] of W equal to e_r^T for r < k_out.
+ * With p >= 0 the sketch is Omega A^T, Omega of size l x n. */
+idcur_status idcur_id_row(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+                          const idcur_opts* opts, void* ws, size_t ws_bytes,
+                          int32_t* k_out, int32_t* I, void* Tr, int64_t ldtr);
+
+/* Two-sided ID (Section 2.4 eq. (boat), (two_sided_approx_id); Algorithm 2):
+ * the column ID (J, T) of A, then a full-rank ID of C^T with C = A(:, J(1:k)),
+ * giving I and Tr (k x (m - k)). k_out is device int32[2]: {column rank, rank of C}. */
+idcur_status idcur_id_two_sided(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, const void* A,
+                                int64_t lda, const idcur_opts* opts, void* ws, size_t ws_bytes,
+                                int32_t* k_out, int32_t* J, void* T, int64_t ldt,
+                                int32_t* I, void* Tr, int64_t ldtr);
+
+/* CUR-ID (Section 3 eq. (choice_C_and_R), (defU); Algorithm 3):
+ * C = A(:, J(1:k)) (m x k), R = A(I(1:k), :) (k x n), U = V* R^+ (k x k), U solving
+ * U R = V* in the least-squares sense (Section 4.3) through a QR factorisation of
+ * R^T. k_out as for the two-sided ID. C and R are optional (NULL: not written).
+ * U has leading dimension ldu >= k (kmax in tolerance mode). */
+idcur_status idcur_cur(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+                       const idcur_opts* opts, void* ws, size_t ws_bytes, int32_t* k_out,
+                       int32_t* J, int32_t* I, void* U, int64_t ldu,
+                       void* C, int64_t ldc, void* R, int64_t ldr);
+
+/* The Gaussian sketch matrix alone (Section 5.1: i.i.d. N(0,1) entries): writes
+ * Omega(r, i), r < rows, i < cols, to out + r*ldo + i. Entry (r, i) is defined by
+ * the Philox4x32-10 counter (f/4 mod 2^32, f/4 div 2^32, stream, 0), f = r*cols + i,
+ * key (seed mod 2^32, seed div 2^32), and a Box-Muller transform of its four
+ * words (u1 = (x+1)/2^32, u2 = x'/2^32). This is the matrix the ID calls draw
+ * when opts->omega is NULL (stream 0). */
+idcur_status idcur_gaussian(idcur_ctx* ctx, int32_t dtype, int64_t rows, int64_t cols, uint64_t seed,
+                            uint64_t stream, void* out, int64_t ldo);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IDCUR_H */

@@ -1,0 +1,305 @@
+"""Interpolative (ID) and CUR decompositions on AMD MI355X (gfx950).
+
+A thin ctypes binding over ``libidcur.so`` (C ABI in ``include/idcur.h``): it
+allocates device buffers with torch, passes raw pointers and the current HIP
+stream, and trims the outputs to the rank the device produced. Every step of
+the computation runs in the library's HIP kernels; there is no host fallback
+and importing this package fails if the library has not been built
+(``python -m paper_1412_8447_amd.build``).
+
+Entry points (names as in the C ABI, Section references to Voronin &
+Martinsson, "Efficient Algorithms for CUR and Interpolative Matrix
+Decompositions"):
+
+* ``id_col``        column ID, Section 2.3 / Algorithm 1 (Algorithm 4 with p >= 0)
+* ``id_row``        row ID, the column ID of A^T (remark closing Section 2.3)
+* ``id_two_sided``  two-sided ID, Section 2.4 / Algorithm 2
+* ``cur``           CUR-ID, Section 3 / Algorithm 3
+* ``gaussian``      the Philox4x32-10 Gaussian sketch matrix of Section 5.1
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+from .flops import flop_model  # noqa: F401  (host-side accounting, no compute)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libidcur.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_1412_8447_amd.build` "
+        "(there is no fallback implementation)"
+    )
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ---------------------------------------------------------------------------
+# C declarations
+# ---------------------------------------------------------------------------
+OK, EINVAL, EDTYPE, EWORKSPACE, EHIP, ERANKCAP, ENONFINITE, ETIMEOUT = 0, -1, -2, -3, -4, -5, -6, -7
+F64, F32 = 0, 1
+PREC_NATIVE, PREC_BF16, PREC_FP16 = 0, 1, 2
+NORMS_DOWNDATE, NORMS_EXACT = 0, 1
+OP_ID_COL, OP_ID_ROW, OP_TWO_SIDED, OP_CUR = 0, 1, 2, 3
+
+STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", EDTYPE: "EDTYPE", EWORKSPACE: "EWORKSPACE", EHIP: "EHIP",
+                ERANKCAP: "ERANKCAP", ENONFINITE: "ENONFINITE", ETIMEOUT: "ETIMEOUT"}
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_int32),
+        ("kmax", ctypes.c_int32),
+        ("tol", ctypes.c_double),
+        ("rank_tol", ctypes.c_double),
+        ("p", ctypes.c_int32),
+        ("q", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("omega", ctypes.c_void_p),
+        ("prec", ctypes.c_int32),
+        ("norms", ctypes.c_int32),
+    ]
+
+
+_vp, _i32, _i64, _sz, _u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_uint64
+_lib.idcur_opts_default.argtypes = [ctypes.POINTER(Opts)]
+_lib.idcur_opts_default.restype = None
+_lib.idcur_create.argtypes = [ctypes.POINTER(_vp), _vp]
+_lib.idcur_set_stream.argtypes = [_vp, _vp]
+_lib.idcur_destroy.argtypes = [_vp]
+_lib.idcur_last_error.argtypes = [_vp]
+_lib.idcur_last_error.restype = ctypes.c_char_p
+_lib.idcur_sync_status.argtypes = [_vp]
+_lib.idcur_workspace_bytes.argtypes = [_vp, _i32, _i32, _i64, _i64, ctypes.POINTER(Opts), ctypes.POINTER(_sz)]
+_common = [_vp, _i32, _i64, _i64, _vp, _i64, ctypes.POINTER(Opts), _vp, _sz, _vp]
+_lib.idcur_id_col.argtypes = _common + [_vp, _vp, _i64]
+_lib.idcur_id_row.argtypes = _common + [_vp, _vp, _i64]
+_lib.idcur_id_two_sided.argtypes = _common + [_vp, _vp, _i64, _vp, _vp, _i64]
+_lib.idcur_cur.argtypes = _common + [_vp, _vp, _vp, _i64, _vp, _i64, _vp, _i64]
+_lib.idcur_gaussian.argtypes = [_vp, _i32, _i64, _i64, _u64, _u64, _vp, _i64]
+for _f in ("idcur_create", "idcur_set_stream", "idcur_destroy", "idcur_sync_status", "idcur_workspace_bytes",
+           "idcur_id_col", "idcur_id_row", "idcur_id_two_sided", "idcur_cur", "idcur_gaussian"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+EXPORTED = ("idcur_opts_default", "idcur_create", "idcur_set_stream", "idcur_destroy", "idcur_last_error",
+            "idcur_sync_status", "idcur_workspace_bytes", "idcur_id_col", "idcur_id_row", "idcur_id_two_sided",
+            "idcur_cur", "idcur_gaussian")
+
+
+class IDCurError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+# ---------------------------------------------------------------------------
+# Context (one per device, bound to torch's current stream at each call)
+# ---------------------------------------------------------------------------
+_ctx: dict = {}
+
+
+def _context(device: torch.device) -> ctypes.c_void_p:
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    if idx not in _ctx:
+        with torch.cuda.device(idx):
+            h = _vp()
+            st = _lib.idcur_create(ctypes.byref(h), _vp(torch.cuda.current_stream(idx).cuda_stream))
+            if st != OK:
+                raise IDCurError(st, "idcur_create failed")
+            _ctx[idx] = h
+    h = _ctx[idx]
+    _lib.idcur_set_stream(h, _vp(torch.cuda.current_stream(idx).cuda_stream))
+    return h
+
+
+def _check(h, st: int) -> None:
+    if st != OK:
+        raise IDCurError(st, _lib.idcur_last_error(h).decode())
+
+
+def sync_status(device=None) -> int:
+    """Synchronise and return the device status code (0 when clean); raises on
+    device-side errors other than the rank cap."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    h = _context(dev)
+    st = _lib.idcur_sync_status(h)
+    if st not in (OK, ERANKCAP):
+        raise IDCurError(st, _lib.idcur_last_error(h).decode())
+    return st
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise IDCurError(EDTYPE, f"unsupported dtype {t.dtype}")
+
+
+def make_opts(k: int = 0, *, tol: float = 0.0, kmax: int = 0, p: int = -1, q: int = 0, seed: int = 0,
+              omega: Optional[torch.Tensor] = None, rank_tol: float = 0.0, norms: str = "downdate",
+              prec: str = "native") -> Opts:
+    o = Opts()
+    _lib.idcur_opts_default(ctypes.byref(o))
+    o.k, o.kmax, o.tol, o.rank_tol = int(k), int(kmax), float(tol), float(rank_tol)
+    o.p, o.q, o.seed = int(p), int(q), int(seed)
+    o.omega = omega.data_ptr() if omega is not None else None
+    o.norms = {"downdate": NORMS_DOWNDATE, "exact": NORMS_EXACT}[norms]
+    o.prec = {"native": PREC_NATIVE, "bf16": PREC_BF16, "fp16": PREC_FP16}[prec]
+    return o
+
+
+def workspace_bytes(op: int, A: torch.Tensor, opts: Opts) -> int:
+    h = _context(A.device)
+    n = ctypes.c_size_t(0)
+    _check(h, _lib.idcur_workspace_bytes(h, op, _dtype_code(A), A.shape[0], A.shape[1], ctypes.byref(opts),
+                                         ctypes.byref(n)))
+    return int(n.value)
+
+
+def _prep(A: torch.Tensor, omega):
+    if not A.is_cuda:
+        raise IDCurError(EINVAL, "A must be a device tensor")
+    if A.dim() != 2 or A.stride(1) != 1:
+        raise IDCurError(EINVAL, "A must be a 2-D row-major tensor (unit column stride)")
+    if omega is not None:
+        if not omega.is_cuda or omega.dtype != A.dtype or not omega.is_contiguous():
+            raise IDCurError(EINVAL, "omega must be a contiguous device tensor of A's dtype")
+    return _context(A.device)
+
+
+def _ws(h, op, A, o, workspace):
+    need = workspace_bytes(op, A, o)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=A.device)
+    return workspace
+
+
+@dataclass
+class ColumnID:
+    J: torch.Tensor          # int32 (n,)
+    T: torch.Tensor          # (k, n-k)
+    k: int
+
+
+@dataclass
+class TwoSided:
+    J: torch.Tensor
+    T: torch.Tensor
+    I: torch.Tensor
+    Tr: torch.Tensor
+    k: int
+    k_row: int
+
+
+@dataclass
+class CUR:
+    J: torch.Tensor
+    I: torch.Tensor
+    C: torch.Tensor
+    U: torch.Tensor
+    R: torch.Tensor
+    k: int
+    k_row: int
+
+
+def id_col(A: torch.Tensor, k: int = 0, *, workspace=None, sync: bool = True, **kw) -> ColumnID:
+    """Column ID A ~ A(:, J[:k]) [I T] P*. Keyword options as :func:`make_opts`."""
+    h = _prep(A, kw.get("omega"))
+    o = make_opts(k, **kw)
+    m, n = A.shape
+    kcap = o.k if o.k > 0 else o.kmax
+    ws = _ws(h, OP_ID_COL, A, o, workspace)
+    J = torch.empty(n, dtype=torch.int32, device=A.device)
+    ldt = n
+    T = torch.empty(max(kcap, 1), max(ldt, 1), dtype=A.dtype, device=A.device)
+    kout = torch.zeros(2, dtype=torch.int32, device=A.device)
+    _check(h, _lib.idcur_id_col(h, _dtype_code(A), m, n, A.data_ptr(), A.stride(0), ctypes.byref(o), ws.data_ptr(),
+                                ws.numel(), kout.data_ptr(), J.data_ptr(), T.data_ptr(), max(ldt, 1)))
+    if not sync:
+        return ColumnID(J, T, -1)
+    sync_status(A.device)
+    kk = int(kout[0].item())
+    return ColumnID(J, T[:kk, : n - kk], kk)
+
+
+def id_row(A: torch.Tensor, k: int = 0, *, workspace=None, sync: bool = True, **kw) -> ColumnID:
+    """Row ID A ~ W A(I[:k], :), returned as ColumnID(J=I, T=Tr)."""
+    h = _prep(A, kw.get("omega"))
+    o = make_opts(k, **kw)
+    m, n = A.shape
+    kcap = o.k if o.k > 0 else o.kmax
+    ws = _ws(h, OP_ID_ROW, A, o, workspace)
+    I = torch.empty(m, dtype=torch.int32, device=A.device)
+    ldt = m
+    Tr = torch.empty(max(kcap, 1), max(ldt, 1), dtype=A.dtype, device=A.device)
+    kout = torch.zeros(2, dtype=torch.int32, device=A.device)
+    _check(h, _lib.idcur_id_row(h, _dtype_code(A), m, n, A.data_ptr(), A.stride(0), ctypes.byref(o), ws.data_ptr(),
+                                ws.numel(), kout.data_ptr(), I.data_ptr(), Tr.data_ptr(), max(ldt, 1)))
+    if not sync:
+        return ColumnID(I, Tr, -1)
+    sync_status(A.device)
+    kk = int(kout[0].item())
+    return ColumnID(I, Tr[:kk, : m - kk], kk)
+
+
+def id_two_sided(A: torch.Tensor, k: int = 0, *, workspace=None, **kw) -> TwoSided:
+    h = _prep(A, kw.get("omega"))
+    o = make_opts(k, **kw)
+    m, n = A.shape
+    kcap = o.k if o.k > 0 else o.kmax
+    ws = _ws(h, OP_TWO_SIDED, A, o, workspace)
+    J = torch.empty(n, dtype=torch.int32, device=A.device)
+    I = torch.empty(m, dtype=torch.int32, device=A.device)
+    ldt, ldtr = n, m
+    T = torch.empty(max(kcap, 1), max(ldt, 1), dtype=A.dtype, device=A.device)
+    Tr = torch.empty(max(kcap, 1), max(ldtr, 1), dtype=A.dtype, device=A.device)
+    kout = torch.zeros(2, dtype=torch.int32, device=A.device)
+    _check(h, _lib.idcur_id_two_sided(h, _dtype_code(A), m, n, A.data_ptr(), A.stride(0), ctypes.byref(o),
+                                      ws.data_ptr(), ws.numel(), kout.data_ptr(), J.data_ptr(), T.data_ptr(),
+                                      max(ldt, 1), I.data_ptr(), Tr.data_ptr(), max(ldtr, 1)))
+    sync_status(A.device)
+    k1, k2 = (int(v) for v in kout.tolist())
+    return TwoSided(J, T[:k1, : n - k1], I, Tr[:k2, : m - k2], k1, k2)
+
+
+def cur(A: torch.Tensor, k: int = 0, *, workspace=None, sync: bool = True, out=None, **kw) -> CUR:
+    """CUR-ID: C = A(:, J[:k]), R = A(I[:k], :), U = V* R^+."""
+    h = _prep(A, kw.get("omega"))
+    o = make_opts(k, **kw)
+    m, n = A.shape
+    kcap = o.k if o.k > 0 else o.kmax
+    ws = _ws(h, OP_CUR, A, o, workspace)
+    if out is None:
+        out = dict(
+            J=torch.empty(n, dtype=torch.int32, device=A.device),
+            I=torch.empty(m, dtype=torch.int32, device=A.device),
+            U=torch.empty(kcap, kcap, dtype=A.dtype, device=A.device),
+            C=torch.empty(m, kcap, dtype=A.dtype, device=A.device),
+            R=torch.empty(kcap, n, dtype=A.dtype, device=A.device),
+            kout=torch.zeros(2, dtype=torch.int32, device=A.device),
+        )
+    J, I, U, C, R, kout = out["J"], out["I"], out["U"], out["C"], out["R"], out["kout"]
+    _check(h, _lib.idcur_cur(h, _dtype_code(A), m, n, A.data_ptr(), A.stride(0), ctypes.byref(o), ws.data_ptr(),
+                             ws.numel(), kout.data_ptr(), J.data_ptr(), I.data_ptr(), U.data_ptr(), kcap,
+                             C.data_ptr(), kcap, R.data_ptr(), n))
+    if not sync:
+        return CUR(J, I, C, U, R, -1, -1)
+    sync_status(A.device)
+    k1, k2 = (int(v) for v in kout.tolist())
+    return CUR(J, I, C[:, :k1], U[:k1, :k2], R[:k2], k1, k2)
+
+
+def gaussian(rows: int, cols: int, seed: int, *, stream_id: int = 0, dtype=torch.float32,
+             device="cuda") -> torch.Tensor:
+    """Omega (rows x cols) from the Philox4x32-10 / Box-Muller definition."""
+    out = torch.empty(rows, cols, dtype=dtype, device=device)
+    h = _context(out.device)
+    _check(h, _lib.idcur_gaussian(h, _dtype_code(out), rows, cols, seed, stream_id, out.data_ptr(), cols))
+    return out

@@ -1,0 +1,556 @@
+// Host side of libidcur: the C ABI declared in include/idcur.h.
+//
+// Every entry point runs the same planner twice: once without a workspace to
+// size it (idcur_workspace_bytes), once to carve the caller's workspace and
+// enqueue the kernels on the context's stream. Argument checks happen before
+// anything is enqueued.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/idcur.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+struct idcur_ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int num_cus = 256;
+  int* dstatus = nullptr;
+  std::string err;
+};
+
+namespace idcur {
+namespace {
+
+constexpr double kU32 = 5.9604644775390625e-08;   // 2^-24
+constexpr double kU64 = 1.1102230246251565e-16;   // 2^-53
+
+struct Fail {
+  idcur_status code;
+};
+
+[[noreturn]] void fail(idcur_ctx* ctx, idcur_status code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  throw Fail{code};
+}
+
+void hipcheck(idcur_ctx* ctx, hipError_t e, const char* what) {
+  if (e != hipSuccess) fail(ctx, IDCUR_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Workspace carving: dry runs only count bytes.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t off = 0;
+  bool dry = true;
+  void* take(size_t bytes) {
+    off = (off + 255) & ~(size_t)255;
+    void* p = dry ? nullptr : base + off;
+    off += (bytes + 255) & ~(size_t)255;
+    return p;
+  }
+};
+
+size_t esz(int dtype) { return dtype == IDCUR_F32 ? 4 : 8; }
+
+// A logical matrix X (rows x cols) viewed inside A: X(i, c) = A[i*xr + c*xc].
+struct View {
+  const void* A;
+  int64_t rows, cols, xr, xc;
+};
+
+struct Ctx {
+  idcur_ctx* c;
+  hipStream_t s;
+  bool dry;
+  Arena* ar;
+  void check(hipError_t e, const char* what) const {
+    if (!dry) hipcheck(c, e, what);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// GEMM helper: C = A * B in the descriptor's layout, with split-K scratch.
+// ---------------------------------------------------------------------------
+void gemm(const Ctx& x, GemmDesc d) {
+  d.splitk = gemm_pick_splitk(d.M, d.N, d.K, x.c->num_cus);
+  void* part = x.ar->take(gemm_part_bytes(d));
+  if (!x.dry) x.check(gemm_launch(d, part, x.s), "gemm");
+}
+
+// Row-orthonormalise V (l x N), stored transposed as Vt (N x l, row-major):
+// Cholesky QR twice (G = V V^T, G = L L^T, V <- L^{-1} V), FP64 Gram and factors.
+void orth_rows(const Ctx& x, int dtype, void* Vt, int64_t N, int l) {
+  double* G = static_cast<double*>(x.ar->take((size_t)l * l * 8));
+  double* L = static_cast<double*>(x.ar->take((size_t)l * l * 8));
+  for (int pass = 0; pass < 2; ++pass) {
+    GemmDesc g{};
+    g.M = l; g.N = l; g.K = N;
+    g.A = Vt; g.sam = 1; g.sak = l;
+    g.B = Vt; g.sbk = l; g.sbn = 1;
+    g.C = G; g.ldc = l;
+    g.in_type = dtype; g.acc_type = 0; g.out_type = 0;
+    g.alpha = 1.0; g.beta = 0.0;
+    gemm(x, g);
+    if (!x.dry) x.check(chol_launch(G, l, l, nullptr, L, l, pass == 0 ? 1e-14 : 1e-16, x.c->dstatus, x.s), "chol");
+    TrsmDesc t{};
+    t.tri = L; t.ldt = l; t.upper = 0; t.trans = 0;
+    t.c_host = l; t.c_dev = nullptr;
+    t.ncol_host = N; t.ncol_sub_c = 0; t.ncol_dev = nullptr;
+    t.B = Vt; t.b_type = dtype; t.sbr = 1; t.sbc = l; t.col_idx = nullptr; t.col_idx_off_c = 0;
+    t.X = Vt; t.x_type = dtype; t.sxr = 1; t.sxc = l;
+    if (!x.dry) x.check(trsm_launch(t, x.s), "trsm(orth)");
+  }
+}
+
+double default_rank_tol(int dtype, int64_t l) {
+  return 10.0 * std::sqrt((double)std::max<int64_t>(l, 1)) * (dtype == IDCUR_F32 ? kU32 : kU64);
+}
+
+// Column ID of the view X: J (cols), T (kcap x (cols-k), ldt), k_out (device).
+// Returns the S buffer (kcap x cols, by original column) for later use.
+struct ColId {
+  void* S = nullptr;
+  int kcap = 0;
+};
+
+ColId column_id(const Ctx& x, int dtype, const View& X, const idcur_opts& o, int* k_out, int* J, void* T,
+                int64_t ldt, bool allow_sketch) {
+  ColId r;
+  const int64_t mr = X.rows, nc = X.cols;
+  const int kcap = o.k > 0 ? o.k : o.kmax;
+  r.kcap = kcap;
+  const bool sketch = allow_sketch && o.p >= 0 && (int64_t)kcap + o.p < mr;
+  const int l = sketch ? kcap + o.p : (int)mr;
+
+  const void* Ymat = X.A;
+  int64_t yrs = X.xr, ycs = X.xc;
+  if (sketch) {
+    void* Omt = x.ar->take((size_t)mr * l * esz(dtype));   // Omega^T, mr x l
+    void* Yt = x.ar->take((size_t)nc * l * esz(dtype));    // Y^T,     nc x l
+    void* Zt = o.q > 0 ? x.ar->take((size_t)mr * l * esz(dtype)) : nullptr;
+    if (!x.dry) {
+      if (o.omega)
+        x.check(copy2d_launch(dtype, l, mr, o.omega, mr, 1, Omt, 1, l, x.s), "omega copy");
+      else
+        x.check(gaussian_launch(dtype, l, mr, o.seed, 0, Omt, 1, l, x.s), "omega");
+    }
+    auto mul_t = [&](const void* Bm) {   // Y^T = X^T * Bm   (Bm: mr x l)
+      GemmDesc g{};
+      g.M = nc; g.N = l; g.K = mr;
+      g.A = X.A; g.sam = X.xc; g.sak = X.xr;
+      g.B = Bm; g.sbk = l; g.sbn = 1;
+      g.C = Yt; g.ldc = l;
+      g.in_type = dtype; g.acc_type = dtype == IDCUR_F32 ? 1 : 0; g.out_type = dtype;
+      g.alpha = 1.0; g.beta = 0.0;
+      gemm(x, g);
+    };
+    mul_t(Omt);
+    for (int it = 0; it < o.q; ++it) {
+      orth_rows(x, dtype, Yt, nc, l);
+      GemmDesc g{};   // Z^T = X * Y^T
+      g.M = mr; g.N = l; g.K = nc;
+      g.A = X.A; g.sam = X.xr; g.sak = X.xc;
+      g.B = Yt; g.sbk = l; g.sbn = 1;
+      g.C = Zt; g.ldc = l;
+      g.in_type = dtype; g.acc_type = dtype == IDCUR_F32 ? 1 : 0; g.out_type = dtype;
+      g.alpha = 1.0; g.beta = 0.0;
+      gemm(x, g);
+      orth_rows(x, dtype, Zt, mr, l);
+      mul_t(Zt);
+    }
+    Ymat = Yt; yrs = 1; ycs = l;
+  }
+
+  // CPQR on Y (l x nc)
+  const CpqrPlan pl = cpqr_plan((int)esz(dtype), l, (int)nc, kcap, x.c->num_cus);
+  void* rec = x.ar->take(pl.rec_bytes + pl.fin_bytes);
+  void* cvals = x.ar->take(pl.cvals_bytes);
+  void* gslab = pl.gslab_bytes ? x.ar->take(pl.gslab_bytes) : nullptr;
+  void* S = x.ar->take((size_t)std::max(kcap, 1) * nc * esz(dtype));
+  double* S11 = static_cast<double*>(x.ar->take((size_t)std::max(kcap, 1) * std::max(kcap, 1) * 8));
+  r.S = S;
+  if (!x.dry) {
+    x.check(zero_launch(rec, pl.rec_bytes + pl.fin_bytes, x.s), "zero");
+    CpqrArgs a{};
+    a.Y = Ymat; a.rs = yrs; a.cs = ycs;
+    a.l_host = l; a.l_dev = nullptr; a.n = (int)nc;
+    a.kmax_host = kcap; a.kmax_dev = nullptr;
+    a.tol = o.k > 0 ? 0.0 : o.tol;
+    a.rank_tol = o.rank_tol > 0 ? o.rank_tol : default_rank_tol(dtype, l);
+    a.norms_exact = o.norms == IDCUR_NORMS_EXACT;
+    a.S = S; a.ldS = nc; a.J = J; a.k_out = k_out; a.status = x.c->dstatus;
+    a.gslab = gslab; a.rec = rec; a.cvals = cvals;
+    a.fin = reinterpret_cast<int*>(static_cast<char*>(rec) + pl.rec_bytes);
+    x.check(cpqr_launch(dtype, pl, a, x.s), "cpqr");
+    // T = S11^{-1} S12
+    x.check(gather_s11_launch(dtype, S, nc, J, kcap, k_out, S11, x.s), "gather S11");
+    TrsmDesc t{};
+    t.tri = S11; t.ldt = kcap; t.upper = 1; t.trans = 0;
+    t.c_host = kcap; t.c_dev = k_out;
+    t.ncol_host = nc; t.ncol_sub_c = 1; t.ncol_dev = nullptr;
+    t.B = S; t.b_type = dtype; t.sbr = nc; t.sbc = 1; t.col_idx = J; t.col_idx_off_c = 1;
+    t.X = T; t.x_type = dtype; t.sxr = ldt; t.sxc = 1; t.xcol_lim = ldt;
+    x.check(trsm_launch(t, x.s), "trsm(T)");
+  }
+  return r;
+}
+
+// Row ID of C (m x kcap, row-major ld kcap) with rank k_dev: the full-rank ID of
+// C^T, giving I (m) and Tr (k x (m-k), ldtr); k_out_r receives its rank.
+void row_id_of_c(const Ctx& x, int dtype, const void* C, int64_t m, int kcap, const int* k_dev, int* k_out_r, int* I,
+                 void* Tr, int64_t ldtr) {
+  const CpqrPlan pl = cpqr_plan((int)esz(dtype), kcap, (int)m, kcap, x.c->num_cus);
+  void* rec = x.ar->take(pl.rec_bytes + pl.fin_bytes);
+  void* cvals = x.ar->take(pl.cvals_bytes);
+  void* gslab = pl.gslab_bytes ? x.ar->take(pl.gslab_bytes) : nullptr;
+  void* S = x.ar->take((size_t)std::max(kcap, 1) * m * esz(dtype));
+  double* S11 = static_cast<double*>(x.ar->take((size_t)std::max(kcap, 1) * std::max(kcap, 1) * 8));
+  if (x.dry) return;
+  x.check(zero_launch(rec, pl.rec_bytes + pl.fin_bytes, x.s), "zero");
+  CpqrArgs a{};
+  a.Y = C; a.rs = 1; a.cs = kcap;
+  a.l_host = kcap; a.l_dev = k_dev; a.n = (int)m;
+  a.kmax_host = kcap; a.kmax_dev = k_dev;
+  a.tol = 0.0;
+  a.rank_tol = 0.0;   // a full-rank ID: stop only on an exactly zero pivot
+  a.norms_exact = 0;
+  a.S = S; a.ldS = m; a.J = I; a.k_out = k_out_r; a.status = x.c->dstatus;
+  a.gslab = gslab; a.rec = rec; a.cvals = cvals;
+  a.fin = reinterpret_cast<int*>(static_cast<char*>(rec) + pl.rec_bytes);
+  x.check(cpqr_launch(dtype, pl, a, x.s), "cpqr(row)");
+  x.check(gather_s11_launch(dtype, S, m, I, kcap, k_out_r, S11, x.s), "gather S11(row)");
+  TrsmDesc t{};
+  t.tri = S11; t.ldt = kcap; t.upper = 1; t.trans = 0;
+  t.c_host = kcap; t.c_dev = k_out_r;
+  t.ncol_host = m; t.ncol_sub_c = 1; t.ncol_dev = nullptr;
+  t.B = S; t.b_type = dtype; t.sbr = m; t.sbc = 1; t.col_idx = I; t.col_idx_off_c = 1;
+  t.X = Tr; t.x_type = dtype; t.sxr = ldtr; t.sxc = 1; t.xcol_lim = ldtr;
+  x.check(trsm_launch(t, x.s), "trsm(Tr)");
+}
+
+// U = argmin |U R - V*|_F through the QR of R^T (Cholesky QR twice, FP64).
+// R: kr x n (row-major ldr), V* from (J, T); k = kout[0] columns, kr = kout[1].
+void solve_u(const Ctx& x, int dtype, const void* R, int64_t ldr, int64_t n, int kcap, const int* kout, const int* J,
+             const void* T, int64_t ldt, void* U, int64_t ldu) {
+  const int* k_dev = kout;
+  const int* kr_dev = kout + 1;
+  double* G = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
+  double* L1 = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
+  double* L2 = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
+  double* Qt = static_cast<double*>(x.ar->take((size_t)kcap * n * 8));
+  double* V = static_cast<double*>(x.ar->take((size_t)n * kcap * 8));
+  double* Bls = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
+  double* Y1 = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
+  // G1 = R R^T
+  {
+    GemmDesc g{};
+    g.M = kcap; g.N = kcap; g.K = n;
+    g.A = R; g.sam = ldr; g.sak = 1;
+    g.B = R; g.sbk = 1; g.sbn = ldr;
+    g.C = G; g.ldc = kcap;
+    g.in_type = dtype; g.acc_type = 0; g.out_type = 0;
+    g.alpha = 1.0; g.beta = 0.0; g.m_dev = kr_dev; g.n_dev = kr_dev;
+    gemm(x, g);
+  }
+  if (!x.dry) {
+    x.check(chol_launch(G, kcap, kcap, kr_dev, L1, kcap, 1e-15, x.c->dstatus, x.s), "chol(R)");
+    TrsmDesc t{};   // Q1^T = L1^{-1} R
+    t.tri = L1; t.ldt = kcap; t.upper = 0; t.trans = 0; t.c_host = kcap; t.c_dev = kr_dev;
+    t.ncol_host = n; t.B = R; t.b_type = dtype; t.sbr = ldr; t.sbc = 1;
+    t.X = Qt; t.x_type = 0; t.sxr = n; t.sxc = 1;
+    x.check(trsm_launch(t, x.s), "trsm(Q1)");
+  }
+  {
+    GemmDesc g{};   // G2 = Q1^T Q1
+    g.M = kcap; g.N = kcap; g.K = n;
+    g.A = Qt; g.sam = n; g.sak = 1;
+    g.B = Qt; g.sbk = 1; g.sbn = n;
+    g.C = G; g.ldc = kcap;
+    g.in_type = 0; g.acc_type = 0; g.out_type = 0;
+    g.alpha = 1.0; g.beta = 0.0; g.m_dev = kr_dev; g.n_dev = kr_dev;
+    gemm(x, g);
+  }
+  if (!x.dry) {
+    x.check(chol_launch(G, kcap, kcap, kr_dev, L2, kcap, 0.0, x.c->dstatus, x.s), "chol(Q1)");
+    TrsmDesc t{};   // Q^T = L2^{-1} Q1^T (in place)
+    t.tri = L2; t.ldt = kcap; t.upper = 0; t.trans = 0; t.c_host = kcap; t.c_dev = kr_dev;
+    t.ncol_host = n; t.B = Qt; t.b_type = 0; t.sbr = n; t.sbc = 1;
+    t.X = Qt; t.x_type = 0; t.sxr = n; t.sxc = 1;
+    x.check(trsm_launch(t, x.s), "trsm(Q)");
+    x.check(build_v_launch(dtype, T, ldt, J, n, kcap, k_dev, V, kcap, x.s), "build V");
+  }
+  {
+    GemmDesc g{};   // Bls = Q^T V  (kr x k)
+    g.M = kcap; g.N = kcap; g.K = n;
+    g.A = Qt; g.sam = n; g.sak = 1;
+    g.B = V; g.sbk = kcap; g.sbn = 1;
+    g.C = Bls; g.ldc = kcap;
+    g.in_type = 0; g.acc_type = 0; g.out_type = 0;
+    g.alpha = 1.0; g.beta = 0.0; g.m_dev = kr_dev; g.n_dev = k_dev;
+    gemm(x, g);
+  }
+  if (!x.dry) {
+    TrsmDesc t{};   // L2^T Y1 = Bls
+    t.tri = L2; t.ldt = kcap; t.upper = 0; t.trans = 1; t.c_host = kcap; t.c_dev = kr_dev;
+    t.ncol_host = kcap; t.ncol_dev = k_dev; t.B = Bls; t.b_type = 0; t.sbr = kcap; t.sbc = 1;
+    t.X = Y1; t.x_type = 0; t.sxr = kcap; t.sxc = 1;
+    x.check(trsm_launch(t, x.s), "trsm(L2^T)");
+    TrsmDesc u{};   // L1^T U^T = Y1, written transposed into U (k x kr)
+    u.tri = L1; u.ldt = kcap; u.upper = 0; u.trans = 1; u.c_host = kcap; u.c_dev = kr_dev;
+    u.ncol_host = kcap; u.ncol_dev = k_dev; u.B = Y1; u.b_type = 0; u.sbr = kcap; u.sbc = 1;
+    u.X = U; u.x_type = dtype; u.sxr = 1; u.sxc = ldu;
+    x.check(trsm_launch(u, x.s), "trsm(L1^T)");
+  }
+}
+
+enum Op { OP_COL = 0, OP_ROW = 1, OP_TWO = 2, OP_CUR = 3 };
+
+struct Outs {
+  int* k_out = nullptr;
+  int* J = nullptr; void* T = nullptr; int64_t ldt = 0;
+  int* I = nullptr; void* Tr = nullptr; int64_t ldtr = 0;
+  void* U = nullptr; int64_t ldu = 0;
+  void* C = nullptr; int64_t ldc = 0;
+  void* R = nullptr; int64_t ldr = 0;
+};
+
+void validate(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+              const idcur_opts* opts) {
+  if (!ctx) throw Fail{IDCUR_EINVAL};
+  if (!opts) fail(ctx, IDCUR_EINVAL, "opts is NULL");
+  if (dtype != IDCUR_F32 && dtype != IDCUR_F64) fail(ctx, IDCUR_EDTYPE, "dtype must be IDCUR_F32 or IDCUR_F64");
+  if (opts->prec != IDCUR_PREC_NATIVE) fail(ctx, IDCUR_EDTYPE, "only native-precision sketches are available");
+  if (op < 0 || op > 3) fail(ctx, IDCUR_EINVAL, "unknown op");
+  if (m <= 0 || n <= 0) fail(ctx, IDCUR_EINVAL, "m and n must be positive");
+  if (m > (1LL << 30) || n > (1LL << 30)) fail(ctx, IDCUR_EINVAL, "m and n must be below 2^30");
+  if (lda < n) fail(ctx, IDCUR_EINVAL, "lda must be >= n");
+  (void)A;
+  const int64_t mr = op == OP_ROW ? n : m, nc = op == OP_ROW ? m : n;
+  const int64_t mn = std::min(m, n);
+  if (opts->k < 0) fail(ctx, IDCUR_EINVAL, "k must be >= 0");
+  if (opts->k > 0) {
+    if (opts->k >= mn) fail(ctx, IDCUR_EINVAL, "k must be < min(m, n)");
+  } else {
+    if (!(opts->tol > 0.0) || !std::isfinite(opts->tol)) fail(ctx, IDCUR_EINVAL, "tolerance mode needs tol > 0");
+    if (opts->kmax <= 0 || opts->kmax >= mn) fail(ctx, IDCUR_EINVAL, "tolerance mode needs 0 < kmax < min(m, n)");
+  }
+  const int kcap = opts->k > 0 ? opts->k : opts->kmax;
+  if (kcap > 256 && (op == OP_CUR)) fail(ctx, IDCUR_EINVAL, "cur supports k <= 256");
+  if (opts->q < 0) fail(ctx, IDCUR_EINVAL, "q must be >= 0");
+  if (opts->p >= 0 && (int64_t)kcap + opts->p < mr && kcap + opts->p > 256)
+    fail(ctx, IDCUR_EINVAL, "sketch width k + p must be <= 256");
+  if (opts->rank_tol < 0 || !std::isfinite(opts->rank_tol)) fail(ctx, IDCUR_EINVAL, "rank_tol must be >= 0");
+  if (opts->norms != IDCUR_NORMS_DOWNDATE && opts->norms != IDCUR_NORMS_EXACT) fail(ctx, IDCUR_EINVAL, "bad norms");
+  (void)nc;
+}
+
+void execute(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+             const idcur_opts& o, Arena& ar, const Outs& out) {
+  Ctx x{ctx, ctx->stream, ar.dry, &ar};
+  const int kcap = o.k > 0 ? o.k : o.kmax;
+  View X{A, m, n, lda, 1};
+  if (op == OP_ROW) {
+    View Xt{A, n, m, 1, lda};
+    column_id(x, dtype, Xt, o, out.k_out, out.I, out.Tr, out.ldtr, true);
+    return;
+  }
+  // column ID (internal J/T buffers when the caller does not receive them)
+  int* J = out.J;
+  void* T = out.T;
+  int64_t ldt = out.ldt;
+  if (!T) {
+    T = ar.take((size_t)kcap * n * esz(dtype));
+    ldt = n;
+  }
+  column_id(x, dtype, X, o, out.k_out, J, T, ldt, true);
+  if (op == OP_COL) return;
+  // C = A(:, J(1:k))
+  void* C = ar.take((size_t)m * kcap * esz(dtype));
+  if (!ar.dry) x.check(gather_cols_launch(dtype, m, A, lda, J, kcap, out.k_out, C, kcap, dtype, x.s), "gather C");
+  void* Tr = out.Tr;
+  int64_t ldtr = out.ldtr;
+  if (!Tr) {
+    Tr = ar.take((size_t)kcap * m * esz(dtype));
+    ldtr = m;
+  }
+  row_id_of_c(x, dtype, C, m, kcap, out.k_out, out.k_out + 1, out.I, Tr, ldtr);
+  if (op == OP_TWO) return;
+  // CUR: R = A(I(1:k), :), optional C output, then U
+  void* R = out.R;
+  int64_t ldr = out.ldr;
+  if (!R) {
+    R = ar.take((size_t)kcap * n * esz(dtype));
+    ldr = n;
+  }
+  if (!ar.dry) {
+    x.check(gather_rows_launch(dtype, n, A, lda, out.I, kcap, out.k_out + 1, R, ldr, dtype, x.s), "gather R");
+    if (out.C) x.check(gather_cols_launch(dtype, m, A, lda, J, kcap, out.k_out, out.C, out.ldc, dtype, x.s), "C out");
+  }
+  solve_u(x, dtype, R, ldr, n, kcap, out.k_out, J, T, ldt, out.U, out.ldu);
+}
+
+idcur_status run(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+                 const idcur_opts* opts, void* ws, size_t ws_bytes, const Outs& out) {
+  try {
+    validate(ctx, op, dtype, m, n, A, lda, opts);
+    if (!A) fail(ctx, IDCUR_EINVAL, "A is NULL");
+    if (!out.k_out) fail(ctx, IDCUR_EINVAL, "k_out is NULL");
+    const int kcap = opts->k > 0 ? opts->k : opts->kmax;
+    const int64_t nc = op == OP_ROW ? m : n;
+    if (op == OP_ROW) {
+      if (!out.I || !out.Tr) fail(ctx, IDCUR_EINVAL, "I and Tr are required");
+      if (out.ldtr < (opts->k > 0 ? m - kcap : m)) fail(ctx, IDCUR_EINVAL, "ldtr too small");
+    } else {
+      if (!out.J) fail(ctx, IDCUR_EINVAL, "J is required");
+      if (op != OP_CUR) {
+        if (!out.T) fail(ctx, IDCUR_EINVAL, "T is required");
+        if (out.ldt < (opts->k > 0 ? nc - kcap : nc)) fail(ctx, IDCUR_EINVAL, "ldt too small");
+      }
+      if (op == OP_TWO) {
+        if (!out.I || !out.Tr) fail(ctx, IDCUR_EINVAL, "I and Tr are required");
+        if (out.ldtr < (opts->k > 0 ? m - kcap : m)) fail(ctx, IDCUR_EINVAL, "ldtr too small");
+      }
+      if (op == OP_CUR) {
+        if (!out.I || !out.U) fail(ctx, IDCUR_EINVAL, "I and U are required");
+        if (out.ldu < kcap) fail(ctx, IDCUR_EINVAL, "ldu too small");
+        if (out.C && out.ldc < kcap) fail(ctx, IDCUR_EINVAL, "ldc too small");
+        if (out.R && out.ldr < n) fail(ctx, IDCUR_EINVAL, "ldr too small");
+      }
+    }
+    Arena dry;
+    execute(ctx, op, dtype, m, n, A, lda, *opts, dry, out);
+    if (!ws || ws_bytes < dry.off) fail(ctx, IDCUR_EWORKSPACE, "workspace missing or too small");
+    Arena ar;
+    ar.dry = false;
+    ar.base = static_cast<char*>(ws);
+    ar.cap = ws_bytes;
+    hipcheck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    execute(ctx, op, dtype, m, n, A, lda, *opts, ar, out);
+    return IDCUR_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  }
+}
+
+}  // namespace
+}  // namespace idcur
+
+using namespace idcur;
+
+extern "C" {
+
+void idcur_opts_default(idcur_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->p = -1;
+  o->prec = IDCUR_PREC_NATIVE;
+  o->norms = IDCUR_NORMS_DOWNDATE;
+}
+
+idcur_status idcur_create(idcur_ctx** out, void* stream) {
+  if (!out) return IDCUR_EINVAL;
+  *out = nullptr;
+  idcur_ctx* c = new idcur_ctx();
+  c->stream = static_cast<hipStream_t>(stream);
+  if (hipGetDevice(&c->device) != hipSuccess) { delete c; return IDCUR_EHIP; }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) { delete c; return IDCUR_EHIP; }
+  c->num_cus = prop.multiProcessorCount;
+  if (hipMalloc(&c->dstatus, 64) != hipSuccess) { delete c; return IDCUR_EHIP; }
+  if (hipMemset(c->dstatus, 0, 64) != hipSuccess) { (void)hipFree(c->dstatus); delete c; return IDCUR_EHIP; }
+  *out = c;
+  return IDCUR_OK;
+}
+
+idcur_status idcur_set_stream(idcur_ctx* ctx, void* stream) {
+  if (!ctx) return IDCUR_EINVAL;
+  ctx->stream = static_cast<hipStream_t>(stream);
+  return IDCUR_OK;
+}
+
+idcur_status idcur_destroy(idcur_ctx* ctx) {
+  if (!ctx) return IDCUR_EINVAL;
+  if (ctx->dstatus) (void)hipFree(ctx->dstatus);
+  delete ctx;
+  return IDCUR_OK;
+}
+
+const char* idcur_last_error(const idcur_ctx* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+idcur_status idcur_sync_status(idcur_ctx* ctx) {
+  if (!ctx) return IDCUR_EINVAL;
+  int st = 0;
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) { ctx->err = "stream synchronisation failed"; return IDCUR_EHIP; }
+  if (hipMemcpy(&st, ctx->dstatus, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return IDCUR_EHIP;
+  if (hipMemset(ctx->dstatus, 0, sizeof(int)) != hipSuccess) return IDCUR_EHIP;
+  if (st & ST_TIMEOUT) { ctx->err = "a grid-wide wait exceeded its spin limit"; return IDCUR_ETIMEOUT; }
+  if (st & ST_NONFINITE) { ctx->err = "non-finite value or breakdown in a factorisation"; return IDCUR_ENONFINITE; }
+  if (st & ST_RANKCAP) { ctx->err = "tolerance not reached within the rank cap"; return IDCUR_ERANKCAP; }
+  return IDCUR_OK;
+}
+
+idcur_status idcur_workspace_bytes(idcur_ctx* ctx, int32_t op, int32_t dtype, int64_t m, int64_t n,
+                                   const idcur_opts* opts, size_t* bytes) {
+  try {
+    if (!bytes) fail(ctx, IDCUR_EINVAL, "bytes is NULL");
+    validate(ctx, op, dtype, m, n, nullptr, std::max<int64_t>(n, 1), opts);
+    Arena dry;
+    Outs out;
+    out.ldt = out.ldtr = std::max(m, n);
+    execute(ctx, op, dtype, m, n, nullptr, n, *opts, dry, out);
+    *bytes = dry.off + 256;
+    return IDCUR_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  }
+}
+
+idcur_status idcur_id_col(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+                          const idcur_opts* opts, void* ws, size_t ws_bytes, int32_t* k_out, int32_t* J, void* T,
+                          int64_t ldt) {
+  Outs o;
+  o.k_out = k_out; o.J = J; o.T = T; o.ldt = ldt;
+  return run(ctx, OP_COL, dtype, m, n, A, lda, opts, ws, ws_bytes, o);
+}
+
+idcur_status idcur_id_row(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+                          const idcur_opts* opts, void* ws, size_t ws_bytes, int32_t* k_out, int32_t* I, void* Tr,
+                          int64_t ldtr) {
+  Outs o;
+  o.k_out = k_out; o.I = I; o.Tr = Tr; o.ldtr = ldtr;
+  return run(ctx, OP_ROW, dtype, m, n, A, lda, opts, ws, ws_bytes, o);
+}
+
+idcur_status idcur_id_two_sided(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+                                const idcur_opts* opts, void* ws, size_t ws_bytes, int32_t* k_out, int32_t* J, void* T,
+                                int64_t ldt, int32_t* I, void* Tr, int64_t ldtr) {
+  Outs o;
+  o.k_out = k_out; o.J = J; o.T = T; o.ldt = ldt; o.I = I; o.Tr = Tr; o.ldtr = ldtr;
+  return run(ctx, OP_TWO, dtype, m, n, A, lda, opts, ws, ws_bytes, o);
+}
+
+idcur_status idcur_cur(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+                       const idcur_opts* opts, void* ws, size_t ws_bytes, int32_t* k_out, int32_t* J, int32_t* I,
+                       void* U, int64_t ldu, void* C, int64_t ldc, void* R, int64_t ldr) {
+  Outs o;
+  o.k_out = k_out; o.J = J; o.I = I; o.U = U; o.ldu = ldu; o.C = C; o.ldc = ldc; o.R = R; o.ldr = ldr;
+  return run(ctx, OP_CUR, dtype, m, n, A, lda, opts, ws, ws_bytes, o);
+}
+
+idcur_status idcur_gaussian(idcur_ctx* ctx, int32_t dtype, int64_t rows, int64_t cols, uint64_t seed, uint64_t stream,
+                            void* out, int64_t ldo) {
+  if (!ctx) return IDCUR_EINVAL;
+  if (dtype != IDCUR_F32 && dtype != IDCUR_F64) { ctx->err = "bad dtype"; return IDCUR_EDTYPE; }
+  if (rows < 0 || cols < 0 || ldo < cols || (!out && rows * cols > 0)) { ctx->err = "bad arguments"; return IDCUR_EINVAL; }
+  hipError_t e = gaussian_launch(dtype, rows, cols, seed, stream, out, ldo, 1, ctx->stream);
+  if (e != hipSuccess) { ctx->err = hipGetErrorString(e); return IDCUR_EHIP; }
+  return IDCUR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,139 @@
+// Launch interfaces of the HIP kernels behind libidcur (host-callable).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+namespace idcur {
+
+// dtype codes match idcur_dtype: 0 = double, 1 = float.
+
+// ---------------------------------------------------------------------------
+// Column-pivoted QR (cpqr.hip)
+// ---------------------------------------------------------------------------
+struct CpqrArgs {
+  const void* Y;          // element (i, c) at Y[i*rs + c*cs]
+  int64_t rs, cs;
+  int l_host;             // rows (upper bound when l_dev is set)
+  const int* l_dev;       // optional device row count
+  int n;                  // columns
+  int kmax_host;          // step cap (upper bound when kmax_dev is set)
+  const int* kmax_dev;    // optional device step cap
+  double tol;             // > 0: tolerance mode (relative Frobenius)
+  double rank_tol;        // relative pivot-norm threshold for exact rank deficiency
+  int norms_exact;        // 1: exact norms every step; 0: downdate + recompute
+  void* S;                // kmax_host x n (dtype), row r at S + r*ldS, by original column
+  int64_t ldS;
+  int* J;                 // n
+  int* k_out;             // device scalar
+  int* status;            // device status word
+  void* gslab;            // global slab (n * lpad) when the slab does not fit LDS
+  void* rec;              // exchange records
+  void* cvals;            // exchanged candidate columns
+  int* fin;               // final-exchange flags (G * 16 ints, zeroed)
+  int lpad;               // set by cpqr_launch
+  int cols_per_wg;        // set by cpqr_launch
+  int lanes_per_col;      // set by cpqr_launch
+};
+
+struct CpqrPlan {
+  int G;
+  int cols_per_wg;
+  int lpad;
+  int lanes_per_col;
+  bool in_lds;
+  size_t lds_bytes;
+  size_t rec_bytes, cvals_bytes, fin_bytes, gslab_bytes;
+};
+
+CpqrPlan cpqr_plan(int dtype_size, int l, int n, int kmax, int num_cus);
+hipError_t cpqr_launch(int dtype, const CpqrPlan& p, CpqrArgs a, hipStream_t stream);
+
+// ---------------------------------------------------------------------------
+// MFMA GEMM (gemm.hip): C (M x N) = A (M x K) * B (K x N)
+//   A(i, k) = A[i*sam + k*sak]   with either sak == 1 (K contiguous) or sam == 1
+//   B(k, j) = B[k*sbk + j*sbn]   with either sbn == 1 (N contiguous) or sbk == 1
+//   C(i, j) = C[i*ldc + j]
+// in: 0 double, 1 float.  acc: 0 double (f64 MFMA), 1 float (f32 MFMA).
+// Split-K partial sums go to `part` (splitk * M * N of acc type) and are
+// reduced in a fixed order by a second kernel.
+// ---------------------------------------------------------------------------
+struct GemmDesc {
+  int64_t M, N, K;
+  const void* A; int64_t sam, sak;
+  const void* B; int64_t sbk, sbn;
+  void* C; int64_t ldc;
+  int in_type;      // of A and B
+  int acc_type;
+  int out_type;     // of C
+  int splitk;       // >= 1
+  double alpha;     // C = alpha * A B (+ beta C when beta != 0)
+  double beta;
+  const int* m_dev; // optional device bound on M (rows >= *m_dev are skipped)
+  const int* n_dev; // optional device bound on N
+};
+size_t gemm_part_bytes(const GemmDesc& d);
+int gemm_pick_splitk(int64_t M, int64_t N, int64_t K, int num_cus);
+hipError_t gemm_launch(const GemmDesc& d, void* part, hipStream_t stream);
+
+// ---------------------------------------------------------------------------
+// Triangular solve (trsm.hip): op(Tri) X = B, Tri c x c double, row-major ld.
+//   B(r, col) = B[r*sbr + bcol(col)*sbc] with bcol(col) = col_idx ? col_idx[col] : col
+//   X(r, col) = X[r*sxr + col*sxc]
+// c and ncol may be bounded by device values (c_dev: c = *c_dev; ncol becomes
+// ncol_base - *c_dev when ncol_sub_c is set). Tri is upper (upper = 1) or
+// lower; trans = 1 uses Tri^T.
+// ---------------------------------------------------------------------------
+struct TrsmDesc {
+  const double* tri; int64_t ldt;
+  int upper, trans;
+  int c_host; const int* c_dev;
+  int64_t ncol_host; int ncol_sub_c; const int* ncol_dev;   // ncol_dev: ncol = min(*ncol_dev, ncol_host)
+  const void* B; int b_type; int64_t sbr, sbc; const int* col_idx; int col_idx_off_c;
+  void* X; int x_type; int64_t sxr, sxc;
+  int64_t xcol_lim;   // > 0: columns >= xcol_lim of X are not written
+};
+hipError_t trsm_launch(const TrsmDesc& d, hipStream_t stream);
+
+// Gather S11 = S(0:c, J(0:c)) into a dense c x c double matrix (row-major).
+hipError_t gather_s11_launch(int dtype, const void* S, int64_t ldS, const int* J, int c_host,
+                             const int* c_dev, double* out, hipStream_t stream);
+
+// ---------------------------------------------------------------------------
+// Cholesky of a small SPD matrix (chol.hip): G = L L^T, c <= 256, double.
+// Writes L (row-major, zeros above the diagonal). A non-positive pivot is
+// clamped to a tiny positive value and reported through `status`.
+// ---------------------------------------------------------------------------
+hipError_t chol_launch(const double* G, int64_t ldg, int c_host, const int* c_dev, double* L,
+                       int64_t ldl, double shift_rel, int* status, hipStream_t stream);
+
+// ---------------------------------------------------------------------------
+// Miscellaneous (misc.hip)
+// ---------------------------------------------------------------------------
+// Gaussian matrix from Philox4x32-10: element (r, i) of a rows x cols matrix
+// written to out[r*sor + i*soc].
+hipError_t gaussian_launch(int dtype, int64_t rows, int64_t cols, uint64_t seed, uint64_t stream_id,
+                           void* out, int64_t sor, int64_t soc, hipStream_t stream);
+// out(r, c) = in(r, c) for an r x c matrix with strides (transpose when swapped).
+hipError_t copy2d_launch(int dtype, int64_t rows, int64_t cols, const void* in, int64_t sir, int64_t sic,
+                         void* out, int64_t sor, int64_t soc, hipStream_t stream);
+// Gather columns: out(i, s) = A(i, idx[s]) for s < k (k = *k_dev if set), row-major out.
+hipError_t gather_cols_launch(int dtype, int64_t m, const void* A, int64_t lda, const int* idx, int k_host,
+                              const int* k_dev, void* out, int64_t ldo, int out_type, hipStream_t stream);
+// Gather rows: out(s, j) = A(idx[s], j) for s < k.
+hipError_t gather_rows_launch(int dtype, int64_t n, const void* A, int64_t lda, const int* idx, int k_host,
+                              const int* k_dev, void* out, int64_t ldo, int out_type, hipStream_t stream);
+// Fill bytes with zero (a kernel, so it can live inside a captured graph).
+hipError_t zero_launch(void* p, size_t bytes, hipStream_t stream);
+// V = V*^T (n x kcap, double, row-major ldv) from (J, T): row J[s] is e_s for
+// s < k, row J[k+t] is T(:, t)^T (Section 2.3, eq. (column_approx_id2)).
+hipError_t build_v_launch(int dtype, const void* T, int64_t ldt, const int* J, int64_t n, int kcap, const int* k_dev,
+                          double* V, int64_t ldv, hipStream_t stream);
+// out(a, b) += Q(a, J[b]) for a < ka, b < kb (double), Q row-major ldq.
+hipError_t add_gathered_launch(const double* Q, int64_t ldq, const int* J, int ka_host, const int* ka_dev,
+                               int kb_host, const int* kb_dev, double* out, int64_t ldo, hipStream_t stream);
+
+}  // namespace idcur

@@ -1,0 +1,209 @@
+// Small bandwidth kernels: the Gaussian sketch matrix (Philox4x32-10 +
+// Box-Muller), strided copies, the gathers C = A(:, J(1:k)) and
+// R = A(I(1:k), :) of the CUR-ID (Section 3, eq. (choice_C_and_R)), and a
+// zero fill.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace idcur {
+namespace {
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of the 4x32 Philox bijection,
+// multipliers 0xD2511F53 / 0xCD9E8D57, key increments 0x9E3779B9 / 0xBB67AE85.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 ctr, uint2 key) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { key.x += 0x9E3779B9u; key.y += 0xBB67AE85u; }
+    const uint32_t lo0 = 0xD2511F53u * ctr.x, hi0 = __umulhi(0xD2511F53u, ctr.x);
+    const uint32_t lo1 = 0xCD9E8D57u * ctr.z, hi1 = __umulhi(0xCD9E8D57u, ctr.z);
+    ctr = make_uint4(hi1 ^ ctr.y ^ key.x, lo1, hi0 ^ ctr.w ^ key.y, lo0);
+  }
+  return ctr;
+}
+
+template <typename T>
+__global__ void gaussian_kernel(int64_t rows, int64_t cols, uint64_t seed, uint64_t sid, T* out, int64_t sor,
+                                int64_t soc) {
+  const int64_t total = rows * cols;
+  const int64_t ngroups = (total + 3) / 4;
+  const uint2 key = make_uint2((uint32_t)seed, (uint32_t)(seed >> 32));
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ngroups; g += (int64_t)gridDim.x * blockDim.x) {
+    const uint4 x = philox4x32_10(make_uint4((uint32_t)g, (uint32_t)(g >> 32), (uint32_t)sid, 0u), key);
+    const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+    double z[4];
+#pragma unroll
+    for (int pr = 0; pr < 2; ++pr) {
+      const double u1 = ((double)w[2 * pr] + 1.0) * 2.3283064365386963e-10;   // 2^-32
+      const double u2 = (double)w[2 * pr + 1] * 2.3283064365386963e-10;
+      const double rho = sqrt(-2.0 * log(u1));
+      const double th = (2.0 * 3.141592653589793) * u2;
+      z[2 * pr] = rho * cos(th);
+      z[2 * pr + 1] = rho * sin(th);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t f = g * 4 + q;
+      if (f < total) {
+        const int64_t r = f / cols, i = f % cols;
+        out[r * sor + i * soc] = (T)z[q];
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ void copy2d_kernel(int64_t rows, int64_t cols, const T* in, int64_t sir, int64_t sic, T* out, int64_t sor,
+                              int64_t soc) {
+  const int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / cols, c = e % cols;
+    out[r * sor + c * soc] = in[r * sir + c * sic];
+  }
+}
+
+template <typename T, typename TO>
+__global__ void gather_cols_kernel(int64_t m, const T* A, int64_t lda, const int* idx, int k_host, const int* k_dev,
+                                   TO* out, int64_t ldo) {
+  const int k = k_dev ? min(*k_dev, k_host) : k_host;
+  const int64_t total = m * k;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / k, s = e % k;
+    out[i * ldo + s] = (TO)A[i * lda + idx[s]];
+  }
+}
+
+template <typename T, typename TO>
+__global__ void gather_rows_kernel(int64_t n, const T* A, int64_t lda, const int* idx, int k_host, const int* k_dev,
+                                   TO* out, int64_t ldo) {
+  const int k = k_dev ? min(*k_dev, k_host) : k_host;
+  const int64_t total = (int64_t)k * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = e / n, j = e % n;
+    out[s * ldo + j] = (TO)A[(int64_t)idx[s] * lda + j];
+  }
+}
+
+__global__ void zero_kernel(uint32_t* p, size_t nwords) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < nwords; e += (size_t)gridDim.x * blockDim.x) p[e] = 0u;
+}
+
+__global__ void add_gathered_kernel(const double* Q, int64_t ldq, const int* J, int ka_host, const int* ka_dev,
+                                    int kb_host, const int* kb_dev, double* out, int64_t ldo) {
+  const int ka = ka_dev ? min(*ka_dev, ka_host) : ka_host;
+  const int kb = kb_dev ? min(*kb_dev, kb_host) : kb_host;
+  const int64_t total = (int64_t)ka * kb;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = e / kb, b = e % kb;
+    out[a * ldo + b] += Q[a * ldq + J[b]];
+  }
+}
+
+template <typename T>
+__global__ void build_v_kernel(const T* Tm, int64_t ldt, const int* J, int64_t n, int kcap, const int* k_dev, double* V,
+                               int64_t ldv) {
+  const int k = k_dev ? min(*k_dev, kcap) : kcap;
+  const int64_t total = (int64_t)kcap * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / n, p = e % n;
+    double v = 0.0;
+    if (p < k) v = (r == p) ? 1.0 : 0.0;
+    else if (r < k) v = (double)Tm[r * ldt + (p - k)];
+    V[(int64_t)J[p] * ldv + r] = v;
+  }
+}
+
+unsigned grid_for(int64_t work) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(work, 256), 8192)); }
+
+}  // namespace
+
+hipError_t gaussian_launch(int dtype, int64_t rows, int64_t cols, uint64_t seed, uint64_t sid, void* out, int64_t sor,
+                           int64_t soc, hipStream_t stream) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  const unsigned g = grid_for(ceil_div(rows * cols, 4));
+  if (dtype == 1)
+    hipLaunchKernelGGL(gaussian_kernel<float>, dim3(g), dim3(256), 0, stream, rows, cols, seed, sid,
+                       static_cast<float*>(out), sor, soc);
+  else
+    hipLaunchKernelGGL(gaussian_kernel<double>, dim3(g), dim3(256), 0, stream, rows, cols, seed, sid,
+                       static_cast<double*>(out), sor, soc);
+  return hipGetLastError();
+}
+
+hipError_t copy2d_launch(int dtype, int64_t rows, int64_t cols, const void* in, int64_t sir, int64_t sic, void* out,
+                         int64_t sor, int64_t soc, hipStream_t stream) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  const unsigned g = grid_for(rows * cols);
+  if (dtype == 1)
+    hipLaunchKernelGGL(copy2d_kernel<float>, dim3(g), dim3(256), 0, stream, rows, cols, static_cast<const float*>(in), sir,
+                       sic, static_cast<float*>(out), sor, soc);
+  else
+    hipLaunchKernelGGL(copy2d_kernel<double>, dim3(g), dim3(256), 0, stream, rows, cols, static_cast<const double*>(in),
+                       sir, sic, static_cast<double*>(out), sor, soc);
+  return hipGetLastError();
+}
+
+hipError_t gather_cols_launch(int dtype, int64_t m, const void* A, int64_t lda, const int* idx, int k_host,
+                              const int* k_dev, void* out, int64_t ldo, int out_type, hipStream_t stream) {
+  if (m <= 0 || k_host <= 0) return hipSuccess;
+  const unsigned g = grid_for(m * k_host);
+  if (dtype == 1 && out_type == 1)
+    hipLaunchKernelGGL((gather_cols_kernel<float, float>), dim3(g), dim3(256), 0, stream, m, static_cast<const float*>(A), lda,
+                       idx, k_host, k_dev, static_cast<float*>(out), ldo);
+  else if (dtype == 1 && out_type == 0)
+    hipLaunchKernelGGL((gather_cols_kernel<float, double>), dim3(g), dim3(256), 0, stream, m, static_cast<const float*>(A),
+                       lda, idx, k_host, k_dev, static_cast<double*>(out), ldo);
+  else if (dtype == 0 && out_type == 0)
+    hipLaunchKernelGGL((gather_cols_kernel<double, double>), dim3(g), dim3(256), 0, stream, m,
+                       static_cast<const double*>(A), lda, idx, k_host, k_dev, static_cast<double*>(out), ldo);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t gather_rows_launch(int dtype, int64_t n, const void* A, int64_t lda, const int* idx, int k_host,
+                              const int* k_dev, void* out, int64_t ldo, int out_type, hipStream_t stream) {
+  if (n <= 0 || k_host <= 0) return hipSuccess;
+  const unsigned g = grid_for(n * k_host);
+  if (dtype == 1 && out_type == 1)
+    hipLaunchKernelGGL((gather_rows_kernel<float, float>), dim3(g), dim3(256), 0, stream, n, static_cast<const float*>(A), lda,
+                       idx, k_host, k_dev, static_cast<float*>(out), ldo);
+  else if (dtype == 1 && out_type == 0)
+    hipLaunchKernelGGL((gather_rows_kernel<float, double>), dim3(g), dim3(256), 0, stream, n, static_cast<const float*>(A),
+                       lda, idx, k_host, k_dev, static_cast<double*>(out), ldo);
+  else if (dtype == 0 && out_type == 0)
+    hipLaunchKernelGGL((gather_rows_kernel<double, double>), dim3(g), dim3(256), 0, stream, n,
+                       static_cast<const double*>(A), lda, idx, k_host, k_dev, static_cast<double*>(out), ldo);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t zero_launch(void* p, size_t bytes, hipStream_t stream) {
+  if (bytes == 0) return hipSuccess;
+  const size_t nw = bytes / 4;
+  hipLaunchKernelGGL(zero_kernel, dim3(grid_for((int64_t)nw)), dim3(256), 0, stream, static_cast<uint32_t*>(p), nw);
+  return hipGetLastError();
+}
+
+hipError_t build_v_launch(int dtype, const void* T, int64_t ldt, const int* J, int64_t n, int kcap, const int* k_dev,
+                          double* V, int64_t ldv, hipStream_t stream) {
+  if (n <= 0 || kcap <= 0) return hipSuccess;
+  const unsigned g = grid_for((int64_t)kcap * n);
+  if (dtype == 1)
+    hipLaunchKernelGGL(build_v_kernel<float>, dim3(g), dim3(256), 0, stream, static_cast<const float*>(T), ldt, J, n, kcap,
+                       k_dev, V, ldv);
+  else
+    hipLaunchKernelGGL(build_v_kernel<double>, dim3(g), dim3(256), 0, stream, static_cast<const double*>(T), ldt, J, n,
+                       kcap, k_dev, V, ldv);
+  return hipGetLastError();
+}
+
+hipError_t add_gathered_launch(const double* Q, int64_t ldq, const int* J, int ka_host, const int* ka_dev, int kb_host,
+                               const int* kb_dev, double* out, int64_t ldo, hipStream_t stream) {
+  if (ka_host <= 0 || kb_host <= 0) return hipSuccess;
+  hipLaunchKernelGGL(add_gathered_kernel, dim3(grid_for((int64_t)ka_host * kb_host)), dim3(256), 0, stream, Q, ldq, J,
+                     ka_host, ka_dev, kb_host, kb_dev, out, ldo);
+  return hipGetLastError();
+}
+
+}  // namespace idcur
