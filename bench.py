@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Throughput of the randomized CUR-ID on one MI355X.
+
+Workload (the FP32 randomized configuration): A = U diag(sigma) V^T, 20000 x 10000,
+sigma_j = (j+1)^-2, U and V from the QR of seeded N(0,1) matrices (drawn on the
+GPU), FP32; rank k = 200, oversampling p = 10, one orthonormalised power step,
+Gaussian Omega (210 x 20000) drawn on the device from Philox4x32-10.
+
+One step = one idcur_cur call: Omega, the sketch and power-step GEMMs, the
+Cholesky-QR orthonormalisations, the column-pivoted QR of Y, T, the gather of C,
+the row ID of C, the gather of R and the least-squares U. The error evaluation
+(|A - CUR|_F) is timed separately, outside the steps.
+
+Prints ONE JSON line. Extra keys: matrices/s, the error, per-stage times, the
+plain FP32 GPU CPQR comparator (the same library with no sketch), the fastest
+(p, q) whose error is within 1.05x of the comparator's, the roofline of the
+dominant kernel (the sketch GEMMs) and the CPU oracle baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def source_hash(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-comparator", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--seed", type=int, default=20260)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1412_8447_amd as P
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    cfg = synth.CONFIGS["rand_fp32_20000x10000_k200"]
+    m, n, k, p, q = cfg.m, cfg.n, cfg.k, cfg.p, cfg.q
+    l = k + p
+
+    t0 = time.time()
+    log(f"generating A {m}x{n} on the GPU")
+    A64 = synth.lowrank_torch(m, n, cfg.spectrum(), seed=args.seed, device=dev)
+    A = A64.to(torch.float32).contiguous()
+    del A64
+    torch.cuda.synchronize()
+    log(f"A ready in {time.time() - t0:.1f}s")
+
+    kw = dict(p=p, q=q, seed=args.seed + 1)
+    ws = torch.empty(P.workspace_bytes(P.OP_CUR, A, P.make_opts(k, **kw)), dtype=torch.uint8, device=dev)
+    out = dict(J=torch.empty(n, dtype=torch.int32, device=dev), I=torch.empty(m, dtype=torch.int32, device=dev),
+               U=torch.empty(k, k, dtype=torch.float32, device=dev), C=torch.empty(m, k, dtype=torch.float32, device=dev),
+               R=torch.empty(k, n, dtype=torch.float32, device=dev), kout=torch.zeros(2, dtype=torch.int32, device=dev))
+
+    def step(**over):
+        o = dict(kw)
+        o.update(over)
+        return P.cur(A, k, workspace=ws, out=out, sync=False, **o)
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    P.sync_status(dev)
+
+    P.timing_enable(True, dev)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    log(f"timing {args.steps} steps")
+    tw0 = time.time()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.time() - tw0
+    ms = e0.elapsed_time(e1) / args.steps
+    stages = P.timing_read(dev)
+    P.timing_enable(False, dev)
+    P.sync_status(dev)
+    kout = out["kout"].tolist()
+    assert kout == [k, k], f"rank {kout}"
+    log(f"{ms:.3f} ms/step (wall {wall / args.steps * 1e3:.3f} ms)")
+
+    # error of the last step (outside the timed region)
+    err = P.cur_error(A, out["C"], out["U"], out["R"], out["kout"], k).tolist()
+    e_cur = math.sqrt(err[0] / err[1])
+    log(f"|A-CUR|_F/|A|_F = {e_cur:.4e} (Eckart-Young floor {cfg.frobenius_floor():.4e})")
+
+    flops = P.flop_model("cur", m, n, k, p, q)
+    value = flops["total"] / (ms * 1e-3) / 1e9
+
+    # dominant kernel: the sketch / power GEMMs (3 launches per step, 2 l m n each)
+    g_ms, g_cnt = stages["sketch_gemm"]
+    g_avg = g_ms / max(g_cnt, 1)
+    g_flops = 2.0 * l * m * n
+    achieved = g_flops / (g_avg * 1e-3) / 1e12
+    traffic = None
+    pmc_path = os.path.join(ROOT, "profiles", "sketch_gemm_pmc.json")
+    if os.path.exists(pmc_path):
+        with open(pmc_path) as f:
+            pmc = json.load(f)
+        if pmc.get("gemm_source_sha") == source_hash(os.path.join(ROOT, "paper_1412_8447_amd", "csrc", "gemm.hip")):
+            traffic = pmc.get("hbm_bytes_per_launch")
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": traffic,
+                "kernel": "sketch_gemm (FP32 MFMA 16x16x4)", "avg_launch_ms": round(g_avg, 4),
+                "launches": g_cnt, "flops_per_launch": g_flops}
+
+    result = {
+        "metric": "ID/CUR GFLOP/s + matrices/sec vs plain FP32 GPU CPQR at equal rel. Frobenius error",
+        "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "randomized CUR-ID, FP32 A=U diag((j+1)^-2) V^T 20000x10000, k=200, p=10, q=1",
+                   "m": m, "n": n, "k": k, "p": p, "q": q},
+        "matrices_per_s": round(1000.0 / ms, 3),
+        "rel_fro_error": e_cur,
+        "flops_per_step": flops["total"],
+        "stages_ms_per_step": {s: round(v[0] / args.steps, 4) for s, v in stages.items() if v[1]},
+        "roofline": roofline,
+    }
+
+    # plain FP32 GPU CPQR comparator (no sketch) and the equal-error sweep
+    if not args.no_comparator:
+        log("comparator: deterministic FP32 CPQR CUR-ID on A")
+        wsd = torch.empty(P.workspace_bytes(P.OP_CUR, A, P.make_opts(k)), dtype=torch.uint8, device=dev)
+        outd = {kk: torch.empty_like(v) for kk, v in out.items()}
+        P.cur(A, k, workspace=wsd, out=outd, sync=False)
+        P.sync_status(dev)
+        reps = 2
+        e0.record()
+        for _ in range(reps):
+            P.cur(A, k, workspace=wsd, out=outd, sync=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_d = e0.elapsed_time(e1) / reps
+        P.sync_status(dev)
+        errd = P.cur_error(A, outd["C"], outd["U"], outd["R"], outd["kout"], k).tolist()
+        e_det = math.sqrt(errd[0] / errd[1])
+        fl_d = P.flop_model("cur", m, n, k)["total"]
+        result["comparator"] = {"name": "plain FP32 GPU CPQR (deterministic CUR-ID, same kernels, Y = A)",
+                                "ms": round(ms_d, 3), "gflops": round(fl_d / (ms_d * 1e-3) / 1e9, 2),
+                                "rel_fro_error": e_det, "speedup_nominal": round(ms_d / ms, 2),
+                                "error_ratio_nominal": round(e_cur / e_det, 4)}
+        del wsd, outd
+        if not args.no_sweep:
+            best = None
+            sweep = []
+            for pp, qq in [(10, 1), (20, 1), (50, 1), (10, 2), (20, 2), (50, 2)]:
+                o = P.make_opts(k, p=pp, q=qq, seed=args.seed + 1)
+                wss = torch.empty(P.workspace_bytes(P.OP_CUR, A, o), dtype=torch.uint8, device=dev)
+                outs = {kk: torch.empty_like(v) for kk, v in out.items()}
+                P.cur(A, k, workspace=wss, out=outs, sync=False, p=pp, q=qq, seed=args.seed + 1)
+                P.sync_status(dev)
+                e0.record()
+                for _ in range(3):
+                    P.cur(A, k, workspace=wss, out=outs, sync=False, p=pp, q=qq, seed=args.seed + 1)
+                e1.record()
+                torch.cuda.synchronize()
+                ms_s = e0.elapsed_time(e1) / 3
+                er = P.cur_error(A, outs["C"], outs["U"], outs["R"], outs["kout"], k).tolist()
+                es = math.sqrt(er[0] / er[1])
+                row = {"p": pp, "q": qq, "ms": round(ms_s, 3), "rel_fro_error": es, "ratio_to_plain": round(es / e_det, 4)}
+                sweep.append(row)
+                log("sweep", row)
+                if es <= 1.05 * e_det and (best is None or ms_s < best["ms"]):
+                    best = row
+                del wss, outs
+            result["equal_error_sweep"] = sweep
+            if best is not None:
+                fl_b = P.flop_model("cur", m, n, k, best["p"], best["q"])["total"]
+                result["equal_error"] = dict(best, gflops=round(fl_b / (best["ms"] * 1e-3) / 1e9, 2),
+                                             matrices_per_s=round(1000.0 / best["ms"], 3),
+                                             speedup_vs_plain=round(ms_d / best["ms"], 2))
+
+    # CPU baseline: the FP64 oracle on the host cores, one full CUR-ID of this input
+    if not args.no_cpu_baseline:
+        import oracle
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([tp.get("num_threads", 1) for tp in threadpool_info()] or [os.cpu_count()])
+        except Exception:  # pragma: no cover
+            cores = os.cpu_count()
+        A_h = A.cpu().numpy().astype(np.float64)
+        om = oracle.philox.gaussian_omega(l, m, seed=args.seed + 1)
+        log(f"cpu baseline: oracle CUR-ID on {cores} threads")
+        tc = time.time()
+        ref = oracle.cur(A_h, k, omega=om, q=q)
+        tcpu = time.time() - tc
+        e_orc = oracle.e_cur(A_h, ref.C, ref.U, ref.R)
+        Jg = out["J"].cpu().numpy()
+        lead = 0
+        for gap in ref.ts.col.qr.gaps:
+            if gap < 1e-4:
+                break
+            lead += 1
+        result["cpu_baseline"] = {"value": round(flops["total"] / tcpu / 1e9, 3), "unit": "GFLOP/s", "cores": cores,
+                                  "kind": "oracle", "seconds": round(tcpu, 2),
+                                  "sample": "one full FP64 CUR-ID of the same 20000x10000 input (same Omega, q=1)",
+                                  "rel_fro_error": e_orc,
+                                  "gpu_error_ratio": round(e_cur / e_orc, 4),
+                                  "leading_pivots_identical": int(np.array_equal(Jg[:lead], ref.ts.col.J[:lead])),
+                                  "clear_pivots": lead}
+        log(f"oracle {tcpu:.1f}s e={e_orc:.4e}")
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

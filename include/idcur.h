@@ -104,6 +104,17 @@ const char* idcur_last_error(const idcur_ctx* ctx);
  * Returns IDCUR_OK or one of the device conditions (ERANKCAP, ENONFINITE, ETIMEOUT). */
 idcur_status idcur_sync_status(idcur_ctx* ctx);
 
+/* Per-stage GPU timers for measurement. With timing enabled, every later call on
+ * this context records a pair of HIP events on the context's stream around each
+ * stage: "omega", "sketch_gemm" (the sketch / power-step GEMM kernels alone,
+ * without their split-K reduction), "orth", "cpqr", "trsm", "gather", "row_id",
+ * "u_solve", "error". Enabling (or disabling) synchronises the stream and clears the
+ * accumulated marks. idcur_timing_read synchronises and returns the summed
+ * elapsed milliseconds and the number of marks of one stage (host outputs). */
+idcur_status idcur_timing_enable(idcur_ctx* ctx, int32_t enable);
+idcur_status idcur_timing_read(idcur_ctx* ctx, const char* stage, double* total_ms /* host */,
+                               int32_t* count /* host */);
+
 /* Workspace size in bytes for one call of `op` (idcur_op) with these arguments. */
 idcur_status idcur_workspace_bytes(idcur_ctx* ctx, int32_t op, int32_t dtype, int64_t m, int64_t n,
                                    const idcur_opts* opts /* host */, size_t* bytes /* host out */);
@@ -150,6 +161,25 @@ idcur_status idcur_cur(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, cons
                        const idcur_opts* opts, void* ws, size_t ws_bytes, int32_t* k_out,
                        int32_t* J, int32_t* I, void* U, int64_t ldu,
                        void* C, int64_t ldc, void* R, int64_t ldr);
+
+/* Error measurement (the relative Frobenius errors reported with every result).
+ * Both write out[0] = |A - C W|_F^2 and out[1] = |A|_F^2 (device doubles), with
+ * FP64 matrix-core products and FP64 sums (a fixed reduction order):
+ *   idcur_id_error   C = A(:, J(1:k)), W = V* = [I T] P*, so |A - C V*|_F is the
+ *                    column-ID error of Section 2.3 eq. (id_error).
+ *   idcur_cur_error  W = U R, the CUR-ID error |A - C U R|_F of Section 3.
+ * k_out is the device rank array written by the decomposition call (k_out[0]:
+ * column rank; k_out[1]: row rank for the CUR); kcap is the k (or kmax) that
+ * sized those buffers. Workspace from idcur_error_workspace_bytes (which: 0 for
+ * the ID error, 1 for the CUR error). */
+idcur_status idcur_error_workspace_bytes(idcur_ctx* ctx, int32_t which, int32_t dtype, int64_t m, int64_t n,
+                                         int32_t kcap, size_t* bytes /* host out */);
+idcur_status idcur_id_error(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+                            const int32_t* J, const void* T, int64_t ldt, const int32_t* k_out, int32_t kcap,
+                            void* ws, size_t ws_bytes, double* out);
+idcur_status idcur_cur_error(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+                             const void* C, int64_t ldc, const void* U, int64_t ldu, const void* R, int64_t ldr,
+                             const int32_t* k_out, int32_t kcap, void* ws, size_t ws_bytes, double* out);
 
 /* The Gaussian sketch matrix alone (Section 5.1: i.i.d. N(0,1) entries): writes
  * Omega(r, i), r < rows, i < cols, to out + r*ldo + i. Entry (r, i) is defined by

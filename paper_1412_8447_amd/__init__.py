@@ -83,13 +83,23 @@ _lib.idcur_id_row.argtypes = _common + [_vp, _vp, _i64]
 _lib.idcur_id_two_sided.argtypes = _common + [_vp, _vp, _i64, _vp, _vp, _i64]
 _lib.idcur_cur.argtypes = _common + [_vp, _vp, _vp, _i64, _vp, _i64, _vp, _i64]
 _lib.idcur_gaussian.argtypes = [_vp, _i32, _i64, _i64, _u64, _u64, _vp, _i64]
-for _f in ("idcur_create", "idcur_set_stream", "idcur_destroy", "idcur_sync_status", "idcur_workspace_bytes",
+_lib.idcur_error_workspace_bytes.argtypes = [_vp, _i32, _i32, _i64, _i64, _i32, ctypes.POINTER(_sz)]
+_lib.idcur_id_error.argtypes = [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _i32, _vp, _sz, _vp]
+_lib.idcur_cur_error.argtypes = [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i32, _vp,
+                                 _sz, _vp]
+_lib.idcur_timing_enable.argtypes = [_vp, _i32]
+_lib.idcur_timing_read.argtypes = [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32)]
+for _f in ("idcur_error_workspace_bytes", "idcur_id_error", "idcur_cur_error",
+           "idcur_timing_enable", "idcur_timing_read", "idcur_create", "idcur_set_stream", "idcur_destroy", "idcur_sync_status", "idcur_workspace_bytes",
            "idcur_id_col", "idcur_id_row", "idcur_id_two_sided", "idcur_cur", "idcur_gaussian"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("idcur_opts_default", "idcur_create", "idcur_set_stream", "idcur_destroy", "idcur_last_error",
             "idcur_sync_status", "idcur_workspace_bytes", "idcur_id_col", "idcur_id_row", "idcur_id_two_sided",
-            "idcur_cur", "idcur_gaussian")
+            "idcur_cur", "idcur_gaussian", "idcur_timing_enable", "idcur_timing_read", "idcur_error_workspace_bytes",
+            "idcur_id_error", "idcur_cur_error")
+
+STAGES = ("omega", "sketch_gemm", "orth", "cpqr", "trsm", "gather", "row_id", "u_solve", "error")
 
 
 class IDCurError(RuntimeError):
@@ -186,6 +196,7 @@ class ColumnID:
     J: torch.Tensor          # int32 (n,)
     T: torch.Tensor          # (k, n-k)
     k: int
+    kout: Optional[torch.Tensor] = None   # device int32 [k, 0]
 
 
 @dataclass
@@ -207,6 +218,7 @@ class CUR:
     R: torch.Tensor
     k: int
     k_row: int
+    kout: Optional[torch.Tensor] = None   # device int32 [k, k_row]
 
 
 def id_col(A: torch.Tensor, k: int = 0, *, workspace=None, sync: bool = True, **kw) -> ColumnID:
@@ -223,10 +235,10 @@ def id_col(A: torch.Tensor, k: int = 0, *, workspace=None, sync: bool = True, **
     _check(h, _lib.idcur_id_col(h, _dtype_code(A), m, n, A.data_ptr(), A.stride(0), ctypes.byref(o), ws.data_ptr(),
                                 ws.numel(), kout.data_ptr(), J.data_ptr(), T.data_ptr(), max(ldt, 1)))
     if not sync:
-        return ColumnID(J, T, -1)
+        return ColumnID(J, T, -1, kout)
     sync_status(A.device)
     kk = int(kout[0].item())
-    return ColumnID(J, T[:kk, : n - kk], kk)
+    return ColumnID(J, T[:kk, : n - kk], kk, kout)
 
 
 def id_row(A: torch.Tensor, k: int = 0, *, workspace=None, sync: bool = True, **kw) -> ColumnID:
@@ -290,10 +302,10 @@ def cur(A: torch.Tensor, k: int = 0, *, workspace=None, sync: bool = True, out=N
                              ws.numel(), kout.data_ptr(), J.data_ptr(), I.data_ptr(), U.data_ptr(), kcap,
                              C.data_ptr(), kcap, R.data_ptr(), n))
     if not sync:
-        return CUR(J, I, C, U, R, -1, -1)
+        return CUR(J, I, C, U, R, -1, -1, kout)
     sync_status(A.device)
     k1, k2 = (int(v) for v in kout.tolist())
-    return CUR(J, I, C[:, :k1], U[:k1, :k2], R[:k2], k1, k2)
+    return CUR(J, I, C[:, :k1], U[:k1, :k2], R[:k2], k1, k2, kout)
 
 
 def gaussian(rows: int, cols: int, seed: int, *, stream_id: int = 0, dtype=torch.float32,
@@ -302,4 +314,57 @@ def gaussian(rows: int, cols: int, seed: int, *, stream_id: int = 0, dtype=torch
     out = torch.empty(rows, cols, dtype=dtype, device=device)
     h = _context(out.device)
     _check(h, _lib.idcur_gaussian(h, _dtype_code(out), rows, cols, seed, stream_id, out.data_ptr(), cols))
+    return out
+
+
+def timing_enable(enable: bool = True, device=None) -> None:
+    """Switch the per-stage event timers on or off (clears previous marks)."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    h = _context(dev)
+    _check(h, _lib.idcur_timing_enable(h, 1 if enable else 0))
+
+
+def timing_read(device=None) -> dict:
+    """{stage: (total_ms, launches)} accumulated since timing_enable."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    h = _context(dev)
+    out = {}
+    for s in STAGES:
+        ms, cnt = ctypes.c_double(0.0), _i32(0)
+        _check(h, _lib.idcur_timing_read(h, s.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
+        out[s] = (ms.value, cnt.value)
+    return out
+
+
+def _err_ws(which, A, kcap, workspace):
+    h = _context(A.device)
+    nb = ctypes.c_size_t(0)
+    _check(h, _lib.idcur_error_workspace_bytes(h, which, _dtype_code(A), A.shape[0], A.shape[1], kcap,
+                                               ctypes.byref(nb)))
+    if workspace is None or workspace.numel() < nb.value:
+        workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=A.device)
+    return h, workspace
+
+
+def id_error(A: torch.Tensor, J: torch.Tensor, T: torch.Tensor, kout: torch.Tensor, kcap: int, *, workspace=None,
+             out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Device [|A - C V*|_F^2, |A|_F^2] (float64) for the column ID (J, T)."""
+    h, ws = _err_ws(0, A, kcap, workspace)
+    if out is None:
+        out = torch.zeros(2, dtype=torch.float64, device=A.device)
+    _check(h, _lib.idcur_id_error(h, _dtype_code(A), A.shape[0], A.shape[1], A.data_ptr(), A.stride(0), J.data_ptr(),
+                                  T.data_ptr(), T.stride(0), kout.data_ptr(), kcap, ws.data_ptr(), ws.numel(),
+                                  out.data_ptr()))
+    return out
+
+
+def cur_error(A: torch.Tensor, C: torch.Tensor, U: torch.Tensor, R: torch.Tensor, kout: torch.Tensor, kcap: int, *,
+              workspace=None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Device [|A - C U R|_F^2, |A|_F^2] (float64)."""
+    h, ws = _err_ws(1, A, kcap, workspace)
+    if out is None:
+        out = torch.zeros(2, dtype=torch.float64, device=A.device)
+    _check(h, _lib.idcur_cur_error(h, _dtype_code(A), A.shape[0], A.shape[1], A.data_ptr(), A.stride(0), C.data_ptr(),
+                                   C.stride(0), U.data_ptr(), U.stride(0), R.data_ptr(), R.stride(0), kout.data_ptr(),
+                                   kcap, ws.data_ptr(), ws.numel(), out.data_ptr()))
     return out

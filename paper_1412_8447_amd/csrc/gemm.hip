@@ -53,6 +53,9 @@ struct KArgs {
   double alpha, beta;
   int vec_a, vec_b;            // 4-wide vector loads allowed
   const int* m_dev; const int* n_dev;
+  // residual mode: accumulate sum (X - A*B)^2 over the tile instead of storing
+  const void* X; int64_t ldx; int x_type; double* rpart;
+  const int* k_dev;            // optional device bound on K
 };
 
 template <typename T> struct V4;
@@ -70,7 +73,7 @@ __device__ __forceinline__ void load4(const T* base, int64_t off, int nvalid, bo
   }
 }
 
-template <typename TA, typename TB, typename TAcc, int NT, bool A_KC, bool B_NC>
+template <typename TA, typename TB, typename TAcc, int NT, bool A_KC, bool B_NC, bool RESID = false>
 __global__ __launch_bounds__(256) void gemm_kernel(KArgs p) {
   constexpr int BN = 16 * NT;
   constexpr int SA = lds_stride<TAcc>(BM);
@@ -84,9 +87,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(KArgs p) {
   const int64_t Nb = p.n_dev ? min((int64_t)*p.n_dev, p.N) : p.N;
   const int64_t m0 = (int64_t)blockIdx.x * BM;
   const int64_t n0 = (int64_t)blockIdx.y * BN;
-  if (m0 >= Mb || n0 >= Nb) return;
+  if (m0 >= Mb || n0 >= Nb) {
+    if (RESID && threadIdx.x == 0) p.rpart[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = 0.0;
+    return;
+  }
+  const int64_t Kb = p.k_dev ? min((int64_t)*p.k_dev, p.K) : p.K;
   const int64_t kb = (int64_t)blockIdx.z * p.kps;
-  const int64_t ke = min(p.K, kb + p.kps);
+  const int64_t ke = min(Kb, kb + p.kps);
   const TA* A = static_cast<const TA*>(p.A);
   const TB* B = static_cast<const TB*>(p.B);
 
@@ -159,7 +166,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(KArgs p) {
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = AV{0, 0, 0, 0};
 
-  const int64_t ntile = (ke - kb + BK - 1) / BK;
+  const int64_t ntile = ke > kb ? (ke - kb + BK - 1) / BK : 0;
   if (ntile > 0) {
     gload(kb);
     sstore(0);
@@ -183,6 +190,31 @@ __global__ __launch_bounds__(256) void gemm_kernel(KArgs p) {
     }
   }
 
+  if (RESID) {
+    // sum of squared residuals of this tile, reduced in a fixed order
+    __shared__ double wsum[4];
+    double s = 0.0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rl = (sizeof(TAcc) == 4) ? (4 * (lane >> 4) + r) : ((lane >> 4) + 4 * r);
+        const int64_t gi = m0 + wv * 16 + rl;
+        const int64_t gj = n0 + t * 16 + (lane & 15);
+        if (gi < Mb && gj < Nb) {
+          const double x = p.x_type == 1 ? (double)static_cast<const float*>(p.X)[gi * p.ldx + gj]
+                                         : static_cast<const double*>(p.X)[gi * p.ldx + gj];
+          const double d = x - p.alpha * (double)acc[t][r];
+          s += d * d;
+        }
+      }
+    }
+    s = wave_sum(s);
+    if (lane == 0) wsum[wv] = s;
+    __syncthreads();
+    if (tid == 0) p.rpart[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+    return;
+  }
   // epilogue
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
@@ -263,7 +295,46 @@ int pick_nt(int64_t N) {
   return 16;
 }
 
+__global__ __launch_bounds__(256) void sum_partials(const double* part, int64_t n, double* out) {
+  // one workgroup; fixed assignment and order -> deterministic
+  __shared__ double ws[4];
+  double s = 0.0;
+  for (int64_t e = threadIdx.x; e < n; e += 256) s += part[e];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+}
+
 }  // namespace
+
+size_t gemm_resid_part_bytes(int64_t M, int64_t N) {
+  return (size_t)ceil_div(M, BM) * ceil_div(N, 256) * sizeof(double);
+}
+
+hipError_t gemm_resid_launch(int x_type, int64_t M, int64_t N, int64_t K, const void* Cm, int64_t ldc, int c_type,
+                             const double* W, int64_t ldw, const void* X, int64_t ldx, const int* k_dev,
+                             double* part, double* out, hipStream_t stream) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  KArgs k{};
+  k.M = M; k.N = N; k.K = K;
+  k.A = Cm; k.sam = ldc; k.sak = 1;
+  k.B = W; k.sbk = ldw; k.sbn = 1;
+  k.kps = round_up(std::max<int64_t>(K, 1), BK);
+  k.direct = 1; k.alpha = 1.0;
+  k.vec_a = 0; k.vec_b = ((uintptr_t)W % 32 == 0) && (ldw % 4 == 0);
+  k.X = X; k.ldx = ldx; k.x_type = x_type; k.rpart = part;
+  k.k_dev = k_dev;
+  dim3 grid((unsigned)ceil_div(M, BM), (unsigned)ceil_div(N, 256), 1);
+  if (c_type == 1)
+    hipLaunchKernelGGL((gemm_kernel<float, double, double, 16, true, true, true>), grid, dim3(256), 0, stream, k);
+  else
+    hipLaunchKernelGGL((gemm_kernel<double, double, double, 16, true, true, true>), grid, dim3(256), 0, stream, k);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sum_partials, dim3(1), dim3(256), 0, stream, part, (int64_t)grid.x * grid.y, out);
+  return hipGetLastError();
+}
 
 size_t gemm_part_bytes(const GemmDesc& d) {
   if (d.splitk <= 1) return 0;
@@ -278,7 +349,7 @@ int gemm_pick_splitk(int64_t M, int64_t N, int64_t K, int num_cus) {
   return s;
 }
 
-hipError_t gemm_launch(const GemmDesc& d, void* part, hipStream_t stream) {
+hipError_t gemm_launch(const GemmDesc& d, void* part, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1) {
   if (d.M <= 0 || d.N <= 0) return hipSuccess;
   const bool akc = (d.sak == 1);
   const bool bnc = (d.sbn == 1);
@@ -295,7 +366,7 @@ hipError_t gemm_launch(const GemmDesc& d, void* part, hipStream_t stream) {
   k.ldo = k.direct ? d.ldc : d.N;
   k.out_type = d.out_type;
   k.alpha = d.alpha; k.beta = d.beta;
-  k.m_dev = d.m_dev; k.n_dev = d.n_dev;
+  k.m_dev = d.m_dev; k.n_dev = d.n_dev; k.k_dev = d.k_dev;
   const size_t esz = d.in_type == 1 ? 4 : 8;
   auto aligned = [&](const void* p, int64_t other_stride) {
     return ((uintptr_t)p % (4 * esz) == 0) && (other_stride % 4 == 0);
@@ -304,10 +375,12 @@ hipError_t gemm_launch(const GemmDesc& d, void* part, hipStream_t stream) {
   k.vec_b = aligned(d.B, bnc ? d.sbk : d.sbn);
   dim3 grid((unsigned)ceil_div(d.M, BM), (unsigned)ceil_div(d.N, bn), (unsigned)splitk);
   hipError_t e;
+  if (ev0) (void)hipEventRecord(ev0, stream);
   if (d.in_type == 1 && d.acc_type == 1) e = launch_types<float, float, float>(nt, k, grid, akc, bnc, stream);
   else if (d.in_type == 1 && d.acc_type == 0) e = launch_types<float, float, double>(nt, k, grid, akc, bnc, stream);
   else if (d.in_type == 0 && d.acc_type == 0) e = launch_types<double, double, double>(nt, k, grid, akc, bnc, stream);
   else return hipErrorInvalidValue;
+  if (ev1) (void)hipEventRecord(ev1, stream);
   if (e != hipSuccess || splitk == 1) return e;
   const int64_t total = d.M * d.N;
   const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(total, 256), 4096);

@@ -15,12 +15,40 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
+#include <map>
+#include <vector>
+
 struct idcur_ctx {
   hipStream_t stream = nullptr;
   int device = 0;
   int num_cus = 256;
   int* dstatus = nullptr;
   std::string err;
+  // per-stage timers (HIP events on the stream), enabled by idcur_timing_enable
+  bool timing = false;
+  struct Mark {
+    std::string stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get_event() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void recycle() {
+    for (auto& m : marks) {
+      pool.push_back(m.a);
+      pool.push_back(m.b);
+    }
+    marks.clear();
+  }
 };
 
 namespace idcur {
@@ -74,13 +102,38 @@ struct Ctx {
   }
 };
 
+// Brackets the launches of one stage with a pair of events when timing is on.
+struct Stage {
+  const Ctx& x;
+  hipEvent_t a = nullptr, b = nullptr;
+  const char* name;
+  Stage(const Ctx& xx, const char* nm) : x(xx), name(nm) {
+    if (x.dry || !x.c->timing) return;
+    a = x.c->get_event();
+    b = x.c->get_event();
+    if (a && b) (void)hipEventRecord(a, x.s);
+  }
+  ~Stage() {
+    if (!a || !b) return;
+    (void)hipEventRecord(b, x.s);
+    x.c->marks.push_back({name, a, b});
+  }
+};
+
 // ---------------------------------------------------------------------------
 // GEMM helper: C = A * B in the descriptor's layout, with split-K scratch.
 // ---------------------------------------------------------------------------
-void gemm(const Ctx& x, GemmDesc d) {
+void gemm(const Ctx& x, GemmDesc d, const char* stage = nullptr) {
   d.splitk = gemm_pick_splitk(d.M, d.N, d.K, x.c->num_cus);
   void* part = x.ar->take(gemm_part_bytes(d));
-  if (!x.dry) x.check(gemm_launch(d, part, x.s), "gemm");
+  if (x.dry) return;
+  hipEvent_t a = nullptr, b = nullptr;
+  if (stage && x.c->timing) {
+    a = x.c->get_event();
+    b = x.c->get_event();
+  }
+  x.check(gemm_launch(d, part, x.s, a, b), "gemm");
+  if (a && b) x.c->marks.push_back({stage, a, b});
 }
 
 // Row-orthonormalise V (l x N), stored transposed as Vt (N x l, row-major):
@@ -134,12 +187,6 @@ ColId column_id(const Ctx& x, int dtype, const View& X, const idcur_opts& o, int
     void* Omt = x.ar->take((size_t)mr * l * esz(dtype));   // Omega^T, mr x l
     void* Yt = x.ar->take((size_t)nc * l * esz(dtype));    // Y^T,     nc x l
     void* Zt = o.q > 0 ? x.ar->take((size_t)mr * l * esz(dtype)) : nullptr;
-    if (!x.dry) {
-      if (o.omega)
-        x.check(copy2d_launch(dtype, l, mr, o.omega, mr, 1, Omt, 1, l, x.s), "omega copy");
-      else
-        x.check(gaussian_launch(dtype, l, mr, o.seed, 0, Omt, 1, l, x.s), "omega");
-    }
     auto mul_t = [&](const void* Bm) {   // Y^T = X^T * Bm   (Bm: mr x l)
       GemmDesc g{};
       g.M = nc; g.N = l; g.K = mr;
@@ -148,11 +195,23 @@ ColId column_id(const Ctx& x, int dtype, const View& X, const idcur_opts& o, int
       g.C = Yt; g.ldc = l;
       g.in_type = dtype; g.acc_type = dtype == IDCUR_F32 ? 1 : 0; g.out_type = dtype;
       g.alpha = 1.0; g.beta = 0.0;
-      gemm(x, g);
+      gemm(x, g, "sketch_gemm");
     };
+    {
+      Stage st(x, "omega");
+      if (!x.dry) {
+        if (o.omega)
+          x.check(copy2d_launch(dtype, l, mr, o.omega, mr, 1, Omt, 1, l, x.s), "omega copy");
+        else
+          x.check(gaussian_launch(dtype, l, mr, o.seed, 0, Omt, 1, l, x.s), "omega");
+      }
+    }
     mul_t(Omt);
     for (int it = 0; it < o.q; ++it) {
-      orth_rows(x, dtype, Yt, nc, l);
+      {
+        Stage st(x, "orth");
+        orth_rows(x, dtype, Yt, nc, l);
+      }
       GemmDesc g{};   // Z^T = X * Y^T
       g.M = mr; g.N = l; g.K = nc;
       g.A = X.A; g.sam = X.xr; g.sak = X.xc;
@@ -160,8 +219,11 @@ ColId column_id(const Ctx& x, int dtype, const View& X, const idcur_opts& o, int
       g.C = Zt; g.ldc = l;
       g.in_type = dtype; g.acc_type = dtype == IDCUR_F32 ? 1 : 0; g.out_type = dtype;
       g.alpha = 1.0; g.beta = 0.0;
-      gemm(x, g);
-      orth_rows(x, dtype, Zt, mr, l);
+      gemm(x, g, "sketch_gemm");
+      {
+        Stage st(x, "orth");
+        orth_rows(x, dtype, Zt, mr, l);
+      }
       mul_t(Zt);
     }
     Ymat = Yt; yrs = 1; ycs = l;
@@ -176,6 +238,7 @@ ColId column_id(const Ctx& x, int dtype, const View& X, const idcur_opts& o, int
   double* S11 = static_cast<double*>(x.ar->take((size_t)std::max(kcap, 1) * std::max(kcap, 1) * 8));
   r.S = S;
   if (!x.dry) {
+    Stage st(x, "cpqr");
     x.check(zero_launch(rec, pl.rec_bytes + pl.fin_bytes, x.s), "zero");
     CpqrArgs a{};
     a.Y = Ymat; a.rs = yrs; a.cs = ycs;
@@ -188,6 +251,9 @@ ColId column_id(const Ctx& x, int dtype, const View& X, const idcur_opts& o, int
     a.gslab = gslab; a.rec = rec; a.cvals = cvals;
     a.fin = reinterpret_cast<int*>(static_cast<char*>(rec) + pl.rec_bytes);
     x.check(cpqr_launch(dtype, pl, a, x.s), "cpqr");
+  }
+  if (!x.dry) {
+    Stage st(x, "trsm");
     // T = S11^{-1} S12
     x.check(gather_s11_launch(dtype, S, nc, J, kcap, k_out, S11, x.s), "gather S11");
     TrsmDesc t{};
@@ -212,6 +278,7 @@ void row_id_of_c(const Ctx& x, int dtype, const void* C, int64_t m, int kcap, co
   void* S = x.ar->take((size_t)std::max(kcap, 1) * m * esz(dtype));
   double* S11 = static_cast<double*>(x.ar->take((size_t)std::max(kcap, 1) * std::max(kcap, 1) * 8));
   if (x.dry) return;
+  Stage st(x, "row_id");
   x.check(zero_launch(rec, pl.rec_bytes + pl.fin_bytes, x.s), "zero");
   CpqrArgs a{};
   a.Y = C; a.rs = 1; a.cs = kcap;
@@ -372,7 +439,10 @@ void execute(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const void
   if (op == OP_COL) return;
   // C = A(:, J(1:k))
   void* C = ar.take((size_t)m * kcap * esz(dtype));
-  if (!ar.dry) x.check(gather_cols_launch(dtype, m, A, lda, J, kcap, out.k_out, C, kcap, dtype, x.s), "gather C");
+  if (!ar.dry) {
+    Stage st(x, "gather");
+    x.check(gather_cols_launch(dtype, m, A, lda, J, kcap, out.k_out, C, kcap, dtype, x.s), "gather C");
+  }
   void* Tr = out.Tr;
   int64_t ldtr = out.ldtr;
   if (!Tr) {
@@ -389,10 +459,82 @@ void execute(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const void
     ldr = n;
   }
   if (!ar.dry) {
+    Stage st(x, "gather");
     x.check(gather_rows_launch(dtype, n, A, lda, out.I, kcap, out.k_out + 1, R, ldr, dtype, x.s), "gather R");
     if (out.C) x.check(gather_cols_launch(dtype, m, A, lda, J, kcap, out.k_out, out.C, out.ldc, dtype, x.s), "C out");
   }
+  Stage st(x, "u_solve");
   solve_u(x, dtype, R, ldr, n, kcap, out.k_out, J, T, ldt, out.U, out.ldu);
+}
+
+// Error measurement: out[0] = |A - C W|_F^2, out[1] = |A|_F^2 (device doubles).
+// which == 0: ID error with C = A(:, J(1:k)), W = V*;  which == 1: CUR error, W = U R.
+struct ErrArgs {
+  int which;
+  const int* J; const void* T; int64_t ldt;
+  const void* C; int64_t ldc; const void* U; int64_t ldu; const void* R; int64_t ldr;
+  const int* k_out; int kcap; double* out;
+};
+
+void run_error(const Ctx& x, int dtype, int64_t m, int64_t n, const void* A, int64_t lda, const ErrArgs& e) {
+  const int kcap = e.kcap;
+  double* W = static_cast<double*>(x.ar->take((size_t)kcap * n * 8));
+  double* rpart = static_cast<double*>(x.ar->take(gemm_resid_part_bytes(m, n)));
+  double* spart = static_cast<double*>(x.ar->take(1024 * 8));
+  const void* C = e.C;
+  int64_t ldc = e.ldc;
+  if (e.which == 0) {
+    void* Cw = x.ar->take((size_t)m * kcap * esz(dtype));
+    if (!x.dry) {
+      x.check(gather_cols_launch(dtype, m, A, lda, e.J, kcap, e.k_out, Cw, kcap, dtype, x.s), "gather C");
+      x.check(build_vstar_launch(dtype, e.T, e.ldt, e.J, n, kcap, e.k_out, W, n, x.s), "build V*");
+    }
+    C = Cw;
+    ldc = kcap;
+  } else {
+    GemmDesc g{};   // W = U R  (k x n), FP64
+    g.M = kcap; g.N = n; g.K = kcap;
+    g.A = e.U; g.sam = e.ldu; g.sak = 1;
+    g.B = e.R; g.sbk = e.ldr; g.sbn = 1;
+    g.C = W; g.ldc = n;
+    g.in_type = dtype; g.acc_type = 0; g.out_type = 0;
+    g.alpha = 1.0; g.beta = 0.0; g.m_dev = e.k_out; g.k_dev = e.k_out + 1;
+    gemm(x, g);
+  }
+  if (x.dry) return;
+  x.check(gemm_resid_launch(dtype, m, n, kcap, C, ldc, dtype, W, n, A, lda, e.k_out, rpart, e.out, x.s), "residual");
+  x.check(sumsq_launch(dtype, m, n, A, lda, spart, e.out + 1, x.s), "norm of A");
+}
+
+idcur_status run_err(idcur_ctx* ctx, int dtype, int64_t m, int64_t n, const void* A, int64_t lda, const ErrArgs& e,
+                     void* ws, size_t ws_bytes, size_t* bytes_only) {
+  try {
+    if (!ctx) return IDCUR_EINVAL;
+    if (dtype != IDCUR_F32 && dtype != IDCUR_F64) fail(ctx, IDCUR_EDTYPE, "bad dtype");
+    if (m <= 0 || n <= 0 || lda < n || e.kcap <= 0 || e.kcap >= std::min(m, n)) fail(ctx, IDCUR_EINVAL, "bad sizes");
+    Arena dry;
+    Ctx xd{ctx, ctx->stream, true, &dry};
+    run_error(xd, dtype, m, n, A, lda, e);
+    if (bytes_only) {
+      *bytes_only = dry.off + 256;
+      return IDCUR_OK;
+    }
+    if (!A || !e.k_out || !e.out) fail(ctx, IDCUR_EINVAL, "null pointer");
+    if (e.which == 0 && (!e.J || !e.T || e.ldt < 1)) fail(ctx, IDCUR_EINVAL, "J and T are required");
+    if (e.which == 1 && (!e.C || !e.U || !e.R || e.ldc < e.kcap || e.ldu < e.kcap || e.ldr < n))
+      fail(ctx, IDCUR_EINVAL, "C, U and R are required");
+    if (!ws || ws_bytes < dry.off) fail(ctx, IDCUR_EWORKSPACE, "workspace missing or too small");
+    Arena ar;
+    ar.dry = false;
+    ar.base = static_cast<char*>(ws);
+    ar.cap = ws_bytes;
+    Ctx x{ctx, ctx->stream, false, &ar};
+    Stage st(x, "error");
+    run_error(x, dtype, m, n, A, lda, e);
+    return IDCUR_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  }
 }
 
 idcur_status run(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const void* A, int64_t lda,
@@ -476,6 +618,8 @@ idcur_status idcur_set_stream(idcur_ctx* ctx, void* stream) {
 
 idcur_status idcur_destroy(idcur_ctx* ctx) {
   if (!ctx) return IDCUR_EINVAL;
+  ctx->recycle();
+  for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
   if (ctx->dstatus) (void)hipFree(ctx->dstatus);
   delete ctx;
   return IDCUR_OK;
@@ -492,6 +636,31 @@ idcur_status idcur_sync_status(idcur_ctx* ctx) {
   if (st & ST_TIMEOUT) { ctx->err = "a grid-wide wait exceeded its spin limit"; return IDCUR_ETIMEOUT; }
   if (st & ST_NONFINITE) { ctx->err = "non-finite value or breakdown in a factorisation"; return IDCUR_ENONFINITE; }
   if (st & ST_RANKCAP) { ctx->err = "tolerance not reached within the rank cap"; return IDCUR_ERANKCAP; }
+  return IDCUR_OK;
+}
+
+idcur_status idcur_timing_enable(idcur_ctx* ctx, int32_t enable) {
+  if (!ctx) return IDCUR_EINVAL;
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) { ctx->err = "stream synchronisation failed"; return IDCUR_EHIP; }
+  ctx->recycle();
+  ctx->timing = enable != 0;
+  return IDCUR_OK;
+}
+
+idcur_status idcur_timing_read(idcur_ctx* ctx, const char* stage, double* total_ms, int32_t* count) {
+  if (!ctx || !stage || !total_ms || !count) return IDCUR_EINVAL;
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) { ctx->err = "stream synchronisation failed"; return IDCUR_EHIP; }
+  double tot = 0.0;
+  int cnt = 0;
+  for (auto& m : ctx->marks) {
+    if (m.stage != stage) continue;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, m.a, m.b) != hipSuccess) { ctx->err = "event timing failed"; return IDCUR_EHIP; }
+    tot += ms;
+    ++cnt;
+  }
+  *total_ms = tot;
+  *count = cnt;
   return IDCUR_OK;
 }
 
@@ -541,6 +710,32 @@ idcur_status idcur_cur(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, cons
   Outs o;
   o.k_out = k_out; o.J = J; o.I = I; o.U = U; o.ldu = ldu; o.C = C; o.ldc = ldc; o.R = R; o.ldr = ldr;
   return run(ctx, OP_CUR, dtype, m, n, A, lda, opts, ws, ws_bytes, o);
+}
+
+idcur_status idcur_error_workspace_bytes(idcur_ctx* ctx, int32_t which, int32_t dtype, int64_t m, int64_t n,
+                                         int32_t kcap, size_t* bytes) {
+  if (!bytes || (which != 0 && which != 1)) return IDCUR_EINVAL;
+  ErrArgs e{};
+  e.which = which;
+  e.kcap = kcap;
+  return run_err(ctx, dtype, m, n, nullptr, n, e, nullptr, 0, bytes);
+}
+
+idcur_status idcur_id_error(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+                            const int32_t* J, const void* T, int64_t ldt, const int32_t* k_out, int32_t kcap, void* ws,
+                            size_t ws_bytes, double* out) {
+  ErrArgs e{};
+  e.which = 0; e.J = J; e.T = T; e.ldt = ldt; e.k_out = k_out; e.kcap = kcap; e.out = out;
+  return run_err(ctx, dtype, m, n, A, lda, e, ws, ws_bytes, nullptr);
+}
+
+idcur_status idcur_cur_error(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+                             const void* C, int64_t ldc, const void* U, int64_t ldu, const void* R, int64_t ldr,
+                             const int32_t* k_out, int32_t kcap, void* ws, size_t ws_bytes, double* out) {
+  ErrArgs e{};
+  e.which = 1; e.C = C; e.ldc = ldc; e.U = U; e.ldu = ldu; e.R = R; e.ldr = ldr;
+  e.k_out = k_out; e.kcap = kcap; e.out = out;
+  return run_err(ctx, dtype, m, n, A, lda, e, ws, ws_bytes, nullptr);
 }
 
 idcur_status idcur_gaussian(idcur_ctx* ctx, int32_t dtype, int64_t rows, int64_t cols, uint64_t seed, uint64_t stream,

@@ -74,10 +74,21 @@ struct GemmDesc {
   double beta;
   const int* m_dev; // optional device bound on M (rows >= *m_dev are skipped)
   const int* n_dev; // optional device bound on N
+  const int* k_dev; // optional device bound on K
 };
 size_t gemm_part_bytes(const GemmDesc& d);
 int gemm_pick_splitk(int64_t M, int64_t N, int64_t K, int num_cus);
-hipError_t gemm_launch(const GemmDesc& d, void* part, hipStream_t stream);
+// ev0/ev1 (optional) bracket the GEMM kernel itself, not the split-K reduction.
+hipError_t gemm_launch(const GemmDesc& d, void* part, hipStream_t stream, hipEvent_t ev0 = nullptr,
+                       hipEvent_t ev1 = nullptr);
+
+// Residual norm: out = sum_{i<M, j<N} (X(i,j) - (C W)(i,j))^2 with C (M x K,
+// row-major ldc, type c_type), W (K x N, double, row-major ldw), X (M x N, x_type).
+// FP64 matrix-core products; `part` holds one partial per 64 x 256 tile.
+size_t gemm_resid_part_bytes(int64_t M, int64_t N);
+hipError_t gemm_resid_launch(int x_type, int64_t M, int64_t N, int64_t K, const void* C, int64_t ldc, int c_type,
+                             const double* W, int64_t ldw, const void* X, int64_t ldx, const int* k_dev,
+                             double* part, double* out, hipStream_t stream);
 
 // ---------------------------------------------------------------------------
 // Triangular solve (trsm.hip): op(Tri) X = B, Tri c x c double, row-major ld.
@@ -133,6 +144,13 @@ hipError_t zero_launch(void* p, size_t bytes, hipStream_t stream);
 hipError_t build_v_launch(int dtype, const void* T, int64_t ldt, const int* J, int64_t n, int kcap, const int* k_dev,
                           double* V, int64_t ldv, hipStream_t stream);
 // out(a, b) += Q(a, J[b]) for a < ka, b < kb (double), Q row-major ldq.
+// W = V* (kcap x n, double, row-major ldw): column J[s] is e_s (s < k), column
+// J[k+t] is T(:, t); rows >= k are zero.
+hipError_t build_vstar_launch(int dtype, const void* T, int64_t ldt, const int* J, int64_t n, int kcap,
+                              const int* k_dev, double* W, int64_t ldw, hipStream_t stream);
+// out = sum of squares of the m x n matrix A (FP64 accumulation; part: 1024 doubles).
+hipError_t sumsq_launch(int dtype, int64_t m, int64_t n, const void* A, int64_t lda, double* part, double* out,
+                        hipStream_t stream);
 hipError_t add_gathered_launch(const double* Q, int64_t ldq, const int* J, int ka_host, const int* ka_dev,
                                int kb_host, const int* kb_dev, double* out, int64_t ldo, hipStream_t stream);
 

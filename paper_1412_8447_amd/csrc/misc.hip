@@ -112,6 +112,44 @@ __global__ void build_v_kernel(const T* Tm, int64_t ldt, const int* J, int64_t n
   }
 }
 
+template <typename T>
+__global__ void build_vstar_kernel(const T* Tm, int64_t ldt, const int* J, int64_t n, int kcap, const int* k_dev,
+                                   double* W, int64_t ldw) {
+  const int k = k_dev ? min(*k_dev, kcap) : kcap;
+  const int64_t total = (int64_t)kcap * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / n, p = e % n;
+    double v = 0.0;
+    if (r < k) v = (p < k) ? ((r == p) ? 1.0 : 0.0) : (double)Tm[r * ldt + (p - k)];
+    W[r * ldw + J[p]] = v;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void sumsq_kernel(int64_t m, int64_t n, const T* A, int64_t lda, double* part) {
+  __shared__ double ws[4];
+  double s = 0.0;
+  const int64_t total = m * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const double v = (double)A[(e / n) * lda + e % n];
+    s += v * v;
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+}
+
+__global__ __launch_bounds__(256) void sum1024(const double* part, double* out) {
+  __shared__ double ws[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < 1024; i += 256) s += part[i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+}
+
 unsigned grid_for(int64_t work) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(work, 256), 8192)); }
 
 }  // namespace
@@ -195,6 +233,32 @@ hipError_t build_v_launch(int dtype, const void* T, int64_t ldt, const int* J, i
   else
     hipLaunchKernelGGL(build_v_kernel<double>, dim3(g), dim3(256), 0, stream, static_cast<const double*>(T), ldt, J, n,
                        kcap, k_dev, V, ldv);
+  return hipGetLastError();
+}
+
+hipError_t build_vstar_launch(int dtype, const void* T, int64_t ldt, const int* J, int64_t n, int kcap,
+                              const int* k_dev, double* W, int64_t ldw, hipStream_t stream) {
+  if (n <= 0 || kcap <= 0) return hipSuccess;
+  const unsigned g = grid_for((int64_t)kcap * n);
+  if (dtype == 1)
+    hipLaunchKernelGGL(build_vstar_kernel<float>, dim3(g), dim3(256), 0, stream, static_cast<const float*>(T), ldt, J, n,
+                       kcap, k_dev, W, ldw);
+  else
+    hipLaunchKernelGGL(build_vstar_kernel<double>, dim3(g), dim3(256), 0, stream, static_cast<const double*>(T), ldt, J,
+                       n, kcap, k_dev, W, ldw);
+  return hipGetLastError();
+}
+
+hipError_t sumsq_launch(int dtype, int64_t m, int64_t n, const void* A, int64_t lda, double* part, double* out,
+                        hipStream_t stream) {
+  if (dtype == 1)
+    hipLaunchKernelGGL(sumsq_kernel<float>, dim3(1024), dim3(256), 0, stream, m, n, static_cast<const float*>(A), lda, part);
+  else
+    hipLaunchKernelGGL(sumsq_kernel<double>, dim3(1024), dim3(256), 0, stream, m, n, static_cast<const double*>(A), lda,
+                       part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sum1024, dim3(1), dim3(256), 0, stream, part, out);
   return hipGetLastError();
 }
 

@@ -225,3 +225,25 @@ def test_ties_smallest_index():
     say("ties")
     got = P.id_col(to_dev(Y, torch.float64), 3)
     assert list(got.J.cpu().numpy()[:3]) == [2, 5, 8]
+
+
+# ---------------------------------------------------------------------------
+# Error measurement kernels
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_error_kernels_match_oracle(dtype):
+    m, n, k = 333, 517, 21
+    say(f"error kernels {dtype}")
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    A = synth.lowrank(m, n, synth.sigma_exp(min(m, n), 7.0), seed=51).astype(npdt)
+    A64 = A.astype(np.float64)
+    dA = to_dev(A, dtype)
+    ci = P.id_col(dA, k)
+    e2 = P.id_error(dA, ci.J, ci.T, ci.kout, k).cpu().numpy()
+    want = oracle.e_id(A64, ci.J.cpu().numpy(), ci.T.cpu().numpy().astype(np.float64))
+    assert abs(math.sqrt(e2[0] / e2[1]) / want - 1) <= 1e-9
+    assert abs(e2[1] / (A64 ** 2).sum() - 1) <= 1e-12
+    cu = P.cur(dA, k)
+    e3 = P.cur_error(dA, cu.C, cu.U, cu.R, cu.kout, k).cpu().numpy()
+    want3 = oracle.e_cur(A64, *(x.cpu().numpy().astype(np.float64) for x in (cu.C, cu.U, cu.R)))
+    assert abs(math.sqrt(e3[0] / e3[1]) / want3 - 1) <= 1e-9
