@@ -23,7 +23,8 @@ FLAGS = [
     "-Wno-unused-result", "-Wno-unused-variable",
 ]
 
-SOURCES = ["cpqr.hip", "gemm.hip", "trsm.hip", "chol.hip", "misc.hip", "host.cpp"]
+SOURCES = ["cpqr.hip", "gemm.hip", "gemm_f32.hip", "gemm_f32_f64acc.hip", "gemm_f64.hip", "gemm_f32_f64.hip",
+           "gemm_f64_f32.hip", "chol.hip", "misc.hip", "host.cpp"]
 
 
 def _compile(src: str, obj: str) -> None:

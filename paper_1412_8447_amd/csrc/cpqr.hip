@@ -72,6 +72,24 @@ __device__ ArgMax block_argmax(ArgMax a, double* sv, int* si) {
   return b;
 }
 
+// Argmax and sum in one pass (one pair of barriers).
+__device__ ArgMax block_argmax_sum(ArgMax a, double& s, double* sv, int* si, double* ss) {
+  a = wave_argmax(a);
+  s = wave_sum(s);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) { sv[w] = a.v; si[w] = a.i; ss[w] = s; }
+  __syncthreads();
+  ArgMax b{sv[0], si[0]};
+  double t = ss[0];
+  for (int i = 1; i < kWaves; ++i) {
+    if (better(sv[i], si[i], b.v, b.i)) { b.v = sv[i]; b.i = si[i]; }
+    t += ss[i];
+  }
+  s = t;
+  return b;
+}
+
 template <typename T, bool IN_LDS>
 __global__ __launch_bounds__(kThreads) void cpqr_kernel(CpqrArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -106,6 +124,7 @@ __global__ __launch_bounds__(kThreads) void cpqr_kernel(CpqrArgs a) {
   int* redi = reinterpret_cast<int*>(sp);          sp += 16 * sizeof(int);
   int* win = reinterpret_cast<int*>(sp);           // kmax_host ints
   __shared__ int sh_flags[4];                      // stop flag, winner owner, ...
+  __shared__ double sh_d[2];
 
   Rec* recs = reinterpret_cast<Rec*>(a.rec);      // [2][G]
   T* cvals = static_cast<T*>(a.cvals);             // [2][G][lpad]
@@ -154,9 +173,9 @@ __global__ __launch_bounds__(kThreads) void cpqr_kernel(CpqrArgs a) {
   int j = 0;
   bool timed_out = false;
 
-  // Publish this workgroup's candidate for publish index e (rows [rb, l)).
-  auto publish = [&](int e, int rb) {
-    // local argmax over active columns
+  // Publish this workgroup's candidate for publish index e (rows [rb, l)):
+  // all data words first, one wait for their completion, then the tag.
+  auto publish = [&](int e, int rb, bool norms_exact) {
     ArgMax best{-1.0, 0x7fffffff};
     double ssq = 0.0;
     for (int c = tid; c < ncl; c += kThreads) {
@@ -165,33 +184,34 @@ __global__ __launch_bounds__(kThreads) void cpqr_kernel(CpqrArgs a) {
         if (better(nu[c], c0 + c, best.v, best.i)) { best.v = nu[c]; best.i = c0 + c; }
       }
     }
-    best = block_argmax(best, red, redi);
-    ssq = block_sum(ssq, red + 8);
+    best = block_argmax_sum(best, ssq, red, redi, red + 8);
     const int par = e & 1;
-    T* dst = cvals + ((size_t)par * G + g) * lpad;
-    double xs = 0.0;
-    if (best.i != 0x7fffffff) {
-      const int cb = best.i - c0;
+    const int cb = best.i - c0;
+    double xnorm = best.v;
+    if (!norms_exact && best.i != 0x7fffffff) {
+      // the key is a downdated norm: the reflector needs the exact one
+      double xs = 0.0;
       for (int i = rb + tid; i < l; i += kThreads) {
-        const T y = slab.at(cb, i);
-        cstore(dst + (i - rb), y);
-        xs += (double)y * (double)y;
+        const double y = (double)slab.at(cb, i);
+        xs += y * y;
       }
+      xnorm = sqrt(block_sum(xs, red + 12));
     }
-    xs = block_sum(xs, red + 12);
+    T* dst = cvals + ((size_t)par * G + g) * lpad;
+    if (best.i != 0x7fffffff)
+      for (int i = rb + tid; i < l; i += kThreads) cstore(dst + (i - rb), slab.at(cb, i));
+    Rec* r = recs + (size_t)par * G + g;
+    if (tid == 0) {
+      cstore(&r->key, dbits(best.v));
+      cstore(&r->xnorm, dbits(xnorm));
+      cstore(&r->sumsq, dbits(ssq));
+    }
     wait_all_mem();
     __syncthreads();
-    if (tid == 0) {
-      Rec* r = recs + (size_t)par * G + g;
-      cstore(&r->key, dbits(best.v));
-      cstore(&r->xnorm, dbits(sqrt(xs)));
-      cstore(&r->sumsq, dbits(ssq));
-      wait_all_mem();
-      cstore(&r->tag, ((uint64_t)(e + 1) << 32) | (uint32_t)best.i);
-    }
+    if (tid == 0) cstore(&r->tag, ((uint64_t)(e + 1) << 32) | (uint32_t)best.i);
   };
 
-  publish(0, 0);
+  publish(0, 0, true);
 
   while (true) {
     // ---- exchange: read every workgroup's record of publish index j ------
@@ -218,8 +238,8 @@ __global__ __launch_bounds__(kThreads) void cpqr_kernel(CpqrArgs a) {
     __syncthreads();
     if (timed_out) sh_flags[0] = 1;
     // owner of the best candidate = the thread index that holds it
-    const ArgMax w = block_argmax(cand, red, redi);
-    const double tot = block_sum(ssq, red + 8);
+    double tot = ssq;
+    const ArgMax w = block_argmax_sum(cand, tot, red, redi, red + 8);
     if (cand.i == w.i && tid < G && w.i != 0x7fffffff) sh_flags[1] = tid;
     __syncthreads();
     if (sh_flags[0]) {
@@ -239,15 +259,15 @@ __global__ __launch_bounds__(kThreads) void cpqr_kernel(CpqrArgs a) {
       break;
     }
     if (w.i == 0x7fffffff || w.v <= a.rank_tol * nu0) break;
+    // winner's exact norm and trailing column, loaded together
     const Rec* wr = recs + (size_t)par * G + wowner;
-    const double xnorm = bitsd(cload(&wr->xnorm));
-    if (!(xnorm > 0.0)) break;
-
-    // ---- Householder vector from the winner's trailing column -----------
     const T* src = cvals + ((size_t)par * G + wowner) * lpad;
     const int len = l - j;
+    if (tid == 0) sh_d[0] = bitsd(cload(&wr->xnorm));
     for (int i = tid; i < len; i += kThreads) v[i] = cload(src + i);
     __syncthreads();
+    const double xnorm = sh_d[0];
+    if (!(xnorm > 0.0)) break;
     const double x0 = (double)v[0];
     const double alpha = (x0 >= 0.0) ? -xnorm : xnorm;
     const double tau = 1.0 / (xnorm * (xnorm + fabs(x0)));
@@ -268,18 +288,46 @@ __global__ __launch_bounds__(kThreads) void cpqr_kernel(CpqrArgs a) {
       const int cl = pass * per_pass + wv * gpw + gidx;
       const bool valid = cl < ncl && act[cl];
       double dot = 0.0;
-      if (valid)
-        for (int i = j + rgi; i < l; i += R) dot += (double)v[i - j] * (double)slab.at(cl, i);
+      if (valid) {
+        // unrolled so that several LDS reads are in flight (independent sums)
+        double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+        int i = j + rgi;
+        for (; i + 3 * R < l; i += 4 * R) {
+          d0 += (double)v[i - j] * (double)slab.at(cl, i);
+          d1 += (double)v[i + R - j] * (double)slab.at(cl, i + R);
+          d2 += (double)v[i + 2 * R - j] * (double)slab.at(cl, i + 2 * R);
+          d3 += (double)v[i + 3 * R - j] * (double)slab.at(cl, i + 3 * R);
+        }
+        for (; i < l; i += R) d0 += (double)v[i - j] * (double)slab.at(cl, i);
+        dot = (d0 + d1) + (d2 + d3);
+      }
       dot = group_sum(dot, R);
       const double wgt = tau * dot;
       double ss = 0.0, s_own = 0.0;
       if (valid) {
-        for (int i = j + rgi; i < l; i += R) {
+        int i = j + rgi;
+        if (rgi == 0) {   // row j: the entry of S
+          const T y = (T)((double)slab.at(cl, i) - wgt * (double)v[0]);
+          slab.at(cl, i) = y;
+          s_own = (double)y;
+          i += R;
+        }
+        double s0 = 0.0, s1 = 0.0;
+        for (; i + R < l; i += 2 * R) {
+          const double a0 = (double)slab.at(cl, i), a1 = (double)slab.at(cl, i + R);
+          const double b0 = (double)v[i - j], b1 = (double)v[i + R - j];
+          const T y0 = (T)(a0 - wgt * b0), y1 = (T)(a1 - wgt * b1);
+          slab.at(cl, i) = y0;
+          slab.at(cl, i + R) = y1;
+          s0 += (double)y0 * (double)y0;
+          s1 += (double)y1 * (double)y1;
+        }
+        for (; i < l; i += R) {
           const T y = (T)((double)slab.at(cl, i) - wgt * (double)v[i - j]);
           slab.at(cl, i) = y;
-          if (i == j) s_own = (double)y;
-          else if (a.norms_exact) ss += (double)y * (double)y;
+          s0 += (double)y * (double)y;
         }
+        if (a.norms_exact) ss = s0 + s1;
       }
       // row j of S for this column: held by the group's first lane
       const double s = __shfl(s_own, (lane / R) * R, 64);
@@ -314,7 +362,7 @@ __global__ __launch_bounds__(kThreads) void cpqr_kernel(CpqrArgs a) {
     __syncthreads();
     ++j;
     if (a.tol <= 0.0 && j >= kmax) break;   // fixed rank: nothing left to decide
-    publish(j, j);
+    publish(j, j, a.norms_exact != 0);
   }
 
   // ---- epilogue -------------------------------------------------------------

@@ -12,279 +12,11 @@
 // Matrix cores: v_mfma_f32_16x16x4f32 (FP32) or v_mfma_f64_16x16x4f64 (FP64).
 // Operand layout per 16x16x4 block: lane L holds A(L%16, L/16) and B(L/16, L%16).
 // Result layout: FP32 -> row 4*(L/16) + r, FP64 -> row L/16 + 4*r, column L%16.
-#include "common.hpp"
-#include "kernels.hpp"
+#include "gemm_kernel.hpp"
 
 namespace idcur {
+using namespace gk;
 namespace {
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-constexpr int BM = 64;
-constexpr int BK = 16;
-
-template <typename TAcc> struct AccVec;
-template <> struct AccVec<float> { using type = f32x4; };
-template <> struct AccVec<double> { using type = f64x4; };
-
-__device__ __forceinline__ f32x4 mfma(float a, float b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ f64x4 mfma(double a, double b, f64x4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
-// LDS row strides chosen so that the 4 k-rows touched by one MFMA operand read
-// start on different bank groups.
-template <typename TAcc>
-__host__ __device__ constexpr int lds_stride(int w) {
-  return sizeof(TAcc) == 4 ? (w + ((16 - (w % 64)) % 64 + 64) % 64) : (w + ((16 - (w % 32)) % 32 + 32) % 32);
-}
-
-struct KArgs {
-  int64_t M, N, K;
-  const void* A; int64_t sam, sak;
-  const void* B; int64_t sbk, sbn;
-  void* out; int64_t ldo;      // C (direct) or partial buffer (ld = N)
-  int64_t kps;                 // K per split (multiple of BK)
-  int direct;                  // 1: write C with alpha/beta/out_type
-  int out_type;
-  double alpha, beta;
-  int vec_a, vec_b;            // 4-wide vector loads allowed
-  const int* m_dev; const int* n_dev;
-  // residual mode: accumulate sum (X - A*B)^2 over the tile instead of storing
-  const void* X; int64_t ldx; int x_type; double* rpart;
-  const int* k_dev;            // optional device bound on K
-};
-
-template <typename T> struct V4;
-template <> struct V4<float> { using type = float4; };
-template <> struct V4<double> { using type = double4; };
-
-template <typename T>
-__device__ __forceinline__ void load4(const T* base, int64_t off, int nvalid, bool vec, T (&r)[4]) {
-  if (vec && nvalid >= 4) {
-    const typename V4<T>::type q = *reinterpret_cast<const typename V4<T>::type*>(base + off);
-    r[0] = q.x; r[1] = q.y; r[2] = q.z; r[3] = q.w;
-  } else {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) r[e] = (e < nvalid) ? base[off + e] : (T)0;
-  }
-}
-
-template <typename TA, typename TB, typename TAcc, int NT, bool A_KC, bool B_NC, bool RESID = false>
-__global__ __launch_bounds__(256) void gemm_kernel(KArgs p) {
-  constexpr int BN = 16 * NT;
-  constexpr int SA = lds_stride<TAcc>(BM);
-  constexpr int SB = lds_stride<TAcc>(BN);
-  constexpr int BQ = (BN * BK / 4 + 255) / 256;   // B quads per thread
-  __shared__ TAcc As[2][BK * SA];
-  __shared__ TAcc Bs[2][BK * SB];
-
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int64_t Mb = p.m_dev ? min((int64_t)*p.m_dev, p.M) : p.M;
-  const int64_t Nb = p.n_dev ? min((int64_t)*p.n_dev, p.N) : p.N;
-  const int64_t m0 = (int64_t)blockIdx.x * BM;
-  const int64_t n0 = (int64_t)blockIdx.y * BN;
-  if (m0 >= Mb || n0 >= Nb) {
-    if (RESID && threadIdx.x == 0) p.rpart[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = 0.0;
-    return;
-  }
-  const int64_t Kb = p.k_dev ? min((int64_t)*p.k_dev, p.K) : p.K;
-  const int64_t kb = (int64_t)blockIdx.z * p.kps;
-  const int64_t ke = min(Kb, kb + p.kps);
-  const TA* A = static_cast<const TA*>(p.A);
-  const TB* B = static_cast<const TB*>(p.B);
-
-  TA ra[4];
-  TB rb[BQ][4];
-
-  auto gload = [&](int64_t k0) {
-    // A tile: BM x BK
-    if (A_KC) {
-      const int row = tid >> 2, kq = (tid & 3) * 4;
-      const int64_t gi = m0 + row, gk = k0 + kq;
-      const int nv = (gi < Mb) ? (int)max((int64_t)0, min((int64_t)4, ke - gk)) : 0;
-      load4(A, gi * p.sam + gk, nv, p.vec_a, ra);
-    } else {
-      const int kr = tid >> 4, iq = (tid & 15) * 4;
-      const int64_t gk = k0 + kr, gi = m0 + iq;
-      const int nv = (gk < ke) ? (int)max((int64_t)0, min((int64_t)4, Mb - gi)) : 0;
-      load4(A, gk * p.sak + gi, nv, p.vec_a, ra);
-    }
-    // B tile: BK x BN
-#pragma unroll
-    for (int qq = 0; qq < BQ; ++qq) {
-      const int q = tid + qq * 256;
-      if (q < BN * BK / 4) {
-        if (B_NC) {
-          const int kr = q / (BN / 4), jq = (q % (BN / 4)) * 4;
-          const int64_t gk = k0 + kr, gj = n0 + jq;
-          const int nv = (gk < ke) ? (int)max((int64_t)0, min((int64_t)4, Nb - gj)) : 0;
-          load4(B, gk * p.sbk + gj, nv, p.vec_b, rb[qq]);
-        } else {
-          const int jc = q >> 2, kq = (q & 3) * 4;
-          const int64_t gj = n0 + jc, gk = k0 + kq;
-          const int nv = (gj < Nb) ? (int)max((int64_t)0, min((int64_t)4, ke - gk)) : 0;
-          load4(B, gj * p.sbn + gk, nv, p.vec_b, rb[qq]);
-        }
-      }
-    }
-  };
-  auto sstore = [&](int buf) {
-    TAcc* as = As[buf];
-    TAcc* bs = Bs[buf];
-    if (A_KC) {
-      const int row = tid >> 2, kq = (tid & 3) * 4;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) as[(kq + e) * SA + row] = (TAcc)ra[e];
-    } else {
-      const int kr = tid >> 4, iq = (tid & 15) * 4;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) as[kr * SA + iq + e] = (TAcc)ra[e];
-    }
-#pragma unroll
-    for (int qq = 0; qq < BQ; ++qq) {
-      const int q = tid + qq * 256;
-      if (q < BN * BK / 4) {
-        if (B_NC) {
-          const int kr = q / (BN / 4), jq = (q % (BN / 4)) * 4;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) bs[kr * SB + jq + e] = (TAcc)rb[qq][e];
-        } else {
-          const int jc = q >> 2, kq = (q & 3) * 4;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) bs[(kq + e) * SB + jc] = (TAcc)rb[qq][e];
-        }
-      }
-    }
-  };
-
-  using AV = typename AccVec<TAcc>::type;
-  AV acc[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = AV{0, 0, 0, 0};
-
-  const int64_t ntile = ke > kb ? (ke - kb + BK - 1) / BK : 0;
-  if (ntile > 0) {
-    gload(kb);
-    sstore(0);
-    __syncthreads();
-    for (int64_t it = 0; it < ntile; ++it) {
-      const int buf = (int)(it & 1);
-      if (it + 1 < ntile) gload(kb + (it + 1) * BK);
-      const TAcc* as = As[buf];
-      const TAcc* bs = Bs[buf];
-#pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
-        const TAcc a = as[(kk + (lane >> 4)) * SA + wv * 16 + (lane & 15)];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          const TAcc b = bs[(kk + (lane >> 4)) * SB + t * 16 + (lane & 15)];
-          acc[t] = mfma(a, b, acc[t]);
-        }
-      }
-      if (it + 1 < ntile) sstore(buf ^ 1);
-      __syncthreads();
-    }
-  }
-
-  if (RESID) {
-    // sum of squared residuals of this tile, reduced in a fixed order
-    __shared__ double wsum[4];
-    double s = 0.0;
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int rl = (sizeof(TAcc) == 4) ? (4 * (lane >> 4) + r) : ((lane >> 4) + 4 * r);
-        const int64_t gi = m0 + wv * 16 + rl;
-        const int64_t gj = n0 + t * 16 + (lane & 15);
-        if (gi < Mb && gj < Nb) {
-          const double x = p.x_type == 1 ? (double)static_cast<const float*>(p.X)[gi * p.ldx + gj]
-                                         : static_cast<const double*>(p.X)[gi * p.ldx + gj];
-          const double d = x - p.alpha * (double)acc[t][r];
-          s += d * d;
-        }
-      }
-    }
-    s = wave_sum(s);
-    if (lane == 0) wsum[wv] = s;
-    __syncthreads();
-    if (tid == 0) p.rpart[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
-    return;
-  }
-  // epilogue
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int rl = (sizeof(TAcc) == 4) ? (4 * (lane >> 4) + r) : ((lane >> 4) + 4 * r);
-      const int64_t gi = m0 + wv * 16 + rl;
-      const int64_t gj = n0 + t * 16 + (lane & 15);
-      if (gi < Mb && gj < Nb) {
-        const TAcc v = acc[t][r];
-        if (p.direct) {
-          if (p.out_type == 1) {
-            float* C = static_cast<float*>(p.out) + gi * p.ldo + gj;
-            const double o = p.beta != 0.0 ? p.beta * (double)*C : 0.0;
-            *C = (float)(p.alpha * (double)v + o);
-          } else {
-            double* C = static_cast<double*>(p.out) + gi * p.ldo + gj;
-            const double o = p.beta != 0.0 ? p.beta * *C : 0.0;
-            *C = p.alpha * (double)v + o;
-          }
-        } else {
-          TAcc* P = static_cast<TAcc*>(p.out) + ((int64_t)blockIdx.z * p.M + gi) * p.N + gj;
-          *P = v;
-        }
-      }
-    }
-  }
-}
-
-template <typename TAcc>
-__global__ __launch_bounds__(256) void splitk_reduce(const TAcc* part, int splitk, int64_t M, int64_t N,
-                                                     void* C, int64_t ldc, int out_type, double alpha,
-                                                     double beta, const int* m_dev, const int* n_dev) {
-  const int64_t Mb = m_dev ? min((int64_t)*m_dev, M) : M;
-  const int64_t Nb = n_dev ? min((int64_t)*n_dev, N) : N;
-  const int64_t total = M * N;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e / N, j = e % N;
-    if (i >= Mb || j >= Nb) continue;
-    double s = 0.0;
-    for (int z = 0; z < splitk; ++z) s += (double)part[(int64_t)z * total + e];
-    if (out_type == 1) {
-      float* c = static_cast<float*>(C) + i * ldc + j;
-      *c = (float)(alpha * s + (beta != 0.0 ? beta * (double)*c : 0.0));
-    } else {
-      double* c = static_cast<double*>(C) + i * ldc + j;
-      *c = alpha * s + (beta != 0.0 ? beta * *c : 0.0);
-    }
-  }
-}
-
-template <typename TA, typename TB, typename TAcc, int NT>
-hipError_t launch_nt(const KArgs& k, dim3 grid, bool akc, bool bnc, hipStream_t s) {
-  if (akc && bnc) hipLaunchKernelGGL((gemm_kernel<TA, TB, TAcc, NT, true, true>), grid, dim3(256), 0, s, k);
-  else if (akc && !bnc) hipLaunchKernelGGL((gemm_kernel<TA, TB, TAcc, NT, true, false>), grid, dim3(256), 0, s, k);
-  else if (!akc && bnc) hipLaunchKernelGGL((gemm_kernel<TA, TB, TAcc, NT, false, true>), grid, dim3(256), 0, s, k);
-  else hipLaunchKernelGGL((gemm_kernel<TA, TB, TAcc, NT, false, false>), grid, dim3(256), 0, s, k);
-  return hipGetLastError();
-}
-
-template <typename TA, typename TB, typename TAcc>
-hipError_t launch_types(int nt, const KArgs& k, dim3 grid, bool akc, bool bnc, hipStream_t s) {
-  switch (nt) {
-    case 2: return launch_nt<TA, TB, TAcc, 2>(k, grid, akc, bnc, s);
-    case 4: return launch_nt<TA, TB, TAcc, 4>(k, grid, akc, bnc, s);
-    case 8: return launch_nt<TA, TB, TAcc, 8>(k, grid, akc, bnc, s);
-    case 14: return launch_nt<TA, TB, TAcc, 14>(k, grid, akc, bnc, s);
-    default: return launch_nt<TA, TB, TAcc, 16>(k, grid, akc, bnc, s);
-  }
-}
 
 int pick_nt(int64_t N) {
   const int64_t t = ceil_div(N, 16);
@@ -344,8 +76,8 @@ size_t gemm_part_bytes(const GemmDesc& d) {
 int gemm_pick_splitk(int64_t M, int64_t N, int64_t K, int num_cus) {
   const int64_t stripes = ceil_div(M, BM) * ceil_div(N, 16 * pick_nt(N));
   int s = 1;
-  // aim for at least 2 workgroups per CU, keep >= 256 K per split
-  while (stripes * s < 2 * num_cus && K / (2 * s) >= 256 && s < 64) s *= 2;
+  // aim for at least 4 workgroups per CU, keep >= 256 K per split
+  while (stripes * s < 4 * num_cus && K / (2 * s) >= 256 && s < 64) s *= 2;
   return s;
 }
 
@@ -367,18 +99,21 @@ hipError_t gemm_launch(const GemmDesc& d, void* part, hipStream_t stream, hipEve
   k.out_type = d.out_type;
   k.alpha = d.alpha; k.beta = d.beta;
   k.m_dev = d.m_dev; k.n_dev = d.n_dev; k.k_dev = d.k_dev;
-  const size_t esz = d.in_type == 1 ? 4 : 8;
-  auto aligned = [&](const void* p, int64_t other_stride) {
-    return ((uintptr_t)p % (4 * esz) == 0) && (other_stride % 4 == 0);
+  const int ta_ = d.a_type >= 0 ? d.a_type : d.in_type, tb_ = d.b_type >= 0 ? d.b_type : d.in_type;
+  auto aligned = [&](const void* p, int64_t other_stride, int t) {
+    return ((uintptr_t)p % (4 * (t == 1 ? 4 : 8)) == 0) && (other_stride % 4 == 0);
   };
-  k.vec_a = aligned(d.A, akc ? d.sam : d.sak);
-  k.vec_b = aligned(d.B, bnc ? d.sbk : d.sbn);
+  k.vec_a = aligned(d.A, akc ? d.sam : d.sak, ta_);
+  k.vec_b = aligned(d.B, bnc ? d.sbk : d.sbn, tb_);
   dim3 grid((unsigned)ceil_div(d.M, BM), (unsigned)ceil_div(d.N, bn), (unsigned)splitk);
   hipError_t e;
   if (ev0) (void)hipEventRecord(ev0, stream);
-  if (d.in_type == 1 && d.acc_type == 1) e = launch_types<float, float, float>(nt, k, grid, akc, bnc, stream);
-  else if (d.in_type == 1 && d.acc_type == 0) e = launch_types<float, float, double>(nt, k, grid, akc, bnc, stream);
-  else if (d.in_type == 0 && d.acc_type == 0) e = launch_types<double, double, double>(nt, k, grid, akc, bnc, stream);
+  const int ta = d.a_type >= 0 ? d.a_type : d.in_type, tb = d.b_type >= 0 ? d.b_type : d.in_type;
+  if (ta == 1 && tb == 1 && d.acc_type == 1) e = launch_f32(nt, k, grid, akc, bnc, stream);
+  else if (ta == 1 && tb == 1 && d.acc_type == 0) e = launch_f32_f64acc(nt, k, grid, akc, bnc, stream);
+  else if (ta == 0 && tb == 0 && d.acc_type == 0) e = launch_f64(nt, k, grid, akc, bnc, stream);
+  else if (ta == 1 && tb == 0 && d.acc_type == 0) e = launch_f32_f64(nt, k, grid, akc, bnc, stream);
+  else if (ta == 0 && tb == 1 && d.acc_type == 0) e = launch_f64_f32(nt, k, grid, akc, bnc, stream);
   else return hipErrorInvalidValue;
   if (ev1) (void)hipEventRecord(ev1, stream);
   if (e != hipSuccess || splitk == 1) return e;

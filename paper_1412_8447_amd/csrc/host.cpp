@@ -136,29 +136,60 @@ void gemm(const Ctx& x, GemmDesc d, const char* stage = nullptr) {
   if (a && b) x.c->marks.push_back({stage, a, b});
 }
 
-// Row-orthonormalise V (l x N), stored transposed as Vt (N x l, row-major):
-// Cholesky QR twice (G = V V^T, G = L L^T, V <- L^{-1} V), FP64 Gram and factors.
-void orth_rows(const Ctx& x, int dtype, void* Vt, int64_t N, int l) {
+// Row-orthonormalise V (l x N), stored transposed as Vt (N x l, row-major),
+// into Qt (same layout): Cholesky QR, G = V V^T + s I = L L^T, Q = L^{-1} V,
+// with an FP64 Gram matrix, factor and inverse, and Q^T = V^T L^{-T} as one
+// matrix-core product. The next power step only needs a well-conditioned basis
+// of the row space (the pivoted QR is invariant to which basis), so one pass
+// with a tiny shift s, which rules out breakdown, is enough.
+void orth_rows(const Ctx& x, int dtype, const void* Vt, void* Qt, int64_t N, int l) {
   double* G = static_cast<double*>(x.ar->take((size_t)l * l * 8));
   double* L = static_cast<double*>(x.ar->take((size_t)l * l * 8));
-  for (int pass = 0; pass < 2; ++pass) {
-    GemmDesc g{};
-    g.M = l; g.N = l; g.K = N;
-    g.A = Vt; g.sam = 1; g.sak = l;
-    g.B = Vt; g.sbk = l; g.sbn = 1;
-    g.C = G; g.ldc = l;
-    g.in_type = dtype; g.acc_type = 0; g.out_type = 0;
-    g.alpha = 1.0; g.beta = 0.0;
-    gemm(x, g);
-    if (!x.dry) x.check(chol_launch(G, l, l, nullptr, L, l, pass == 0 ? 1e-14 : 1e-16, x.c->dstatus, x.s), "chol");
-    TrsmDesc t{};
-    t.tri = L; t.ldt = l; t.upper = 0; t.trans = 0;
-    t.c_host = l; t.c_dev = nullptr;
-    t.ncol_host = N; t.ncol_sub_c = 0; t.ncol_dev = nullptr;
-    t.B = Vt; t.b_type = dtype; t.sbr = 1; t.sbc = l; t.col_idx = nullptr; t.col_idx_off_c = 0;
-    t.X = Vt; t.x_type = dtype; t.sxr = 1; t.sxc = l;
-    if (!x.dry) x.check(trsm_launch(t, x.s), "trsm(orth)");
+  double* Li = static_cast<double*>(x.ar->take((size_t)l * l * 8));
+  GemmDesc g{};
+  g.M = l; g.N = l; g.K = N;
+  g.A = Vt; g.sam = 1; g.sak = l;
+  g.B = Vt; g.sbk = l; g.sbn = 1;
+  g.C = G; g.ldc = l;
+  g.in_type = dtype; g.acc_type = 0; g.out_type = 0;
+  g.alpha = 1.0; g.beta = 0.0;
+  gemm(x, g);
+  if (!x.dry) x.check(chol_inv_launch(0, G, l, 1, l, nullptr, L, l, Li, l, 1e-14, x.c->dstatus, x.s), "chol");
+  GemmDesc q{};   // Q^T = V^T L^{-T}
+  q.M = N; q.N = l; q.K = l;
+  q.A = Vt; q.sam = l; q.sak = 1;
+  q.B = Li; q.sbk = 1; q.sbn = l;
+  q.C = Qt; q.ldc = l;
+  q.a_type = dtype; q.b_type = 0; q.acc_type = 0; q.out_type = dtype;
+  q.alpha = 1.0; q.beta = 0.0;
+  gemm(x, q);
+}
+
+// T = S11^{-1} S12 for the rank-c pivoted QR held in S (rows by original column,
+// ld ldS): S11 gathered and inverted (as the lower factor S11^T), S12 gathered,
+// T = (S11^{-T})^T S12 as an FP64 matrix-core product written in T's dtype.
+void interp_matrix(const Ctx& x, int dtype, const void* S, int64_t ldS, const int* J, int64_t n, int kcap,
+                   const int* k_dev, void* T, int64_t ldt) {
+  double* S11 = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
+  double* S11it = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
+  double* S12 = static_cast<double*>(x.ar->take((size_t)kcap * std::max<int64_t>(n - 1, 1) * 8));
+  int* ncol = static_cast<int*>(x.ar->take(256));
+  const int64_t ldo = std::max<int64_t>(n - 1, 1);
+  if (!x.dry) {
+    x.check(gather_s11_launch(dtype, S, ldS, J, kcap, k_dev, S11, x.s), "gather S11");
+    x.check(gather_s12_launch(dtype, S, ldS, J, n, kcap, k_dev, S12, ldo, ncol, x.s), "gather S12");
+    // view S11^T as lower: element (i, j) = S11[j][i]
+    x.check(chol_inv_launch(1, S11, 1, kcap, kcap, k_dev, nullptr, 0, S11it, kcap, 0.0, x.c->dstatus, x.s), "S11 inverse");
   }
+  GemmDesc g{};   // T = S11^{-1} S12, A(i, kk) = S11it[kk][i]
+  g.M = kcap; g.N = std::min<int64_t>(n - 1, ldt); g.K = kcap;
+  g.A = S11it; g.sam = 1; g.sak = kcap;
+  g.B = S12; g.sbk = ldo; g.sbn = 1;
+  g.C = T; g.ldc = ldt;
+  g.in_type = 0; g.acc_type = 0; g.out_type = dtype;
+  g.alpha = 1.0; g.beta = 0.0;
+  g.m_dev = k_dev; g.k_dev = k_dev; g.n_dev = ncol;
+  gemm(x, g);
 }
 
 double default_rank_tol(int dtype, int64_t l) {
@@ -187,6 +218,8 @@ ColId column_id(const Ctx& x, int dtype, const View& X, const idcur_opts& o, int
     void* Omt = x.ar->take((size_t)mr * l * esz(dtype));   // Omega^T, mr x l
     void* Yt = x.ar->take((size_t)nc * l * esz(dtype));    // Y^T,     nc x l
     void* Zt = o.q > 0 ? x.ar->take((size_t)mr * l * esz(dtype)) : nullptr;
+    void* Qyt = o.q > 0 ? x.ar->take((size_t)nc * l * esz(dtype)) : nullptr;   // orth(Y)^T
+    void* Qzt = o.q > 0 ? x.ar->take((size_t)mr * l * esz(dtype)) : nullptr;   // orth(Z)^T
     auto mul_t = [&](const void* Bm) {   // Y^T = X^T * Bm   (Bm: mr x l)
       GemmDesc g{};
       g.M = nc; g.N = l; g.K = mr;
@@ -210,21 +243,21 @@ ColId column_id(const Ctx& x, int dtype, const View& X, const idcur_opts& o, int
     for (int it = 0; it < o.q; ++it) {
       {
         Stage st(x, "orth");
-        orth_rows(x, dtype, Yt, nc, l);
+        orth_rows(x, dtype, Yt, Qyt, nc, l);
       }
-      GemmDesc g{};   // Z^T = X * Y^T
+      GemmDesc g{};   // Z^T = X * orth(Y)^T
       g.M = mr; g.N = l; g.K = nc;
       g.A = X.A; g.sam = X.xr; g.sak = X.xc;
-      g.B = Yt; g.sbk = l; g.sbn = 1;
+      g.B = Qyt; g.sbk = l; g.sbn = 1;
       g.C = Zt; g.ldc = l;
       g.in_type = dtype; g.acc_type = dtype == IDCUR_F32 ? 1 : 0; g.out_type = dtype;
       g.alpha = 1.0; g.beta = 0.0;
       gemm(x, g, "sketch_gemm");
       {
         Stage st(x, "orth");
-        orth_rows(x, dtype, Zt, mr, l);
+        orth_rows(x, dtype, Zt, Qzt, mr, l);
       }
-      mul_t(Zt);
+      mul_t(Qzt);
     }
     Ymat = Yt; yrs = 1; ycs = l;
   }
@@ -235,7 +268,6 @@ ColId column_id(const Ctx& x, int dtype, const View& X, const idcur_opts& o, int
   void* cvals = x.ar->take(pl.cvals_bytes);
   void* gslab = pl.gslab_bytes ? x.ar->take(pl.gslab_bytes) : nullptr;
   void* S = x.ar->take((size_t)std::max(kcap, 1) * nc * esz(dtype));
-  double* S11 = static_cast<double*>(x.ar->take((size_t)std::max(kcap, 1) * std::max(kcap, 1) * 8));
   r.S = S;
   if (!x.dry) {
     Stage st(x, "cpqr");
@@ -252,17 +284,9 @@ ColId column_id(const Ctx& x, int dtype, const View& X, const idcur_opts& o, int
     a.fin = reinterpret_cast<int*>(static_cast<char*>(rec) + pl.rec_bytes);
     x.check(cpqr_launch(dtype, pl, a, x.s), "cpqr");
   }
-  if (!x.dry) {
+  {
     Stage st(x, "trsm");
-    // T = S11^{-1} S12
-    x.check(gather_s11_launch(dtype, S, nc, J, kcap, k_out, S11, x.s), "gather S11");
-    TrsmDesc t{};
-    t.tri = S11; t.ldt = kcap; t.upper = 1; t.trans = 0;
-    t.c_host = kcap; t.c_dev = k_out;
-    t.ncol_host = nc; t.ncol_sub_c = 1; t.ncol_dev = nullptr;
-    t.B = S; t.b_type = dtype; t.sbr = nc; t.sbc = 1; t.col_idx = J; t.col_idx_off_c = 1;
-    t.X = T; t.x_type = dtype; t.sxr = ldt; t.sxc = 1; t.xcol_lim = ldt;
-    x.check(trsm_launch(t, x.s), "trsm(T)");
+    interp_matrix(x, dtype, S, nc, J, nc, kcap, k_out, T, ldt);
   }
   return r;
 }
@@ -276,32 +300,28 @@ void row_id_of_c(const Ctx& x, int dtype, const void* C, int64_t m, int kcap, co
   void* cvals = x.ar->take(pl.cvals_bytes);
   void* gslab = pl.gslab_bytes ? x.ar->take(pl.gslab_bytes) : nullptr;
   void* S = x.ar->take((size_t)std::max(kcap, 1) * m * esz(dtype));
-  double* S11 = static_cast<double*>(x.ar->take((size_t)std::max(kcap, 1) * std::max(kcap, 1) * 8));
-  if (x.dry) return;
+  if (!x.dry) {
+    Stage st(x, "row_id");
+    x.check(zero_launch(rec, pl.rec_bytes + pl.fin_bytes, x.s), "zero");
+    CpqrArgs a{};
+    a.Y = C; a.rs = 1; a.cs = kcap;
+    a.l_host = kcap; a.l_dev = k_dev; a.n = (int)m;
+    a.kmax_host = kcap; a.kmax_dev = k_dev;
+    a.tol = 0.0;
+    a.rank_tol = 0.0;   // a full-rank ID: stop only on an exactly zero pivot
+    a.norms_exact = 0;
+    a.S = S; a.ldS = m; a.J = I; a.k_out = k_out_r; a.status = x.c->dstatus;
+    a.gslab = gslab; a.rec = rec; a.cvals = cvals;
+    a.fin = reinterpret_cast<int*>(static_cast<char*>(rec) + pl.rec_bytes);
+    x.check(cpqr_launch(dtype, pl, a, x.s), "cpqr(row)");
+  }
   Stage st(x, "row_id");
-  x.check(zero_launch(rec, pl.rec_bytes + pl.fin_bytes, x.s), "zero");
-  CpqrArgs a{};
-  a.Y = C; a.rs = 1; a.cs = kcap;
-  a.l_host = kcap; a.l_dev = k_dev; a.n = (int)m;
-  a.kmax_host = kcap; a.kmax_dev = k_dev;
-  a.tol = 0.0;
-  a.rank_tol = 0.0;   // a full-rank ID: stop only on an exactly zero pivot
-  a.norms_exact = 0;
-  a.S = S; a.ldS = m; a.J = I; a.k_out = k_out_r; a.status = x.c->dstatus;
-  a.gslab = gslab; a.rec = rec; a.cvals = cvals;
-  a.fin = reinterpret_cast<int*>(static_cast<char*>(rec) + pl.rec_bytes);
-  x.check(cpqr_launch(dtype, pl, a, x.s), "cpqr(row)");
-  x.check(gather_s11_launch(dtype, S, m, I, kcap, k_out_r, S11, x.s), "gather S11(row)");
-  TrsmDesc t{};
-  t.tri = S11; t.ldt = kcap; t.upper = 1; t.trans = 0;
-  t.c_host = kcap; t.c_dev = k_out_r;
-  t.ncol_host = m; t.ncol_sub_c = 1; t.ncol_dev = nullptr;
-  t.B = S; t.b_type = dtype; t.sbr = m; t.sbc = 1; t.col_idx = I; t.col_idx_off_c = 1;
-  t.X = Tr; t.x_type = dtype; t.sxr = ldtr; t.sxc = 1; t.xcol_lim = ldtr;
-  x.check(trsm_launch(t, x.s), "trsm(Tr)");
+  interp_matrix(x, dtype, S, m, I, m, kcap, k_out_r, Tr, ldtr);
 }
 
-// U = argmin |U R - V*|_F through the QR of R^T (Cholesky QR twice, FP64).
+// U = argmin |U R - V*|_F through the QR of R^T (Cholesky QR twice, FP64):
+// R^T = Q S_R with S_R = L2^T L1^T, so U^T = S_R^{-1} Q^T V = L1^{-T} L2^{-T} Q^T V.
+// Every step is a matrix-core product with the explicit triangular inverses.
 // R: kr x n (row-major ldr), V* from (J, T); k = kout[0] columns, kr = kout[1].
 void solve_u(const Ctx& x, int dtype, const void* R, int64_t ldr, int64_t n, int kcap, const int* kout, const int* J,
              const void* T, int64_t ldt, void* U, int64_t ldu) {
@@ -309,71 +329,42 @@ void solve_u(const Ctx& x, int dtype, const void* R, int64_t ldr, int64_t n, int
   const int* kr_dev = kout + 1;
   double* G = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
   double* L1 = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
+  double* L1i = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
   double* L2 = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
+  double* L2i = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
+  double* Q1t = static_cast<double*>(x.ar->take((size_t)kcap * n * 8));
   double* Qt = static_cast<double*>(x.ar->take((size_t)kcap * n * 8));
   double* V = static_cast<double*>(x.ar->take((size_t)n * kcap * 8));
   double* Bls = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
   double* Y1 = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
-  // G1 = R R^T
-  {
+  auto prod = [&](int64_t M, int64_t N, int64_t K, const void* Am, int64_t sam, int64_t sak, int at, const void* Bm,
+                  int64_t sbk, int64_t sbn, int bt, void* Cm, int64_t ldc, int ct, const int* md, const int* nd,
+                  const int* kd) {
     GemmDesc g{};
-    g.M = kcap; g.N = kcap; g.K = n;
-    g.A = R; g.sam = ldr; g.sak = 1;
-    g.B = R; g.sbk = 1; g.sbn = ldr;
-    g.C = G; g.ldc = kcap;
-    g.in_type = dtype; g.acc_type = 0; g.out_type = 0;
-    g.alpha = 1.0; g.beta = 0.0; g.m_dev = kr_dev; g.n_dev = kr_dev;
+    g.M = M; g.N = N; g.K = K;
+    g.A = Am; g.sam = sam; g.sak = sak; g.a_type = at;
+    g.B = Bm; g.sbk = sbk; g.sbn = sbn; g.b_type = bt;
+    g.C = Cm; g.ldc = ldc; g.out_type = ct;
+    g.in_type = at; g.acc_type = 0; g.alpha = 1.0; g.beta = 0.0;
+    g.m_dev = md; g.n_dev = nd; g.k_dev = kd;
     gemm(x, g);
-  }
-  if (!x.dry) {
-    x.check(chol_launch(G, kcap, kcap, kr_dev, L1, kcap, 1e-15, x.c->dstatus, x.s), "chol(R)");
-    TrsmDesc t{};   // Q1^T = L1^{-1} R
-    t.tri = L1; t.ldt = kcap; t.upper = 0; t.trans = 0; t.c_host = kcap; t.c_dev = kr_dev;
-    t.ncol_host = n; t.B = R; t.b_type = dtype; t.sbr = ldr; t.sbc = 1;
-    t.X = Qt; t.x_type = 0; t.sxr = n; t.sxc = 1;
-    x.check(trsm_launch(t, x.s), "trsm(Q1)");
-  }
-  {
-    GemmDesc g{};   // G2 = Q1^T Q1
-    g.M = kcap; g.N = kcap; g.K = n;
-    g.A = Qt; g.sam = n; g.sak = 1;
-    g.B = Qt; g.sbk = 1; g.sbn = n;
-    g.C = G; g.ldc = kcap;
-    g.in_type = 0; g.acc_type = 0; g.out_type = 0;
-    g.alpha = 1.0; g.beta = 0.0; g.m_dev = kr_dev; g.n_dev = kr_dev;
-    gemm(x, g);
-  }
-  if (!x.dry) {
-    x.check(chol_launch(G, kcap, kcap, kr_dev, L2, kcap, 0.0, x.c->dstatus, x.s), "chol(Q1)");
-    TrsmDesc t{};   // Q^T = L2^{-1} Q1^T (in place)
-    t.tri = L2; t.ldt = kcap; t.upper = 0; t.trans = 0; t.c_host = kcap; t.c_dev = kr_dev;
-    t.ncol_host = n; t.B = Qt; t.b_type = 0; t.sbr = n; t.sbc = 1;
-    t.X = Qt; t.x_type = 0; t.sxr = n; t.sxc = 1;
-    x.check(trsm_launch(t, x.s), "trsm(Q)");
-    x.check(build_v_launch(dtype, T, ldt, J, n, kcap, k_dev, V, kcap, x.s), "build V");
-  }
-  {
-    GemmDesc g{};   // Bls = Q^T V  (kr x k)
-    g.M = kcap; g.N = kcap; g.K = n;
-    g.A = Qt; g.sam = n; g.sak = 1;
-    g.B = V; g.sbk = kcap; g.sbn = 1;
-    g.C = Bls; g.ldc = kcap;
-    g.in_type = 0; g.acc_type = 0; g.out_type = 0;
-    g.alpha = 1.0; g.beta = 0.0; g.m_dev = kr_dev; g.n_dev = k_dev;
-    gemm(x, g);
-  }
-  if (!x.dry) {
-    TrsmDesc t{};   // L2^T Y1 = Bls
-    t.tri = L2; t.ldt = kcap; t.upper = 0; t.trans = 1; t.c_host = kcap; t.c_dev = kr_dev;
-    t.ncol_host = kcap; t.ncol_dev = k_dev; t.B = Bls; t.b_type = 0; t.sbr = kcap; t.sbc = 1;
-    t.X = Y1; t.x_type = 0; t.sxr = kcap; t.sxc = 1;
-    x.check(trsm_launch(t, x.s), "trsm(L2^T)");
-    TrsmDesc u{};   // L1^T U^T = Y1, written transposed into U (k x kr)
-    u.tri = L1; u.ldt = kcap; u.upper = 0; u.trans = 1; u.c_host = kcap; u.c_dev = kr_dev;
-    u.ncol_host = kcap; u.ncol_dev = k_dev; u.B = Y1; u.b_type = 0; u.sbr = kcap; u.sbc = 1;
-    u.X = U; u.x_type = dtype; u.sxr = 1; u.sxc = ldu;
-    x.check(trsm_launch(u, x.s), "trsm(L1^T)");
-  }
+  };
+  // G1 = R R^T, L1 L1^T = G1
+  prod(kcap, kcap, n, R, ldr, 1, dtype, R, 1, ldr, dtype, G, kcap, 0, kr_dev, kr_dev, nullptr);
+  if (!x.dry) x.check(chol_inv_launch(0, G, kcap, 1, kcap, kr_dev, L1, kcap, L1i, kcap, 1e-15, x.c->dstatus, x.s), "chol(R)");
+  // Q1^T = L1^{-1} R
+  prod(kcap, n, kcap, L1i, kcap, 1, 0, R, ldr, 1, dtype, Q1t, n, 0, kr_dev, nullptr, kr_dev);
+  // G2 = Q1^T Q1, L2 L2^T = G2, Q^T = L2^{-1} Q1^T
+  prod(kcap, kcap, n, Q1t, n, 1, 0, Q1t, 1, n, 0, G, kcap, 0, kr_dev, kr_dev, nullptr);
+  if (!x.dry) x.check(chol_inv_launch(0, G, kcap, 1, kcap, kr_dev, L2, kcap, L2i, kcap, 0.0, x.c->dstatus, x.s), "chol(Q1)");
+  prod(kcap, n, kcap, L2i, kcap, 1, 0, Q1t, n, 1, 0, Qt, n, 0, kr_dev, nullptr, kr_dev);
+  // Bls = Q^T V (kr x k)
+  if (!x.dry) x.check(build_v_launch(dtype, T, ldt, J, n, kcap, k_dev, V, kcap, x.s), "build V");
+  prod(kcap, kcap, n, Qt, n, 1, 0, V, kcap, 1, 0, Bls, kcap, 0, kr_dev, k_dev, nullptr);
+  // Y1 = L2^{-T} Bls  (A(i, kk) = L2i[kk][i])
+  prod(kcap, kcap, kcap, L2i, 1, kcap, 0, Bls, kcap, 1, 0, Y1, kcap, 0, kr_dev, k_dev, kr_dev);
+  // U = Y1^T L1^{-1}  (k x kr): A(i, kk) = Y1[kk][i]
+  prod(kcap, kcap, kcap, Y1, 1, kcap, 0, L1i, kcap, 1, 0, U, ldu, dtype, k_dev, kr_dev, kr_dev);
 }
 
 enum Op { OP_COL = 0, OP_ROW = 1, OP_TWO = 2, OP_CUR = 3 };

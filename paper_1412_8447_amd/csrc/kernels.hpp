@@ -66,7 +66,9 @@ struct GemmDesc {
   const void* A; int64_t sam, sak;
   const void* B; int64_t sbk, sbn;
   void* C; int64_t ldc;
-  int in_type;      // of A and B
+  int in_type;      // of A and B (unless a_type / b_type are set)
+  int a_type = -1;  // overrides in_type for A when >= 0
+  int b_type = -1;  // overrides in_type for B when >= 0
   int acc_type;
   int out_type;     // of C
   int splitk;       // >= 1
@@ -91,35 +93,23 @@ hipError_t gemm_resid_launch(int x_type, int64_t M, int64_t N, int64_t K, const 
                              double* part, double* out, hipStream_t stream);
 
 // ---------------------------------------------------------------------------
-// Triangular solve (trsm.hip): op(Tri) X = B, Tri c x c double, row-major ld.
-//   B(r, col) = B[r*sbr + bcol(col)*sbc] with bcol(col) = col_idx ? col_idx[col] : col
-//   X(r, col) = X[r*sxr + col*sxc]
-// c and ncol may be bounded by device values (c_dev: c = *c_dev; ncol becomes
-// ncol_base - *c_dev when ncol_sub_c is set). Tri is upper (upper = 1) or
-// lower; trans = 1 uses Tri^T.
+// Cholesky factor and triangular inverse (chol.hip), FP64, c <= 256, one workgroup.
+//   mode 0: G = L L^T (G(i,j) = G[i*gr + j*gc], optional diagonal shift
+//           shift_rel * max diag) -> L (row-major, zeros above) and X = L^{-1}
+//   mode 1: G is a lower-triangular factor (strided view) -> X = G^{-1}
+// A non-positive pivot is clamped and reported through `status`.
 // ---------------------------------------------------------------------------
-struct TrsmDesc {
-  const double* tri; int64_t ldt;
-  int upper, trans;
-  int c_host; const int* c_dev;
-  int64_t ncol_host; int ncol_sub_c; const int* ncol_dev;   // ncol_dev: ncol = min(*ncol_dev, ncol_host)
-  const void* B; int b_type; int64_t sbr, sbc; const int* col_idx; int col_idx_off_c;
-  void* X; int x_type; int64_t sxr, sxc;
-  int64_t xcol_lim;   // > 0: columns >= xcol_lim of X are not written
-};
-hipError_t trsm_launch(const TrsmDesc& d, hipStream_t stream);
+size_t chol_inv_lds_bytes(int c_host);
+hipError_t chol_inv_launch(int mode, const double* G, int64_t gr, int64_t gc, int c_host, const int* c_dev, double* L,
+                           int64_t ldl, double* X, int64_t ldx, double shift_rel, int* status, hipStream_t stream);
 
-// Gather S11 = S(0:c, J(0:c)) into a dense c x c double matrix (row-major).
+// S11 = S(0:c, J(0:c)) into a dense c x c double matrix (row-major, ld c_host).
 hipError_t gather_s11_launch(int dtype, const void* S, int64_t ldS, const int* J, int c_host,
                              const int* c_dev, double* out, hipStream_t stream);
-
-// ---------------------------------------------------------------------------
-// Cholesky of a small SPD matrix (chol.hip): G = L L^T, c <= 256, double.
-// Writes L (row-major, zeros above the diagonal). A non-positive pivot is
-// clamped to a tiny positive value and reported through `status`.
-// ---------------------------------------------------------------------------
-hipError_t chol_launch(const double* G, int64_t ldg, int c_host, const int* c_dev, double* L,
-                       int64_t ldl, double shift_rel, int* status, hipStream_t stream);
+// S12 = S(0:c, J(c:n)) into a dense c x (n - c) double matrix (ld ldo) with c read
+// on the device; also writes n - c to *ncols_out (device int).
+hipError_t gather_s12_launch(int dtype, const void* S, int64_t ldS, const int* J, int64_t n, int c_host,
+                             const int* c_dev, double* out, int64_t ldo, int* ncols_out, hipStream_t stream);
 
 // ---------------------------------------------------------------------------
 // Miscellaneous (misc.hip)

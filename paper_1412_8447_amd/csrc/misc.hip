@@ -150,6 +150,27 @@ __global__ __launch_bounds__(256) void sum1024(const double* part, double* out) 
   if (threadIdx.x == 0) *out = ((ws[0] + ws[1]) + ws[2]) + ws[3];
 }
 
+template <typename T>
+__global__ void gather_s11_kernel(const T* S, int64_t ldS, const int* J, int c_host, const int* c_dev, double* out) {
+  const int c = c_dev ? min(*c_dev, c_host) : c_host;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)c * c; e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e / c), s = (int)(e % c);
+    out[(int64_t)r * c_host + s] = (double)S[(int64_t)r * ldS + J[s]];
+  }
+}
+
+template <typename T>
+__global__ void gather_s12_kernel(const T* S, int64_t ldS, const int* J, int64_t n, int c_host, const int* c_dev,
+                                  double* out, int64_t ldo, int* ncols_out) {
+  const int c = c_dev ? min(*c_dev, c_host) : c_host;
+  const int64_t nc = n - c;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *ncols_out = (int)nc;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)c * nc; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / nc, t = e % nc;
+    out[r * ldo + t] = (double)S[r * ldS + J[c + t]];
+  }
+}
+
 unsigned grid_for(int64_t work) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(work, 256), 8192)); }
 
 }  // namespace
@@ -233,6 +254,31 @@ hipError_t build_v_launch(int dtype, const void* T, int64_t ldt, const int* J, i
   else
     hipLaunchKernelGGL(build_v_kernel<double>, dim3(g), dim3(256), 0, stream, static_cast<const double*>(T), ldt, J, n,
                        kcap, k_dev, V, ldv);
+  return hipGetLastError();
+}
+
+hipError_t gather_s11_launch(int dtype, const void* S, int64_t ldS, const int* J, int c_host, const int* c_dev,
+                             double* out, hipStream_t stream) {
+  if (c_host <= 0) return hipSuccess;
+  const unsigned g = grid_for((int64_t)c_host * c_host);
+  if (dtype == 1)
+    hipLaunchKernelGGL(gather_s11_kernel<float>, dim3(g), dim3(256), 0, stream, static_cast<const float*>(S), ldS, J,
+                       c_host, c_dev, out);
+  else
+    hipLaunchKernelGGL(gather_s11_kernel<double>, dim3(g), dim3(256), 0, stream, static_cast<const double*>(S), ldS, J,
+                       c_host, c_dev, out);
+  return hipGetLastError();
+}
+
+hipError_t gather_s12_launch(int dtype, const void* S, int64_t ldS, const int* J, int64_t n, int c_host,
+                             const int* c_dev, double* out, int64_t ldo, int* ncols_out, hipStream_t stream) {
+  const unsigned g = grid_for((int64_t)c_host * n);
+  if (dtype == 1)
+    hipLaunchKernelGGL(gather_s12_kernel<float>, dim3(g), dim3(256), 0, stream, static_cast<const float*>(S), ldS, J, n,
+                       c_host, c_dev, out, ldo, ncols_out);
+  else
+    hipLaunchKernelGGL(gather_s12_kernel<double>, dim3(g), dim3(256), 0, stream, static_cast<const double*>(S), ldS, J,
+                       n, c_host, c_dev, out, ldo, ncols_out);
   return hipGetLastError();
 }
 
