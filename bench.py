@@ -23,6 +23,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -37,9 +38,32 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def source_hash(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+GEMM_SOURCES = ("gemm_kernel.hpp", "gemm.hip", "gemm_f32.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sketch_gemm_fp32_20000x10000_l210_traffic.md")
+
+
+def gemm_source_hash():
+    h = hashlib.sha256()
+    for f in GEMM_SOURCES:
+        with open(os.path.join(ROOT, "paper_1412_8447_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per sketch-GEMM launch from the committed counter summary, or
+    None when the GEMM sources changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            m = re.match(r"^\s*(\w+)\s*=\s*(\S+)\s*$", line)
+            if m:
+                kv[m.group(1)] = m.group(2)
+    if kv.get("gemm_sources_sha") != gemm_source_hash() or "traffic_bytes_per_launch" not in kv:
+        return None
+    return int(float(kv["traffic_bytes_per_launch"]))
 
 
 def main():
@@ -51,6 +75,8 @@ def main():
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--seed", type=int, default=20260)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path; run with --gpus 1", file=sys.stderr)
@@ -64,6 +90,15 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_calib:
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes_read": nbytes, "copy_calib_bytes_written": nbytes, "launches": 3}))
+        return
     cfg = synth.CONFIGS["rand_fp32_20000x10000_k200"]
     m, n, k, p, q = cfg.m, cfg.n, cfg.k, cfg.p, cfg.q
     l = k + p
@@ -124,13 +159,7 @@ def main():
     g_avg = g_ms / max(g_cnt, 1)
     g_flops = 2.0 * l * m * n
     achieved = g_flops / (g_avg * 1e-3) / 1e12
-    traffic = None
-    pmc_path = os.path.join(ROOT, "profiles", "sketch_gemm_pmc.json")
-    if os.path.exists(pmc_path):
-        with open(pmc_path) as f:
-            pmc = json.load(f)
-        if pmc.get("gemm_source_sha") == source_hash(os.path.join(ROOT, "paper_1412_8447_amd", "csrc", "gemm.hip")):
-            traffic = pmc.get("hbm_bytes_per_launch")
+    traffic = read_traffic()
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": traffic,
                 "kernel": "sketch_gemm (FP32 MFMA 16x16x4)", "avg_launch_ms": round(g_avg, 4),

@@ -8,26 +8,41 @@
 //   mode 0:  G = L L^T  ->  L and X = L^{-1}
 //   mode 1:  lower-triangular L given (strided view)  ->  X = L^{-1}
 //
-// One workgroup of 512 threads, right-looking over 32-column panels. For a
-// panel with diagonal block D and rows below B:
-//   mode 0 only: one wave factors D in LDS, the rows below become B D^{-T},
-//                and the trailing lower triangle takes - B B^T;
-//   both modes:  D^{-1} (one wave, a column per lane), then the elimination
-//                applied to X: X_p <- D^{-1} X_p for the panel rows, and
-//                X_below <- X_below - B X_p.
-// Every inner operation is a block of independent multiply-adds over LDS
-// operands; the only sequential chains are the 32 steps inside a diagonal
-// block, each confined to a single wave.
+// One workgroup of 8 waves, right-looking over 32 x 32 tiles (T = ceil(c/32)
+// tile rows, padded with the identity). For panel p, with D_p = L_pp^{-1}:
+//   phase 2 (all waves, one tile each):
+//       L_rp = A_rp D_p^T                (mode 0; mode 1 reads L_rp)   r > p
+//       X_pc = D_p X_pc                  (X_pc accumulated so far)     c < p
+//       X_pp = D_p
+//   phase 3 (waves 1..7):
+//       A_rs -= L_rp L_sp^T              (mode 0 trailing update)      p < s <= r
+//       X_rc -= L_rp X_pc                                              r > p, c <= p
+//   phase 3 (wave 0, look-ahead): update A_{p+1,p+1}, factor it and invert
+//       its factor, so that D_{p+1} is ready when the barrier ends the phase.
+// Tile products run on the FP64 matrix cores (v_mfma_f64_16x16x4f64) with
+// operands from LDS (the panel column L_.p and the panel row X_p.); the
+// trailing tiles of A and X are accumulated in place in the output arrays
+// (L2-resident). The diagonal tile is factored by one wave with its rows in
+// registers (one row per lane, pivot columns broadcast with v_readlane) and
+// inverted with a column per lane.
+//
+// f64 16x16x4 operand layout: lane L holds A(L%16, L/16) and B(L/16, L%16);
+// result register t of lane L is C(L/16 + 4t, L%16).
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace idcur {
 namespace {
 
-constexpr int kCT = 512;
-constexpr int kNB = 32;
-constexpr int kMaxC = 256;
-constexpr int kLd = kNB + 1;   // padded row stride of the 32-wide LDS tiles
+constexpr int kCT = 512;             // 8 waves
+constexpr int kWaves = kCT / 64;
+constexpr int kTS = 32;              // tile edge
+constexpr int kTL = kTS + 1;         // LDS row stride of a tile (doubles)
+constexpr int kTile = kTS * kTL;     // doubles per LDS tile
+constexpr int kMaxT = 8;
+constexpr int kMaxC = kMaxT * kTS;
+
+typedef double d4 __attribute__((ext_vector_type(4)));
 
 struct CArgs {
   const double* G; int64_t gr, gc;   // mode 0: G(i,j) = G[i*gr + j*gc]; mode 1: the factor L
@@ -39,221 +54,361 @@ struct CArgs {
   int* status;
 };
 
-// sum_{t < 32, lo <= t <= hi} a[t*sa] * b[t*sb] with both operands read into
-// registers first (all 64 LDS reads in flight), masked terms selected to zero.
-__device__ __forceinline__ double dot32(const double* a, int sa, const double* b, int sb, int lo, int hi) {
-  double x[kNB], y[kNB];
-#pragma unroll
-  for (int t = 0; t < kNB; ++t) {
-    x[t] = a[t * sa];
-    y[t] = b[t * sb];
+// strided read-only view, padded with the identity outside [0, c)^2
+struct View {
+  const double* p;
+  int64_t rs, cs;
+  int c;
+  __device__ __forceinline__ double at(int i, int j) const {
+    const bool in = i < c && j < c;
+    const double v = p[(int64_t)min(i, c - 1) * rs + (int64_t)min(j, c - 1) * cs];
+    return in ? v : (i == j ? 1.0 : 0.0);
   }
-  double s = 0.0;
+};
+
+// LDS (dynamic): every helper addresses it through `sm` with an offset, so
+// that out-of-line helpers still compile to LDS instructions.
+extern __shared__ __align__(16) double sm[];
+constexpr int kPan = 0;                          // L(r, p), r = 1..kMaxT-1 at kPan + (r-1)*kTile
+constexpr int kXrow = kPan + (kMaxT - 1) * kTile;    // X(p, c), c = 0..kMaxT-2
+constexpr int kDbuf = kXrow + (kMaxT - 1) * kTile;   // D_p, double-buffered
+constexpr int kDg = kDbuf + 2 * kTile;               // diagonal tile being factored
+constexpr int kRinv = kDg + kTile;                   // reciprocals of its diagonal (32)
+constexpr int kOnehot = kRinv + kTS;                 // 64 doubles: e_32
+constexpr int kSmax = kOnehot + 64;                  // per-wave maxima (kWaves)
+constexpr int kLdsDoubles = kSmax + kWaves;
+
+struct Acc {
+  d4 v[2][2];
+};
+
+__device__ __forceinline__ void acc_zero(Acc& a) {
 #pragma unroll
-  for (int t = 0; t < kNB; ++t) s += (t >= lo && t <= hi) ? x[t] * y[t] : 0.0;
-  return s;
-}
-// same with the first operand already in registers
-__device__ __forceinline__ double dot32r(const double (&x)[kNB], const double* b, int sb, int lo, int hi) {
-  double y[kNB];
+  for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-  for (int t = 0; t < kNB; ++t) y[t] = b[t * sb];
-  double s = 0.0;
-#pragma unroll
-  for (int t = 0; t < kNB; ++t) s += (t >= lo && t <= hi) ? x[t] * y[t] : 0.0;
-  return s;
+    for (int bj = 0; bj < 2; ++bj) a.v[bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
 }
 
-// Element-wise copy with B independent loads in flight per thread: load(e)
-// must be safe for e = 0; store(e, v) is only called for e < total.
-template <int B, class LoadF, class StoreF>
-__device__ __forceinline__ void batched(int total, LoadF load, StoreF store) {
-  for (int e0 = 0; e0 < total; e0 += kCT * B) {
-    double v[B];
+// accumulator element (bi, bj, t) of lane L sits at tile row bi*16 + L/16 + 4t,
+// column bj*16 + L%16
+__device__ __forceinline__ void acc_load(Acc& a, const View& m, int i0, int j0) {
+  const int lane = threadIdx.x & 63, q = lane >> 4, r16 = lane & 15;
 #pragma unroll
-    for (int q = 0; q < B; ++q) {
-      const int e = e0 + q * kCT + (int)threadIdx.x;
-      v[q] = load(e < total ? e : 0);
-    }
+  for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-    for (int q = 0; q < B; ++q) {
-      const int e = e0 + q * kCT + (int)threadIdx.x;
-      if (e < total) store(e, v[q]);
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) a.v[bi][bj][t] = m.at(i0 + bi * 16 + q + 4 * t, j0 + bj * 16 + r16);
+}
+
+__device__ __forceinline__ void acc_store(const Acc& a, double* M, int64_t ld, int i0, int j0, int c, bool lower_only) {
+  const int lane = threadIdx.x & 63, q = lane >> 4, r16 = lane & 15;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int i = i0 + bi * 16 + q + 4 * t, j = j0 + bj * 16 + r16;
+        if (i < c && j < c && (!lower_only || j <= i)) M[(int64_t)i * ld + j] = a.v[bi][bj][t];
+      }
+}
+
+__device__ __forceinline__ void acc_to_lds(const Acc& a, int tile) {
+  const int lane = threadIdx.x & 63, q = lane >> 4, r16 = lane & 15;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) sm[tile + (bi * 16 + q + 4 * t) * kTL + bj * 16 + r16] = a.v[bi][bj][t];
+}
+
+// one wave copies the tile at (i0, j0) of the view into LDS
+__device__ __forceinline__ void tile_from_view(int tile, const View& m, int i0, int j0) {
+  const int lane = threadIdx.x & 63;
+  double v[kTS * kTS / 64];
+#pragma unroll
+  for (int t = 0; t < kTS * kTS / 64; ++t) {
+    const int e = lane + 64 * t;
+    v[t] = m.at(i0 + (e >> 5), j0 + (e & 31));
+  }
+#pragma unroll
+  for (int t = 0; t < kTS * kTS / 64; ++t) {
+    const int e = lane + 64 * t;
+    sm[tile + (e >> 5) * kTL + (e & 31)] = v[t];
+  }
+}
+
+// acc += sgn * A * B (NT = false: B[k][j]; NT = true: B given transposed, B[j][k])
+template <bool NT>
+__device__ __forceinline__ void tile_mma(Acc& acc, int A, int B, double sgn) {
+  const int lane = threadIdx.x & 63, q = lane >> 4, r16 = lane & 15;
+#pragma unroll
+  for (int k0 = 0; k0 < kTS; k0 += 4) {
+    const double a0 = sgn * sm[A + r16 * kTL + k0 + q];
+    const double a1 = sgn * sm[A + (16 + r16) * kTL + k0 + q];
+    const double b0 = NT ? sm[B + r16 * kTL + k0 + q] : sm[B + (k0 + q) * kTL + r16];
+    const double b1 = NT ? sm[B + (16 + r16) * kTL + k0 + q] : sm[B + (k0 + q) * kTL + 16 + r16];
+    acc.v[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc.v[0][0], 0, 0, 0);
+    acc.v[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc.v[0][1], 0, 0, 0);
+    acc.v[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc.v[1][0], 0, 0, 0);
+    acc.v[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc.v[1][1], 0, 0, 0);
+  }
+}
+
+// 1/sqrt(a) for a > 0: the hardware estimate refined by two Newton-Raphson
+// steps y <- y + y (1 - a y^2) / 2 (each step doubles the correct bits)
+__device__ __forceinline__ double rsqrt_nr(double a) {
+  double y = __builtin_amdgcn_rsq(a);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-a * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
+__device__ __forceinline__ double readlane_d(double x, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+  return __hiloint2double(hi, lo);
+}
+
+// ---- work items (out of line: each computes its own lane indexing, so the
+// compiler keeps none of it alive across the panel loop) ----------------------
+
+// phase 2, mode 0: L(r, p) = A(r, p) D_p^T into LDS and L; mode 1: L(r, p) into LDS
+__device__ __noinline__ void item_panel(View A, double* L, int64_t ldl, int r, int p, int D, bool m0) {
+  const int P = kPan + (r - 1) * kTile;
+  tile_from_view(P, A, r * kTS, p * kTS);
+  if (m0) {
+    Acc acc;
+    acc_zero(acc);
+    tile_mma<true>(acc, P, D, 1.0);
+    acc_to_lds(acc, P);
+    acc_store(acc, L, ldl, r * kTS, p * kTS, A.c, false);
+  }
+}
+
+// phase 2: X(p, p) = D_p
+__device__ __noinline__ void item_store_d(double* X, int64_t ldx, int p, int D, int c) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int t = 0; t < kTS * kTS / 64; ++t) {
+    const int e = lane + 64 * t;
+    const int i = p * kTS + (e >> 5), j = p * kTS + (e & 31);
+    if (i < c && j < c) X[(int64_t)i * ldx + j] = sm[D + (e >> 5) * kTL + (e & 31)];
+  }
+}
+
+// phase 2: X(p, cc) = D_p X(p, cc) into LDS and X
+__device__ __noinline__ void item_xrow(View XV, double* X, int64_t ldx, int p, int cc, int D) {
+  const int Xr = kXrow + cc * kTile;
+  tile_from_view(Xr, XV, p * kTS, cc * kTS);
+  Acc acc;
+  acc_zero(acc);
+  tile_mma<false>(acc, D, Xr, 1.0);
+  acc_to_lds(acc, Xr);
+  acc_store(acc, X, ldx, p * kTS, cc * kTS, XV.c, false);
+}
+
+// phase 3 for one of the waves 1..kWaves-1: its share of the tiles
+//   trailing (mode 0): A(r, s) -= L(r, p) L(s, p)^T, p+1 <= s <= r <= T-1,
+//                      without (p+1, p+1), which wave 0 takes
+//   X:                 X(r, cc) -= L(r, p) X(p, cc), r > p, cc <= p (X(p, p) = D_p)
+// The accumulator tile of the next item is loaded while the current one is
+// multiplied.
+__device__ __noinline__ void phase3_items(View A, double* L, int64_t ldl, View XV, double* X, int64_t ldx, int p,
+                                          int m, bool m0, int D, int w) {
+  const int ntr = m0 ? m * (m + 1) / 2 - 1 : 0;
+  const int n = ntr + m * (p + 1);
+  const int step = kWaves - 1;
+  struct Item {
+    int r, s;
+    bool tr;
+  };
+  auto decode = [&](int it) {
+    Item t;
+    if (it < ntr) {
+      int e = it + 1, s = p + 1, len = m;
+      while (e >= len) {
+        e -= len;
+        ++s;
+        --len;
+      }
+      t.r = s + e;
+      t.s = s;
+      t.tr = true;
+    } else {
+      const int j = it - ntr;
+      t.r = p + 1 + j / (p + 1);
+      t.s = j % (p + 1);
+      t.tr = false;
     }
+    return t;
+  };
+  int it = w;
+  if (it >= n) return;
+  Item cur = decode(it);
+  Acc acc;
+  acc_load(acc, cur.tr ? A : XV, cur.r * kTS, cur.s * kTS);
+  for (; it < n; it += step) {
+    Acc nxt;
+    Item ni = cur;
+    const bool more = it + step < n;
+    if (more) {
+      ni = decode(it + step);
+      acc_load(nxt, ni.tr ? A : XV, ni.r * kTS, ni.s * kTS);
+    }
+    if (cur.tr) {
+      tile_mma<true>(acc, kPan + (cur.r - 1) * kTile, kPan + (cur.s - 1) * kTile, -1.0);
+      acc_store(acc, L, ldl, cur.r * kTS, cur.s * kTS, A.c, cur.r == cur.s);
+    } else {
+      tile_mma<false>(acc, kPan + (cur.r - 1) * kTile, cur.s == p ? D : kXrow + cur.s * kTile, -1.0);
+      acc_store(acc, X, ldx, cur.r * kTS, cur.s * kTS, XV.c, false);
+    }
+    if (more) {
+      acc = nxt;
+      cur = ni;
+    }
+  }
+}
+
+// One wave: diagonal tile q (after the update by panel q-1, whose L(q, q-1)
+// sits in the panel buffer when upd is set). mode 0: Cholesky of the tile in
+// registers (one row per lane, pivot columns broadcast with v_readlane), rows
+// stored to L; mode 1: the tile of the given factor. Then dout <- L_qq^{-1},
+// a column per lane starting from the unit vector (zeros above the diagonal).
+// No step depends on a lane predicate, so the unrolled code keeps no per-lane
+// masks alive.
+__device__ __noinline__ void item_diag(View A, double* L, int64_t ldl, int q, bool upd, int dout, bool m0,
+                                       int* status) {
+  const int lane = threadIdx.x & 63, i = lane & 31;
+  const int q0 = q * kTS;
+  if (m0) {
+    Acc acc;
+    acc_load(acc, A, q0, q0);
+    if (upd) tile_mma<true>(acc, kPan + (q - 1) * kTile, kPan + (q - 1) * kTile, -1.0);
+    acc_to_lds(acc, kDg);
+  } else {
+    tile_from_view(kDg, A, q0, q0);
+  }
+  if (m0) {
+    double r[kTS];   // row i (entries above the diagonal are scratch)
+#pragma unroll
+    for (int j = 0; j < kTS; ++j) r[j] = sm[kDg + i * kTL + j];
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < kTS; ++k) {
+      double akk = readlane_d(r[k], k);
+      bad = bad || !(akk > 0.0);
+      akk = (akk > 0.0) ? akk : 1e-300;
+      const double inv = rsqrt_nr(akk);
+      // row k's own entry becomes akk / sqrt(akk), the pivot; rows above k
+      // (i < k) only ever change entries above their diagonal
+      const double lk = r[k] * inv;
+      r[k] = lk;
+#pragma unroll
+      for (int j = k + 1; j < kTS; ++j) r[j] = fma(-lk, readlane_d(r[k], j), r[j]);
+    }
+    if (bad && lane == 0) set_status(status, ST_NONFINITE);
+    if (lane < kTS) {
+#pragma unroll
+      for (int j = 0; j < kTS; ++j) sm[kDg + i * kTL + j] = r[j];
+      if (q0 + i < A.c) {
+#pragma unroll
+        for (int j = 0; j < kTS; ++j)
+          if (j <= i) L[(int64_t)(q0 + i) * ldl + q0 + j] = r[j];
+      }
+    }
+  }
+  if (lane < kTS) sm[kRinv + i] = 1.0 / sm[kDg + i * kTL + i];
+  double x[kTS];
+#pragma unroll
+  for (int ii = 0; ii < kTS; ++ii) x[ii] = sm[kOnehot + 32 + i - ii];
+#pragma unroll
+  for (int ii = 0; ii < kTS; ++ii) {
+    // four interleaved partial sums keep the dependent chain short
+    double s[4] = {x[ii], 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < ii; ++t) s[t & 3] = fma(-sm[kDg + ii * kTL + t], x[t], s[t & 3]);
+    x[ii] = ((s[0] + s[1]) + (s[2] + s[3])) * sm[kRinv + ii];
+  }
+  if (lane < kTS) {
+#pragma unroll
+    for (int ii = 0; ii < kTS; ++ii) sm[dout + ii * kTL + i] = x[ii];
   }
 }
 
 __global__ __launch_bounds__(kCT) void chol_inv_kernel(CArgs a) {
-  extern __shared__ __align__(16) double sm[];
-  double* D = sm;                          // kNB x kLd   diagonal block (factored)
-  double* Di = D + kNB * kLd;              // kNB x kLd   its inverse
-  double* Pb = Di + kNB * kLd;             // c_host x kLd rows below the block (the factor's panel)
-  double* Xp = Pb + (size_t)a.c_host * kLd;// kNB x (c_host+1) panel rows of X
-  __shared__ double smax[kCT / 64];
   const int c = a.c_dev ? min(*a.c_dev, a.c_host) : a.c_host;
-  const int ldxp = a.c_host + 1;
+  if (c <= 0) return;
+  const int T = (c + kTS - 1) / kTS;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const bool m0 = a.mode == 0;
   double* L = a.L;
   double* X = a.X;
+  if (tid < 64) sm[kOnehot + tid] = tid == 32 ? 1.0 : 0.0;
 
-  // ---- setup: L = lower(G) (+ shift), X = I --------------------------------
-  double sh = 0.0;
-  if (a.mode == 0 && a.shift_rel > 0.0) {
-    double mx = 0.0;
-    for (int i = tid; i < c; i += kCT) mx = fmax(mx, a.G[(int64_t)i * a.gr + (int64_t)i * a.gc]);
-    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-    if (lane == 0) smax[wv] = mx;
-    __syncthreads();
-    mx = 0.0;
-    for (int w = 0; w < kCT / 64; ++w) mx = fmax(mx, smax[w]);
-    sh = a.shift_rel * mx;
+  // ---- setup: L = lower(G) + shift (mode 0), X = 0 ---------------------------
+  if (m0) {
+    double sh = 0.0;
+    if (a.shift_rel > 0.0) {
+      double mx = 0.0;
+      for (int i = tid; i < c; i += kCT) mx = fmax(mx, a.G[(int64_t)i * a.gr + (int64_t)i * a.gc]);
+      for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+      if (lane == 0) sm[kSmax + wv] = mx;
+      __syncthreads();
+      mx = 0.0;
+      for (int w = 0; w < kWaves; ++w) mx = fmax(mx, sm[kSmax + w]);
+      sh = a.shift_rel * mx;
+    }
+    const int total = c * c;
+    for (int e0 = 0; e0 < total; e0 += kCT * 4) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = min(e0 + u * kCT + tid, total - 1);
+        v[u] = a.G[(int64_t)(e / c) * a.gr + (int64_t)(e % c) * a.gc];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * kCT + tid;
+        if (e < total) {
+          const int i = e / c, j = e % c;
+          L[(int64_t)i * a.ldl + j] = (j <= i) ? v[u] + (i == j ? sh : 0.0) : 0.0;
+        }
+      }
+    }
   }
-  if (a.mode == 0)
-    batched<8>(c * c,
-               [&](int e) { const int i = e / c, j = e % c; return a.G[(int64_t)i * a.gr + (int64_t)j * a.gc]; },
-               [&](int e, double v) {
-                 const int i = e / c, j = e % c;
-                 L[(int64_t)i * a.ldl + j] = (j <= i) ? v + (i == j ? sh : 0.0) : 0.0;
-               });
-  for (int e = tid; e < c * c; e += kCT) X[(int64_t)(e / c) * a.ldx + e % c] = (e / c == e % c) ? 1.0 : 0.0;
+  for (int e = tid; e < c * c; e += kCT) X[(int64_t)(e / c) * a.ldx + e % c] = 0.0;
   __syncthreads();
-  // the factor being eliminated: L (mode 0, updated in place) or the input view
-  auto fel = [&](int i, int j) -> double {
-    return a.mode == 0 ? L[(int64_t)i * a.ldl + j] : a.G[(int64_t)i * a.gr + (int64_t)j * a.gc];
-  };
 
-  for (int p0 = 0; p0 < c; p0 += kNB) {
-    const int nb = min(kNB, c - p0);
-    const int p1 = p0 + nb;
-    const int nr = c - p1;
-    // ---- (a) diagonal block to LDS -----------------------------------------
-    batched<2>(kNB * kNB,
-               [&](int e) { const int i = min(e / kNB, nb - 1), j = min(e % kNB, nb - 1); return fel(p0 + i, p0 + j); },
-               [&](int e, double v) {
-                 const int i = e / kNB, j = e % kNB;
-                 D[i * kLd + j] = (i < nb && j < nb && j <= i) ? v : (i == j ? 1.0 : 0.0);
-               });
-    __syncthreads();
-    // ---- (b) mode 0: factor D in place (wave 0, row `lane`) -------------------
-    // (loads are unconditional and results selected, so that the LDS reads of
-    // one step are issued together instead of one masked branch per term)
-    if (a.mode == 0 && wv == 0 && lane < kNB) {
-      for (int j = 0; j < nb; ++j) {
-        if (lane == j) {
-          double d = D[j * kLd + j];
-          if (!(d > 0.0)) {
-            set_status(a.status, ST_NONFINITE);
-            d = 1e-300;
-          }
-          D[j * kLd + j] = sqrt(d);
-        }
-        const double djj = D[j * kLd + j];
-        const bool below = lane > j && lane < nb;
-        const double lraw = D[lane * kLd + j];
-        const double lij = below ? lraw / djj : 0.0;
-        if (below) D[lane * kLd + j] = lij;
-        double dk[kNB], cur[kNB];
-#pragma unroll
-        for (int k = 1; k < kNB; ++k) {
-          dk[k] = D[k * kLd + j];
-          cur[k] = D[lane * kLd + k];
-        }
-#pragma unroll
-        for (int k = 1; k < kNB; ++k)
-          D[lane * kLd + k] = (k > j && k <= lane && below) ? cur[k] - lij * dk[k] : cur[k];
-      }
-    }
-    __syncthreads();
-    // ---- (c) Di = D^{-1} (wave 0, column `lane`) ------------------------------
-    if (wv == 0 && lane < kNB) {
-      const int j = lane;
-      for (int i = 0; i < kNB; ++i) {
-        double v;
-        if (i < j) v = 0.0;
-        else if (i == j) v = 1.0 / D[i * kLd + i];
-        else {
-          const double s = dot32(D + i * kLd, 1, Di + j, kLd, j, i - 1);
-          v = -s / D[i * kLd + i];
-        }
-        Di[i * kLd + j] = v;
-      }
-    }
-    __syncthreads();
-    if (a.mode == 0) {
-      for (int e = tid; e < nb * kNB; e += kCT) {
-        const int i = e / kNB, j = e % kNB;
-        if (j <= i) L[(int64_t)(p0 + i) * a.ldl + p0 + j] = D[i * kLd + j];
-      }
-    }
-    // ---- (d) rows below: Pb = B (mode 1) or B D^{-T} (mode 0) ----------------
-    // stage B into Pb
-    batched<8>(nr * kNB,
-               [&](int e) { return fel(p1 + e / kNB, p0 + min(e % kNB, nb - 1)); },
-               [&](int e, double v) { Pb[(e / kNB) * kLd + e % kNB] = (e % kNB < nb) ? v : 0.0; });
-    __syncthreads();
-    if (a.mode == 0) {
-      // out(r, j) = sum_{t <= j} B(r, t) Di(j, t), in place along row r with j
-      // descending (out(r, j) only reads entries t <= j, still unchanged)
-      for (int r = tid; r < nr; r += kCT) {
-        double row[kNB];
-#pragma unroll
-        for (int t = 0; t < kNB; ++t) row[t] = Pb[r * kLd + t];
-        for (int j = nb - 1; j >= 0; --j) {
-          const double s = dot32r(row, Di + j * kLd, 1, 0, j);
-          Pb[r * kLd + j] = s;
-          L[(int64_t)(p1 + r) * a.ldl + p0 + j] = s;
-        }
+  // the matrix being factored (mode 0: L, updated in place) or the given factor
+  const View A = m0 ? View{L, a.ldl, 1, c} : View{a.G, a.gr, a.gc, c};
+  const View XV{X, a.ldx, 1, c};
+
+  // p = -1 only factors the first diagonal tile
+  for (int p = -1; p < T; ++p) {
+    const int m = T - 1 - p;   // tile rows below the panel
+    const int D = kDbuf + (p & 1) * kTile;
+    if (p >= 0) {
+      // ---- phase 2 --------------------------------------------------------------
+      for (int it = wv; it < T; it += kWaves) {
+        if (it < m) item_panel(A, L, a.ldl, p + 1 + it, p, D, m0);
+        else if (it == m) item_store_d(X, a.ldx, p, D, c);
+        else item_xrow(XV, X, a.ldx, p, it - m - 1, D);
       }
       __syncthreads();
-      // trailing lower triangle: L(i, l) -= sum_t Pb(i, t) Pb(l, t), p1 <= l <= i
-      const int64_t ntri = (int64_t)nr * (nr + 1) / 2;
-      for (int64_t e0 = 0; e0 < ntri; e0 += (int64_t)kCT * 4) {
-        int ii[4], ll[4];
-        double cur[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int64_t e = e0 + (int64_t)q * kCT + tid;
-          const int64_t ec = e < ntri ? e : 0;
-          int i = (int)((sqrt(8.0 * (double)ec + 1.0) - 1.0) * 0.5);
-          while ((int64_t)i * (i + 1) / 2 > ec) --i;
-          while ((int64_t)(i + 1) * (i + 2) / 2 <= ec) ++i;
-          ii[q] = i;
-          ll[q] = (int)(ec - (int64_t)i * (i + 1) / 2);
-          cur[q] = L[(int64_t)(p1 + ii[q]) * a.ldl + p1 + ll[q]];
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int64_t e = e0 + (int64_t)q * kCT + tid;
-          const double s = dot32(Pb + ii[q] * kLd, 1, Pb + ll[q] * kLd, 1, 0, kNB - 1);
-          if (e < ntri) L[(int64_t)(p1 + ii[q]) * a.ldl + p1 + ll[q]] = cur[q] - s;
-        }
-      }
+      if (m == 0) break;
     }
-    __syncthreads();
-    // ---- (e) elimination applied to X ----------------------------------------
-    // stage X[p0:p1, 0:p1] (rows not yet final) into Xp
-    batched<8>(nb * p1, [&](int e) { return X[(int64_t)(p0 + e / p1) * a.ldx + e % p1]; },
-               [&](int e, double v) { Xp[(e / p1) * ldxp + e % p1] = v; });
-    __syncthreads();
-    // Xp <- Di Xp, in place down each column with rows descending (row i only
-    // reads rows t <= i, still unchanged)
-    for (int col = tid; col < p1; col += kCT) {
-      double xc[kNB];
-#pragma unroll
-      for (int t = 0; t < kNB; ++t) xc[t] = Xp[t * ldxp + col];
-      for (int i = nb - 1; i >= 0; --i) {
-        const double s = dot32r(xc, Di + i * kLd, 1, 0, i);
-        Xp[i * ldxp + col] = s;
-        X[(int64_t)(p0 + i) * a.ldx + col] = s;
-      }
+    // ---- phase 3 ----------------------------------------------------------------
+    if (wv == 0) {
+      item_diag(A, L, a.ldl, p + 1, p >= 0, kDbuf + ((p + 1) & 1) * kTile, m0, a.status);
+    } else if (p >= 0) {
+      phase3_items(A, L, a.ldl, XV, X, a.ldx, p, m, m0, D, wv - 1);
     }
-    __syncthreads();
-    // rows below: X[p1+r, col] -= sum_t Pb(r, t) Xp(t, col), col < p1
-    batched<8>(nr * p1, [&](int e) { return X[(int64_t)(p1 + e / p1) * a.ldx + e % p1]; },
-               [&](int e, double v) {
-                 const int r = e / p1, col = e % p1;
-                 X[(int64_t)(p1 + r) * a.ldx + col] = v - dot32(Pb + r * kLd, 1, Xp + col, ldxp, 0, kNB - 1);
-               });
     __syncthreads();
   }
 }
@@ -261,13 +416,15 @@ __global__ __launch_bounds__(kCT) void chol_inv_kernel(CArgs a) {
 }  // namespace
 
 size_t chol_inv_lds_bytes(int c_host) {
-  return ((size_t)2 * kNB * kLd + (size_t)c_host * kLd + (size_t)kNB * (c_host + 1)) * sizeof(double);
+  (void)c_host;
+  return (size_t)kLdsDoubles * sizeof(double);
 }
 
 hipError_t chol_inv_launch(int mode, const double* G, int64_t gr, int64_t gc, int c_host, const int* c_dev, double* L,
                            int64_t ldl, double* X, int64_t ldx, double shift_rel, int* status, hipStream_t stream) {
   if (c_host <= 0) return hipSuccess;
   if (c_host > kMaxC) return hipErrorInvalidValue;
+  if (mode == 0 && !L) return hipErrorInvalidValue;
   CArgs a{};
   a.G = G; a.gr = gr; a.gc = gc; a.c_host = c_host; a.c_dev = c_dev;
   a.L = L; a.ldl = ldl; a.X = X; a.ldx = ldx; a.shift_rel = shift_rel; a.mode = mode; a.status = status;
