@@ -21,6 +21,8 @@
 //  * Pivots: largest norm, ties to the smallest column index. Householder sign:
 //    alpha = -sgn(x0)|x|. Output S is written by original column index; J lists
 //    the pivots, then the remaining columns in increasing order.
+#include <cstdlib>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -427,6 +429,26 @@ static size_t cpqr_lds_bytes(int cols_per_wg, int lpad, int kmax, bool in_lds) {
 
 CpqrPlan cpqr_plan(int dtype_size, int l, int n, int kmax, int num_cus) {
   CpqrPlan p{};
+  p.reg_cfg = -1;
+  const char* force_slab = getenv("IDCUR_CPQR_SLAB");
+  if (!(force_slab && force_slab[0] == '1')) {
+    int G = 0, cpw = 0;
+    const int cfg = cpqr_reg_pick(dtype_size, l, n, num_cus, &G, &cpw);
+    if (cfg >= 0) {
+      p.reg_cfg = cfg;
+      p.G = G;
+      p.cols_per_wg = cpw;
+      p.lpad = (int)round_up(std::max(l, 1), 4);
+      p.lanes_per_col = 0;
+      p.in_lds = true;
+      p.lds_bytes = cpqr_reg_lds_bytes(cfg, kmax, cpw, dtype_size);
+      p.rec_bytes = cpqr_reg_rec_bytes(p.G);
+      p.cvals_bytes = cpqr_reg_cvals_bytes(cfg, p.G, dtype_size);
+      p.fin_bytes = (size_t)p.G * 16 * sizeof(int);
+      p.gslab_bytes = 0;
+      return p;
+    }
+  }
   p.G = (int)std::max(1, std::min(num_cus, n));
   p.cols_per_wg = (int)ceil_div(n, p.G);
   p.lpad = (int)round_up(std::max(l, 1), 4) + (dtype_size == 4 ? 1 : 0);
@@ -453,6 +475,12 @@ hipError_t cpqr_launch(int dtype, const CpqrPlan& p, CpqrArgs a, hipStream_t str
   a.lpad = p.lpad;
   a.cols_per_wg = p.cols_per_wg;
   a.lanes_per_col = p.lanes_per_col;
+  if (p.reg_cfg >= 0) {
+    // exchanged words carry the publish index: clear what an earlier call left
+    hipError_t e = zero_launch(a.cvals, p.cvals_bytes, stream);
+    if (e != hipSuccess) return e;
+    return cpqr_reg_launch(dtype, p.reg_cfg, p.G, a, p.lds_bytes, stream);
+  }
   void* args[] = {&a};
   const void* fn;
   if (dtype == 0) fn = p.in_lds ? (const void*)cpqr_kernel<double, true> : (const void*)cpqr_kernel<double, false>;

@@ -44,6 +44,7 @@ struct CpqrPlan {
   int cols_per_wg;
   int lpad;
   int lanes_per_col;
+  int reg_cfg;        // >= 0: register-slab kernel configuration; -1: LDS/global slab kernel
   bool in_lds;
   size_t lds_bytes;
   size_t rec_bytes, cvals_bytes, fin_bytes, gslab_bytes;
@@ -51,6 +52,13 @@ struct CpqrPlan {
 
 CpqrPlan cpqr_plan(int dtype_size, int l, int n, int kmax, int num_cus);
 hipError_t cpqr_launch(int dtype, const CpqrPlan& p, CpqrArgs a, hipStream_t stream);
+// register-slab variant (cpqr_reg.hip): configuration index or -1 when the
+// shape does not fit; sets the grid size and the columns per workgroup
+int cpqr_reg_pick(int dtype_size, int l, int n, int num_cus, int* G, int* cols_per_wg);
+size_t cpqr_reg_lds_bytes(int cfg, int kmax_host, int cols_per_wg, int dtype_size);
+size_t cpqr_reg_rec_bytes(int G);
+size_t cpqr_reg_cvals_bytes(int cfg, int G, int dtype_size);
+hipError_t cpqr_reg_launch(int dtype, int cfg, int G, CpqrArgs a, size_t lds_bytes, hipStream_t stream);
 
 // ---------------------------------------------------------------------------
 // MFMA GEMM (gemm.hip): C (M x N) = A (M x K) * B (K x N)
