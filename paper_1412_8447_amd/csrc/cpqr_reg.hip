@@ -166,6 +166,7 @@ __global__ __launch_bounds__(kRT) void cpqr_reg_kernel(CpqrArgs a) {
   // wave is still reading
   __shared__ double p_v[kRW], p_s[kRW], x_v[kRW], x_s[kRW];
   __shared__ int p_i[kRW], p_o[kRW], x_i[kRW], x_o[kRW], x_t[kRW];
+  __shared__ int s_vfail;   // a thread gave up waiting for the winning column
   int* win = reinterpret_cast<int*>(rsm);   // kmax_host pivots
   int* act_s = win + a.kmax_host;           // cols_per_wg flags
   // the winning column by row (R * RPL entries; rows outside [j, l) unused)
@@ -221,6 +222,7 @@ __global__ __launch_bounds__(kRT) void cpqr_reg_kernel(CpqrArgs a) {
     for (int u = 0; u < NC; ++u) nu2[u] = gsum<R>(ss[u]);
   }
 
+  if (tid == 0) s_vfail = 0;
   const double eps = (sizeof(T) == 4) ? 5.9604644775390625e-08 : 1.1102230246251565e-16;
   const double tol3z = sqrt(eps);
   double y0fro2 = 0.0, nu0sq = 0.0;
@@ -262,6 +264,7 @@ __global__ __launch_bounds__(kRT) void cpqr_reg_kernel(CpqrArgs a) {
       p_s[wv] = ssq;
     }
     __syncthreads();
+    if (tid == 0) s_vfail = 0;   // read by every thread before this barrier, set only after the next one
     Cand b{p_v[0], p_i[0], p_o[0]};
     double tot = p_s[0];
 #pragma unroll
@@ -372,7 +375,9 @@ __global__ __launch_bounds__(kRT) void cpqr_reg_kernel(CpqrArgs a) {
         vbuf[i] = val;
       }
       // every thread either has its words or has given up; agree on the outcome
-      if (__syncthreads_or(ok ? 0 : 1)) stop = ST_TIMEOUT;
+      if (!ok) s_vfail = 1;
+      __syncthreads();
+      if (s_vfail) stop = ST_TIMEOUT;
 #pragma unroll
       for (int t = 0; t < RPL; ++t) {
         const int row = rgi + R * t;
@@ -576,7 +581,7 @@ struct RegCfg {
 };
 // searched in order: the first entry that covers l, fits the register budget
 // and needs at most one workgroup per compute unit is taken
-constexpr RegCfg kRegCfgs[] = {{16, 16, 1}, {16, 16, 2}, {16, 16, 4}, {16, 16, 8},
+constexpr RegCfg kRegCfgs[] = {{16, 16, 1}, {16, 16, 2}, {16, 16, 3}, {16, 16, 4}, {16, 16, 5}, {16, 16, 6}, {16, 16, 8},
                                {64, 16, 1}, {64, 16, 2}, {64, 16, 4}, {64, 16, 8},
                                {64, 32, 1}, {64, 32, 2}, {64, 32, 4}};
 constexpr int kNumRegCfgs = sizeof(kRegCfgs) / sizeof(kRegCfgs[0]);
