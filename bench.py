@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--seed", type=int, default=20260)
+    ap.add_argument("--input-cache", default=None,
+                    help="load A from this file when it exists, else generate it and save it there")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -104,10 +106,17 @@ def main():
     l = k + p
 
     t0 = time.time()
-    log(f"generating A {m}x{n} on the GPU")
-    A64 = synth.lowrank_torch(m, n, cfg.spectrum(), seed=args.seed, device=dev)
-    A = A64.to(torch.float32).contiguous()
-    del A64
+    if args.input_cache and os.path.exists(args.input_cache):
+        log(f"loading A from {args.input_cache}")
+        A = torch.load(args.input_cache, weights_only=True).to(dev).contiguous()
+        assert A.shape == (m, n) and A.dtype == torch.float32
+    else:
+        log(f"generating A {m}x{n} on the GPU")
+        A64 = synth.lowrank_torch(m, n, cfg.spectrum(), seed=args.seed, device=dev)
+        A = A64.to(torch.float32).contiguous()
+        del A64
+        if args.input_cache:
+            torch.save(A.cpu(), args.input_cache)
     torch.cuda.synchronize()
     log(f"A ready in {time.time() - t0:.1f}s")
 

@@ -18,9 +18,6 @@ Layout of the oracle:
 * ``errors``   -- the reported error measures (Frobenius; spectral at small sizes).
 * ``philox``   -- Philox4x32-10 (Salmon et al., SC'11) and a Box-Muller transform,
                   the counter-based generator used for the sketch matrix.
-* ``adjoint``  -- gradient of the column-ID reconstruction loss with the skeleton
-                  frozen (least-squares adjoint through T).
-* ``batched``  -- tolerance-mode IDs of many independent blocks.
 
 Every function here is pinned by a ``-m "not gpu"`` test against something other
 than itself (brute force, closed forms, library routines, identities from the
