@@ -181,6 +181,29 @@ idcur_status idcur_cur_error(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n
                              const void* C, int64_t ldc, const void* U, int64_t ldu, const void* R, int64_t ldr,
                              const int32_t* k_out, int32_t kcap, void* ws, size_t ws_bytes, double* out);
 
+/* Gradient of the column-ID reconstruction loss with the skeleton frozen
+ * (the column ID of Section 2.3 / Algorithm 1, sketched as in Section 5.1):
+ *   Y = Omega A (omega != NULL) or Y = A (omega == NULL),
+ *   T = argmin_X |Y(:,J1) X - Y(:,J2)|_F  (= S11^{-1} S12, Section 4.1),
+ *   L = |A(:,J2) - A(:,J1) T|_F^2,        J1 = J[0..k-1], J2 = J[k..n-1].
+ * Writes dA = scale * dL/dA (m x n, row-major, ld ldda >= n; overwritten) with J
+ * and Omega held fixed: the explicit terms 2E and -2 E T^T plus the path through
+ * T (the derivative of the least-squares solution, M = (Y1^T Y1)^{-1} Tbar with
+ * Tbar = -2 A(:,J1)^T E; Y1^T Y1 factored in FP64 on the device).
+ *   A      m x n (ld lda), dtype.
+ *   omega  l x m row-major (ld m), same dtype, or NULL; k <= l <= m.
+ *   J      device int32[n], a permutation (e.g. from idcur_id_col); values out of
+ *          range are reported as IDCUR_EINVAL by idcur_sync_status.
+ *   k      rank, 0 < k < min(m, n), k <= 256 (host value).
+ *   T      k x (n-k) (ld ldt >= n-k), dtype: the interpolation matrix of that ID.
+ * Workspace from idcur_id_col_backward_workspace_bytes(dtype, m, n, k, l,
+ * sketched = omega != NULL). */
+idcur_status idcur_id_col_backward_workspace_bytes(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, int32_t k,
+                                                   int32_t l, int32_t sketched, size_t* bytes /* host out */);
+idcur_status idcur_id_col_backward(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+                                   const void* omega, int32_t l, const int32_t* J, int32_t k, const void* T,
+                                   int64_t ldt, double scale, void* dA, int64_t ldda, void* ws, size_t ws_bytes);
+
 /* The Gaussian sketch matrix alone (Section 5.1: i.i.d. N(0,1) entries): writes
  * Omega(r, i), r < rows, i < cols, to out + r*ldo + i. Entry (r, i) is defined by
  * the Philox4x32-10 counter (f/4 mod 2^32, f/4 div 2^32, stream, 0), f = r*cols + i,

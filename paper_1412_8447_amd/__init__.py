@@ -87,9 +87,13 @@ _lib.idcur_error_workspace_bytes.argtypes = [_vp, _i32, _i32, _i64, _i64, _i32, 
 _lib.idcur_id_error.argtypes = [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _i32, _vp, _sz, _vp]
 _lib.idcur_cur_error.argtypes = [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i32, _vp,
                                  _sz, _vp]
+_lib.idcur_id_col_backward_workspace_bytes.argtypes = [_vp, _i32, _i64, _i64, _i32, _i32, _i32, ctypes.POINTER(_sz)]
+_lib.idcur_id_col_backward.argtypes = [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _i32, _vp, _i32, _vp, _i64,
+                                       ctypes.c_double, _vp, _i64, _vp, _sz]
 _lib.idcur_timing_enable.argtypes = [_vp, _i32]
 _lib.idcur_timing_read.argtypes = [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32)]
-for _f in ("idcur_error_workspace_bytes", "idcur_id_error", "idcur_cur_error",
+for _f in ("idcur_error_workspace_bytes", "idcur_id_error", "idcur_cur_error", "idcur_id_col_backward_workspace_bytes",
+           "idcur_id_col_backward",
            "idcur_timing_enable", "idcur_timing_read", "idcur_create", "idcur_set_stream", "idcur_destroy", "idcur_sync_status", "idcur_workspace_bytes",
            "idcur_id_col", "idcur_id_row", "idcur_id_two_sided", "idcur_cur", "idcur_gaussian"):
     getattr(_lib, _f).restype = ctypes.c_int
@@ -97,9 +101,9 @@ for _f in ("idcur_error_workspace_bytes", "idcur_id_error", "idcur_cur_error",
 EXPORTED = ("idcur_opts_default", "idcur_create", "idcur_set_stream", "idcur_destroy", "idcur_last_error",
             "idcur_sync_status", "idcur_workspace_bytes", "idcur_id_col", "idcur_id_row", "idcur_id_two_sided",
             "idcur_cur", "idcur_gaussian", "idcur_timing_enable", "idcur_timing_read", "idcur_error_workspace_bytes",
-            "idcur_id_error", "idcur_cur_error")
+            "idcur_id_error", "idcur_cur_error", "idcur_id_col_backward_workspace_bytes", "idcur_id_col_backward")
 
-STAGES = ("omega", "sketch_gemm", "orth", "cpqr", "trsm", "gather", "row_id", "u_solve", "error")
+STAGES = ("omega", "sketch_gemm", "orth", "cpqr", "trsm", "gather", "row_id", "u_solve", "error", "backward")
 
 
 class IDCurError(RuntimeError):
@@ -368,3 +372,59 @@ def cur_error(A: torch.Tensor, C: torch.Tensor, U: torch.Tensor, R: torch.Tensor
                                    C.stride(0), U.data_ptr(), U.stride(0), R.data_ptr(), R.stride(0), kout.data_ptr(),
                                    kcap, ws.data_ptr(), ws.numel(), out.data_ptr()))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Gradient of the column-ID reconstruction loss (skeleton frozen)
+# ---------------------------------------------------------------------------
+def id_col_backward(A: torch.Tensor, J: torch.Tensor, T: torch.Tensor, k: int, *, omega: Optional[torch.Tensor] = None,
+                    scale: float = 1.0, out: Optional[torch.Tensor] = None, workspace=None) -> torch.Tensor:
+    """scale * dL/dA for L = |A(:,J2) - A(:,J1) T|_F^2 with J and Omega fixed and T
+    the least-squares interpolation from Y = Omega A (or Y = A when omega is None)."""
+    h = _prep(A, omega)
+    m, n = A.shape
+    l = int(omega.shape[0]) if omega is not None else 0
+    nb = ctypes.c_size_t(0)
+    _check(h, _lib.idcur_id_col_backward_workspace_bytes(h, _dtype_code(A), m, n, int(k), l,
+                                                         1 if omega is not None else 0, ctypes.byref(nb)))
+    if workspace is None or workspace.numel() < nb.value:
+        workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=A.device)
+    if out is None:
+        out = torch.empty(m, n, dtype=A.dtype, device=A.device)
+    if J.dtype != torch.int32 or not J.is_contiguous() or T.stride(1) != 1:
+        raise IDCurError(EINVAL, "J must be contiguous int32 and T row-major")
+    _check(h, _lib.idcur_id_col_backward(h, _dtype_code(A), m, n, A.data_ptr(), A.stride(0),
+                                         omega.data_ptr() if omega is not None else None, l, J.data_ptr(), int(k),
+                                         T.data_ptr(), T.stride(0), float(scale), out.data_ptr(), out.stride(0),
+                                         workspace.data_ptr(), workspace.numel()))
+    return out
+
+
+class IDReconLoss(torch.autograd.Function):
+    """L(A) = |A(:,J2) - A(:,J1) T|_F^2 of the rank-k column ID of A (T from the
+    sketch Y = Omega A when omega is given, one pass, no power steps). The
+    skeleton J chosen in the forward pass is frozen in the backward pass."""
+
+    @staticmethod
+    def forward(ctx, A, k, omega=None):
+        p = int(omega.shape[0]) - int(k) if omega is not None else -1
+        r = id_col(A, int(k), p=p, q=0, omega=omega)
+        if r.k != int(k):
+            raise IDCurError(EINVAL, f"rank deficiency: the column ID stopped at {r.k} < k")
+        Tfull = r.T.as_strided((r.k, A.shape[1] - r.k), (r.T.stride(0), 1))
+        err = id_error(A, r.J, Tfull, r.kout, r.k)
+        ctx.save_for_backward(A, r.J, Tfull, omega if omega is not None else torch.empty(0, device=A.device))
+        ctx.k = r.k
+        ctx.sketched = omega is not None
+        return err[0].clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        A, J, T, omega = ctx.saved_tensors
+        dA = id_col_backward(A, J, T, ctx.k, omega=omega if ctx.sketched else None, scale=float(g))
+        return dA, None, None
+
+
+def recon_loss(A: torch.Tensor, k: int, omega: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Differentiable column-ID reconstruction loss (see IDReconLoss)."""
+    return IDReconLoss.apply(A, k, omega)

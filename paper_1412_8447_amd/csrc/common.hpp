@@ -11,6 +11,7 @@ enum : int {
   ST_RANKCAP = 1,
   ST_NONFINITE = 2,
   ST_TIMEOUT = 4,
+  ST_BADINDEX = 8,   // an index array held a value out of range (clamped)
 };
 
 // Spin limit of every grid-wide wait (polls, each followed by s_sleep 1).

@@ -57,14 +57,15 @@ hipError_t gemm_resid_launch(int x_type, int64_t M, int64_t N, int64_t K, const 
   k.vec_a = 0; k.vec_b = ((uintptr_t)W % 32 == 0) && (ldw % 4 == 0);
   k.X = X; k.ldx = ldx; k.x_type = x_type; k.rpart = part;
   k.k_dev = k_dev;
-  dim3 grid((unsigned)ceil_div(M, BM), (unsigned)ceil_div(N, 256), 1);
+  k.gx = (int)ceil_div(M, BM); k.gy = (int)ceil_div(N, 256); k.gz = 1;
+  dim3 grid(xcd_grid(k));
   if (c_type == 1)
     hipLaunchKernelGGL((gemm_kernel<float, double, double, 16, true, true, true>), grid, dim3(256), 0, stream, k);
   else
     hipLaunchKernelGGL((gemm_kernel<double, double, double, 16, true, true, true>), grid, dim3(256), 0, stream, k);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(sum_partials, dim3(1), dim3(256), 0, stream, part, (int64_t)grid.x * grid.y, out);
+  hipLaunchKernelGGL(sum_partials, dim3(1), dim3(256), 0, stream, part, (int64_t)k.gx * k.gy, out);
   return hipGetLastError();
 }
 
@@ -105,7 +106,8 @@ hipError_t gemm_launch(const GemmDesc& d, void* part, hipStream_t stream, hipEve
   };
   k.vec_a = aligned(d.A, akc ? d.sam : d.sak, ta_);
   k.vec_b = aligned(d.B, bnc ? d.sbk : d.sbn, tb_);
-  dim3 grid((unsigned)ceil_div(d.M, BM), (unsigned)ceil_div(d.N, bn), (unsigned)splitk);
+  k.gx = (int)ceil_div(d.M, BM); k.gy = (int)ceil_div(d.N, bn); k.gz = splitk;
+  dim3 grid(xcd_grid(k));
   hipError_t e;
   if (ev0) (void)hipEventRecord(ev0, stream);
   const int ta = d.a_type >= 0 ? d.a_type : d.in_type, tb = d.b_type >= 0 ? d.b_type : d.in_type;

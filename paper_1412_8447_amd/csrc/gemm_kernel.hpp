@@ -44,7 +44,17 @@ struct KArgs {
   // residual mode: accumulate sum (X - A*B)^2 over the tile instead of storing
   const void* X; int64_t ldx; int x_type; double* rpart;
   const int* k_dev;            // optional device bound on K
+  int gx, gy, gz;              // tile grid: row stripes, column tiles, K splits
 };
+
+// Tiles are numbered t = x + gx*(y + gy*z) (z = K split). The launch is 1-D with
+// 8*ceil(W/8) workgroups, and workgroup `lin` takes tile (lin % 8)*ceil(W/8) +
+// lin / 8. Workgroups are handed to the 8 XCDs round-robin by `lin`, so each XCD
+// gets one contiguous range of tiles: the tiles of one K split, whose slice of
+// the thin operand then stays in that XCD's L2 instead of being re-read from the
+// Infinity Cache by every XCD.
+__host__ __device__ inline int64_t tiles_total(const KArgs& p) { return (int64_t)p.gx * p.gy * p.gz; }
+__host__ inline unsigned xcd_grid(const KArgs& p) { return (unsigned)(8 * ((tiles_total(p) + 7) / 8)); }
 
 template <typename T> struct V4;
 template <> struct V4<float> { using type = float4; };
@@ -71,16 +81,20 @@ __global__ __launch_bounds__(256) void gemm_kernel(KArgs p) {
   __shared__ TAcc Bs[2][BK * SB];
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t W = tiles_total(p), per = (W + 7) / 8;
+  const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (tile >= W) return;
+  const int bx = (int)(tile % p.gx), by = (int)((tile / p.gx) % p.gy), bz = (int)(tile / ((int64_t)p.gx * p.gy));
   const int64_t Mb = p.m_dev ? min((int64_t)*p.m_dev, p.M) : p.M;
   const int64_t Nb = p.n_dev ? min((int64_t)*p.n_dev, p.N) : p.N;
-  const int64_t m0 = (int64_t)blockIdx.x * BM;
-  const int64_t n0 = (int64_t)blockIdx.y * BN;
+  const int64_t m0 = (int64_t)bx * BM;
+  const int64_t n0 = (int64_t)by * BN;
   if (m0 >= Mb || n0 >= Nb) {
-    if (RESID && threadIdx.x == 0) p.rpart[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = 0.0;
+    if (RESID && threadIdx.x == 0) p.rpart[(int64_t)by * p.gx + bx] = 0.0;
     return;
   }
   const int64_t Kb = p.k_dev ? min((int64_t)*p.k_dev, p.K) : p.K;
-  const int64_t kb = (int64_t)blockIdx.z * p.kps;
+  const int64_t kb = (int64_t)bz * p.kps;
   const int64_t ke = min(Kb, kb + p.kps);
   const TA* A = static_cast<const TA*>(p.A);
   const TB* B = static_cast<const TB*>(p.B);
@@ -91,7 +105,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(KArgs p) {
   auto gload = [&](int64_t k0) {
     // A tile: BM x BK
     if (A_KC) {
-      const int row = tid >> 2, kq = (tid & 3) * 4;
+      // a wave takes one k-quad of 64 rows: its transposing LDS stores below
+      // then hit 64 consecutive words (no bank conflicts)
+      const int row = tid & 63, kq = (tid >> 6) * 4;
       const int64_t gi = m0 + row, gk = k0 + kq;
       const int nv = (gi < Mb) ? (int)max((int64_t)0, min((int64_t)4, ke - gk)) : 0;
       load4(A, gi * p.sam + gk, nv, p.vec_a, ra);
@@ -124,7 +140,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(KArgs p) {
     TAcc* as = As[buf];
     TAcc* bs = Bs[buf];
     if (A_KC) {
-      const int row = tid >> 2, kq = (tid & 3) * 4;
+      const int row = tid & 63, kq = (tid >> 6) * 4;
 #pragma unroll
       for (int e = 0; e < 4; ++e) as[(kq + e) * SA + row] = (TAcc)ra[e];
     } else {
@@ -200,7 +216,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(KArgs p) {
     s = wave_sum(s);
     if (lane == 0) wsum[wv] = s;
     __syncthreads();
-    if (tid == 0) p.rpart[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+    if (tid == 0) p.rpart[(int64_t)by * p.gx + bx] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
     return;
   }
   // epilogue
@@ -224,7 +240,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(KArgs p) {
             *C = p.alpha * (double)v + o;
           }
         } else {
-          TAcc* P = static_cast<TAcc*>(p.out) + ((int64_t)blockIdx.z * p.M + gi) * p.N + gj;
+          TAcc* P = static_cast<TAcc*>(p.out) + ((int64_t)bz * p.M + gi) * p.N + gj;
           *P = v;
         }
       }

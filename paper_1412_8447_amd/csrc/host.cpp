@@ -142,14 +142,15 @@ void gemm(const Ctx& x, GemmDesc d, const char* stage = nullptr) {
 // matrix-core product. The next power step only needs a well-conditioned basis
 // of the row space (the pivoted QR is invariant to which basis), so one pass
 // with a tiny shift s, which rules out breakdown, is enough.
-void orth_rows(const Ctx& x, int dtype, const void* Vt, void* Qt, int64_t N, int l) {
+// Q^T = orth(V^T): V^T and Q^T are N x l with leading dimension ld.
+void orth_rows(const Ctx& x, int dtype, const void* Vt, void* Qt, int64_t N, int l, int64_t ld) {
   double* G = static_cast<double*>(x.ar->take((size_t)l * l * 8));
   double* L = static_cast<double*>(x.ar->take((size_t)l * l * 8));
   double* Li = static_cast<double*>(x.ar->take((size_t)l * l * 8));
   GemmDesc g{};
   g.M = l; g.N = l; g.K = N;
-  g.A = Vt; g.sam = 1; g.sak = l;
-  g.B = Vt; g.sbk = l; g.sbn = 1;
+  g.A = Vt; g.sam = 1; g.sak = ld;
+  g.B = Vt; g.sbk = ld; g.sbn = 1;
   g.C = G; g.ldc = l;
   g.in_type = dtype; g.acc_type = 0; g.out_type = 0;
   g.alpha = 1.0; g.beta = 0.0;
@@ -157,9 +158,9 @@ void orth_rows(const Ctx& x, int dtype, const void* Vt, void* Qt, int64_t N, int
   if (!x.dry) x.check(chol_inv_launch(0, G, l, 1, l, nullptr, L, l, Li, l, 1e-14, x.c->dstatus, x.s), "chol");
   GemmDesc q{};   // Q^T = V^T L^{-T}
   q.M = N; q.N = l; q.K = l;
-  q.A = Vt; q.sam = l; q.sak = 1;
+  q.A = Vt; q.sam = ld; q.sak = 1;
   q.B = Li; q.sbk = 1; q.sbn = l;
-  q.C = Qt; q.ldc = l;
+  q.C = Qt; q.ldc = ld;
   q.a_type = dtype; q.b_type = 0; q.acc_type = 0; q.out_type = dtype;
   q.alpha = 1.0; q.beta = 0.0;
   gemm(x, q);
@@ -215,17 +216,21 @@ ColId column_id(const Ctx& x, int dtype, const View& X, const idcur_opts& o, int
   const void* Ymat = X.A;
   int64_t yrs = X.xr, ycs = X.xc;
   if (sketch) {
-    void* Omt = x.ar->take((size_t)mr * l * esz(dtype));   // Omega^T, mr x l
-    void* Yt = x.ar->take((size_t)nc * l * esz(dtype));    // Y^T,     nc x l
-    void* Zt = o.q > 0 ? x.ar->take((size_t)mr * l * esz(dtype)) : nullptr;
-    void* Qyt = o.q > 0 ? x.ar->take((size_t)nc * l * esz(dtype)) : nullptr;   // orth(Y)^T
-    void* Qzt = o.q > 0 ? x.ar->take((size_t)mr * l * esz(dtype)) : nullptr;   // orth(Z)^T
+    // the thin sketch matrices are row-major with their width l padded to a
+    // multiple of 4 elements, so that every row starts 16-byte aligned and the
+    // GEMMs read them with vector loads
+    const int64_t ll = round_up(l, 4);
+    void* Omt = x.ar->take((size_t)mr * ll * esz(dtype));   // Omega^T, mr x l
+    void* Yt = x.ar->take((size_t)nc * ll * esz(dtype));    // Y^T,     nc x l
+    void* Zt = o.q > 0 ? x.ar->take((size_t)mr * ll * esz(dtype)) : nullptr;
+    void* Qyt = o.q > 0 ? x.ar->take((size_t)nc * ll * esz(dtype)) : nullptr;   // orth(Y)^T
+    void* Qzt = o.q > 0 ? x.ar->take((size_t)mr * ll * esz(dtype)) : nullptr;   // orth(Z)^T
     auto mul_t = [&](const void* Bm) {   // Y^T = X^T * Bm   (Bm: mr x l)
       GemmDesc g{};
       g.M = nc; g.N = l; g.K = mr;
       g.A = X.A; g.sam = X.xc; g.sak = X.xr;
-      g.B = Bm; g.sbk = l; g.sbn = 1;
-      g.C = Yt; g.ldc = l;
+      g.B = Bm; g.sbk = ll; g.sbn = 1;
+      g.C = Yt; g.ldc = ll;
       g.in_type = dtype; g.acc_type = dtype == IDCUR_F32 ? 1 : 0; g.out_type = dtype;
       g.alpha = 1.0; g.beta = 0.0;
       gemm(x, g, "sketch_gemm");
@@ -234,32 +239,32 @@ ColId column_id(const Ctx& x, int dtype, const View& X, const idcur_opts& o, int
       Stage st(x, "omega");
       if (!x.dry) {
         if (o.omega)
-          x.check(copy2d_launch(dtype, l, mr, o.omega, mr, 1, Omt, 1, l, x.s), "omega copy");
+          x.check(copy2d_launch(dtype, l, mr, o.omega, mr, 1, Omt, 1, ll, x.s), "omega copy");
         else
-          x.check(gaussian_launch(dtype, l, mr, o.seed, 0, Omt, 1, l, x.s), "omega");
+          x.check(gaussian_launch(dtype, l, mr, o.seed, 0, Omt, 1, ll, x.s), "omega");
       }
     }
     mul_t(Omt);
     for (int it = 0; it < o.q; ++it) {
       {
         Stage st(x, "orth");
-        orth_rows(x, dtype, Yt, Qyt, nc, l);
+        orth_rows(x, dtype, Yt, Qyt, nc, l, ll);
       }
       GemmDesc g{};   // Z^T = X * orth(Y)^T
       g.M = mr; g.N = l; g.K = nc;
       g.A = X.A; g.sam = X.xr; g.sak = X.xc;
-      g.B = Qyt; g.sbk = l; g.sbn = 1;
-      g.C = Zt; g.ldc = l;
+      g.B = Qyt; g.sbk = ll; g.sbn = 1;
+      g.C = Zt; g.ldc = ll;
       g.in_type = dtype; g.acc_type = dtype == IDCUR_F32 ? 1 : 0; g.out_type = dtype;
       g.alpha = 1.0; g.beta = 0.0;
       gemm(x, g, "sketch_gemm");
       {
         Stage st(x, "orth");
-        orth_rows(x, dtype, Zt, Qzt, mr, l);
+        orth_rows(x, dtype, Zt, Qzt, mr, l, ll);
       }
       mul_t(Qzt);
     }
-    Ymat = Yt; yrs = 1; ycs = l;
+    Ymat = Yt; yrs = 1; ycs = ll;
   }
 
   // CPQR on Y (l x nc)
@@ -528,6 +533,145 @@ idcur_status run_err(idcur_ctx* ctx, int dtype, int64_t m, int64_t n, const void
   }
 }
 
+// ---------------------------------------------------------------------------
+// Gradient of the column-ID reconstruction loss with the skeleton frozen
+// (Section 2.3 / Algorithm 1, sketched as in Section 5.1):
+//   Y = Omega A (or A),  T = argmin |Y(:,J1) X - Y(:,J2)|_F = S11^{-1} S12,
+//   E = A(:,J2) - A(:,J1) T,  L = |E|_F^2.
+// With Tbar = -2 C^T E (C = A(:,J1)) and M = (Y1^T Y1)^{-1} Tbar:
+//   Abar(:,J2) = 2E,  Abar(:,J1) = -2 E T^T,
+//   Ybar2 = Y1 M,  Ybar1 = (Y2 - Y1 T) M^T - Y1 M T^T,  Abar += Omega^T Ybar.
+// Everything is formed with columns in J order (Aj = A(:,J), Gj the gradient)
+// and permuted back at the end. Y1^T Y1 = S11^T S11 is factored by the FP64
+// Cholesky kernel; the small products run in FP64, the m x n ones in the
+// dtype with FP64 accumulation where a cancellation can occur.
+// ---------------------------------------------------------------------------
+struct BwdArgs {
+  const void* omega = nullptr;   // l x m row-major (ld m), or null: Y = A
+  int l = 0;
+  const int* J = nullptr;
+  int k = 0;
+  const void* T = nullptr;
+  int64_t ldt = 0;
+  double scale = 1.0;
+  void* dA = nullptr;
+  int64_t ldda = 0;
+};
+
+void id_col_backward(const Ctx& x, int dtype, int64_t m, int64_t n, const void* A, int64_t lda, const BwdArgs& b) {
+  const size_t es = esz(dtype);
+  const int k = b.k;
+  const int64_t n2 = n - k;
+  const bool sk = b.omega != nullptr;
+  const int l = b.l;
+  const int64_t ll = round_up(std::max(l, 1), 4);
+  int* Jinv = static_cast<int*>(x.ar->take((size_t)n * sizeof(int)));
+  char* Aj = static_cast<char*>(x.ar->take((size_t)m * n * es));   // A(:, J)
+  char* Gj = static_cast<char*>(x.ar->take((size_t)m * n * es));   // gradient, J order
+  double* Tb = static_cast<double*>(x.ar->take((size_t)k * n2 * 8));
+  double* Gr = static_cast<double*>(x.ar->take((size_t)k * k * 8));
+  double* Lf = static_cast<double*>(x.ar->take((size_t)k * k * 8));
+  double* Li = static_cast<double*>(x.ar->take((size_t)k * k * 8));
+  double* W = static_cast<double*>(x.ar->take((size_t)k * n2 * 8));
+  double* M = static_cast<double*>(x.ar->take((size_t)k * n2 * 8));
+  double* TMt = static_cast<double*>(x.ar->take((size_t)k * k * 8));
+  char* Yjt = sk ? static_cast<char*>(x.ar->take((size_t)n * ll * es)) : nullptr;    // Y^T, rows in J order
+  char* Rt = sk ? static_cast<char*>(x.ar->take((size_t)n2 * ll * es)) : nullptr;    // (Y2 - Y1 T)^T
+  double* Ybt = sk ? static_cast<double*>(x.ar->take((size_t)n * ll * 8)) : nullptr; // Ybar^T
+  const int F64 = IDCUR_F64;
+  auto mm = [&](int64_t Mr, int64_t Nc, int64_t K, const void* Am, int64_t sam, int64_t sak, int at, const void* Bm,
+                int64_t sbk, int64_t sbn, int bt, void* Cm, int64_t ldc, int ct, double alpha, double beta, int acc) {
+    GemmDesc g{};
+    g.M = Mr; g.N = Nc; g.K = K;
+    g.A = Am; g.sam = sam; g.sak = sak; g.a_type = at;
+    g.B = Bm; g.sbk = sbk; g.sbn = sbn; g.b_type = bt;
+    g.C = Cm; g.ldc = ldc; g.out_type = ct;
+    g.in_type = at; g.acc_type = acc; g.alpha = alpha; g.beta = beta;
+    gemm(x, g);
+  };
+  const int acc_d = dtype == IDCUR_F32 ? 1 : 0;   // accumulation in the dtype
+  // C = Aj(:, 0:k), E2 = 2E lives in Gj(:, k:n), Y1^T = Yjt rows 0..k
+  if (!x.dry) {
+    x.check(gather_cols_scaled_launch(dtype, m, A, lda, n, b.J, n, 1.0, 0, Aj, n, x.c->dstatus, x.s), "gather A(:,J)");
+    x.check(gather_cols_scaled_launch(dtype, m, A, lda, n, b.J + k, n2, 2.0, 0, Gj + k * es, n, x.c->dstatus, x.s),
+            "gather A(:,J2)");
+  }
+  // E2 = 2 A(:,J2) - 2 C T
+  mm(m, n2, k, Aj, n, 1, dtype, b.T, b.ldt, 1, dtype, Gj + k * es, n, dtype, -2.0, 1.0, 0);
+  // Tbar = -C^T E2 (FP64)
+  mm(k, n2, m, Aj, 1, n, dtype, Gj + k * es, n, 1, dtype, Tb, n2, F64, -1.0, 0.0, 0);
+  // Gj(:, 0:k) = -E2 T^T
+  mm(m, k, n2, Gj + k * es, n, 1, dtype, b.T, 1, b.ldt, dtype, Gj, n, dtype, -1.0, 0.0, acc_d);
+  // Gram Y1^T Y1 = S11^T S11
+  if (sk) {
+    // Y^T = Aj^T Omega^T (n x l, ld ll)
+    mm(n, l, m, Aj, 1, n, dtype, b.omega, 1, m, dtype, Yjt, ll, dtype, 1.0, 0.0, acc_d);
+    mm(k, k, l, Yjt, ll, 1, dtype, Yjt, 1, ll, dtype, Gr, k, F64, 1.0, 0.0, 0);
+  } else {
+    mm(k, k, m, Aj, 1, n, dtype, Aj, n, 1, dtype, Gr, k, F64, 1.0, 0.0, 0);
+  }
+  if (!x.dry)
+    x.check(chol_inv_launch(0, Gr, k, 1, k, nullptr, Lf, k, Li, k, 0.0, x.c->dstatus, x.s), "chol(Y1^T Y1)");
+  // M = Li^T (Li Tbar) = (Y1^T Y1)^{-1} Tbar;  TMt = T M^T
+  mm(k, n2, k, Li, k, 1, F64, Tb, n2, 1, F64, W, n2, F64, 1.0, 0.0, 0);
+  mm(k, n2, k, Li, 1, k, F64, W, n2, 1, F64, M, n2, F64, 1.0, 0.0, 0);
+  mm(k, k, n2, b.T, b.ldt, 1, dtype, M, 1, n2, F64, TMt, k, F64, 1.0, 0.0, 0);
+  if (sk) {
+    // R^T = Y2^T - T^T Y1^T
+    if (!x.dry) x.check(copy2d_launch(dtype, n2, l, Yjt + (size_t)k * ll * es, ll, 1, Rt, ll, 1, x.s), "copy Y2^T");
+    mm(n2, l, k, b.T, 1, b.ldt, dtype, Yjt, ll, 1, dtype, Rt, ll, dtype, -1.0, 1.0, 0);
+    // Ybar2^T = M^T Y1^T;  Ybar1^T = M R^T - (T M^T) Y1^T
+    mm(n2, l, k, M, 1, n2, F64, Yjt, ll, 1, dtype, Ybt + (size_t)k * ll, ll, F64, 1.0, 0.0, 0);
+    mm(k, l, n2, M, n2, 1, F64, Rt, ll, 1, dtype, Ybt, ll, F64, 1.0, 0.0, 0);
+    mm(k, l, k, TMt, k, 1, F64, Yjt, ll, 1, dtype, Ybt, ll, F64, -1.0, 1.0, 0);
+    // Gj += Omega^T Ybar
+    mm(m, n, l, b.omega, 1, m, dtype, Ybt, 1, ll, F64, Gj, n, dtype, 1.0, 1.0, 0);
+  } else {
+    // Y = A: Y1 = C, Y2 - Y1 T = E.  Ybar1 = E M^T - C (T M^T)^T first (it reads E),
+    // then Ybar2 = C M
+    mm(m, k, n2, Gj + k * es, n, 1, dtype, M, 1, n2, F64, Gj, n, dtype, 0.5, 1.0, 0);
+    mm(m, k, k, Aj, n, 1, dtype, TMt, 1, k, F64, Gj, n, dtype, -1.0, 1.0, 0);
+    mm(m, n2, k, Aj, n, 1, dtype, M, n2, 1, F64, Gj + k * es, n, dtype, 1.0, 1.0, 0);
+  }
+  // dA(:, c) = scale * Gj(:, Jinv(c))
+  if (!x.dry) {
+    x.check(invert_perm_launch(b.J, n, Jinv, x.c->dstatus, x.s), "invert J");
+    x.check(gather_cols_scaled_launch(dtype, m, Gj, n, n, Jinv, n, b.scale, 0, b.dA, b.ldda, x.c->dstatus, x.s),
+            "scatter gradient");
+  }
+}
+
+idcur_status run_bwd(idcur_ctx* ctx, int dtype, int64_t m, int64_t n, const void* A, int64_t lda, const BwdArgs& b,
+                     void* ws, size_t ws_bytes, size_t* bytes_only) {
+  try {
+    if (!ctx) return IDCUR_EINVAL;
+    if (dtype != IDCUR_F32 && dtype != IDCUR_F64) fail(ctx, IDCUR_EDTYPE, "bad dtype");
+    if (m <= 0 || n <= 0 || lda < n) fail(ctx, IDCUR_EINVAL, "bad sizes");
+    if (b.k <= 0 || b.k >= std::min(m, n) || b.k > 256) fail(ctx, IDCUR_EINVAL, "k must satisfy 0 < k < min(m, n), k <= 256");
+    if (b.omega && (b.l < b.k || b.l > m)) fail(ctx, IDCUR_EINVAL, "sketch rows l must satisfy k <= l <= m");
+    Arena dry;
+    Ctx xd{ctx, ctx->stream, true, &dry};
+    id_col_backward(xd, dtype, m, n, A, lda, b);
+    if (bytes_only) {
+      *bytes_only = dry.off + 256;
+      return IDCUR_OK;
+    }
+    if (!A || !b.J || !b.T || !b.dA) fail(ctx, IDCUR_EINVAL, "null pointer");
+    if (b.ldt < n - b.k || b.ldda < n) fail(ctx, IDCUR_EINVAL, "ldt or ldda too small");
+    if (!ws || ws_bytes < dry.off) fail(ctx, IDCUR_EWORKSPACE, "workspace missing or too small");
+    Arena ar;
+    ar.dry = false;
+    ar.base = static_cast<char*>(ws);
+    ar.cap = ws_bytes;
+    Ctx x{ctx, ctx->stream, false, &ar};
+    Stage st(x, "backward");
+    id_col_backward(x, dtype, m, n, A, lda, b);
+    return IDCUR_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  }
+}
+
 idcur_status run(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const void* A, int64_t lda,
                  const idcur_opts* opts, void* ws, size_t ws_bytes, const Outs& out) {
   try {
@@ -626,6 +770,7 @@ idcur_status idcur_sync_status(idcur_ctx* ctx) {
   if (hipMemset(ctx->dstatus, 0, sizeof(int)) != hipSuccess) return IDCUR_EHIP;
   if (st & ST_TIMEOUT) { ctx->err = "a grid-wide wait exceeded its spin limit"; return IDCUR_ETIMEOUT; }
   if (st & ST_NONFINITE) { ctx->err = "non-finite value or breakdown in a factorisation"; return IDCUR_ENONFINITE; }
+  if (st & ST_BADINDEX) { ctx->err = "an index array held a value out of range"; return IDCUR_EINVAL; }
   if (st & ST_RANKCAP) { ctx->err = "tolerance not reached within the rank cap"; return IDCUR_ERANKCAP; }
   return IDCUR_OK;
 }
@@ -727,6 +872,25 @@ idcur_status idcur_cur_error(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n
   e.which = 1; e.C = C; e.ldc = ldc; e.U = U; e.ldu = ldu; e.R = R; e.ldr = ldr;
   e.k_out = k_out; e.kcap = kcap; e.out = out;
   return run_err(ctx, dtype, m, n, A, lda, e, ws, ws_bytes, nullptr);
+}
+
+idcur_status idcur_id_col_backward_workspace_bytes(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, int32_t k,
+                                                   int32_t l, int32_t sketched, size_t* bytes) {
+  if (!bytes) return IDCUR_EINVAL;
+  idcur::BwdArgs b;
+  b.k = k;
+  b.l = l;
+  static const char dummy = 0;
+  b.omega = sketched ? &dummy : nullptr;
+  return idcur::run_bwd(ctx, dtype, m, n, nullptr, n, b, nullptr, 0, bytes);
+}
+
+idcur_status idcur_id_col_backward(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+                                   const void* omega, int32_t l, const int32_t* J, int32_t k, const void* T,
+                                   int64_t ldt, double scale, void* dA, int64_t ldda, void* ws, size_t ws_bytes) {
+  idcur::BwdArgs b;
+  b.omega = omega; b.l = l; b.J = J; b.k = k; b.T = T; b.ldt = ldt; b.scale = scale; b.dA = dA; b.ldda = ldda;
+  return idcur::run_bwd(ctx, dtype, m, n, A, lda, b, ws, ws_bytes, nullptr);
 }
 
 idcur_status idcur_gaussian(idcur_ctx* ctx, int32_t dtype, int64_t rows, int64_t cols, uint64_t seed, uint64_t stream,

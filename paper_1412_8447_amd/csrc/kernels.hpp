@@ -132,6 +132,14 @@ hipError_t copy2d_launch(int dtype, int64_t rows, int64_t cols, const void* in, 
 // Gather columns: out(i, s) = A(i, idx[s]) for s < k (k = *k_dev if set), row-major out.
 hipError_t gather_cols_launch(int dtype, int64_t m, const void* A, int64_t lda, const int* idx, int k_host,
                               const int* k_dev, void* out, int64_t ldo, int out_type, hipStream_t stream);
+// inv[idx[s]] = s: the inverse of a permutation of 0..n-1 (out-of-range
+// entries flag ST_BADINDEX).
+hipError_t invert_perm_launch(const int* idx, int64_t n, int* inv, int* status, hipStream_t stream);
+// out(i, c) = alpha * in(i, p[c]) (+= when accumulate) for c < ncols; in has nin
+// columns (p[c] outside [0, nin) flags ST_BADINDEX and reads column 0).
+hipError_t gather_cols_scaled_launch(int dtype, int64_t m, const void* in, int64_t ldi, int64_t nin, const int* p,
+                                     int64_t ncols, double alpha, int accumulate, void* out, int64_t ldo, int* status,
+                                     hipStream_t stream);
 // Gather rows: out(s, j) = A(idx[s], j) for s < k.
 hipError_t gather_rows_launch(int dtype, int64_t n, const void* A, int64_t lda, const int* idx, int k_host,
                               const int* k_dev, void* out, int64_t ldo, int out_type, hipStream_t stream);

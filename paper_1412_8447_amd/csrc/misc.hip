@@ -83,6 +83,42 @@ __global__ void gather_rows_kernel(int64_t n, const T* A, int64_t lda, const int
   }
 }
 
+__global__ void fill_int_kernel(int* p, int64_t n, int v) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) p[e] = v;
+}
+
+// inv[idx[s]] = s for s < n (idx a permutation of 0..n-1); out-of-range
+// entries are skipped and flagged.
+__global__ void invert_perm_kernel(const int* idx, int64_t n, int* inv, int* status) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x) {
+    const int c = idx[s];
+    if (c < 0 || c >= n) {
+      set_status(status, ST_BADINDEX);
+      continue;
+    }
+    inv[c] = (int)s;
+  }
+}
+
+// out(i, c) = alpha * in(i, p[c]) (+ out(i, c) when accumulate), c < ncols; an
+// out-of-range p[c] reads column 0 and is flagged.
+template <typename T>
+__global__ void gather_cols_scaled_kernel(int64_t m, const T* in, int64_t ldi, int64_t nin, const int* p, int64_t ncols,
+                                          double alpha, int accumulate, T* out, int64_t ldo, int* status) {
+  const int64_t total = m * ncols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / ncols, c = e % ncols;
+    int s = p[c];
+    if (s < 0 || s >= nin) {
+      set_status(status, ST_BADINDEX);
+      s = 0;
+    }
+    const double v = alpha * (double)in[i * ldi + s];
+    T* o = out + i * ldo + c;
+    *o = accumulate ? (T)((double)*o + v) : (T)v;
+  }
+}
+
 __global__ void zero_kernel(uint32_t* p, size_t nwords) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < nwords; e += (size_t)gridDim.x * blockDim.x) p[e] = 0u;
 }
@@ -198,6 +234,29 @@ hipError_t copy2d_launch(int dtype, int64_t rows, int64_t cols, const void* in, 
   else
     hipLaunchKernelGGL(copy2d_kernel<double>, dim3(g), dim3(256), 0, stream, rows, cols, static_cast<const double*>(in),
                        sir, sic, static_cast<double*>(out), sor, soc);
+  return hipGetLastError();
+}
+
+hipError_t invert_perm_launch(const int* idx, int64_t n, int* inv, int* status, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  // entries no index points to stay -1 (then flagged by the gathers that read them)
+  hipLaunchKernelGGL(fill_int_kernel, dim3(grid_for(n)), dim3(256), 0, stream, inv, n, -1);
+  hipLaunchKernelGGL(invert_perm_kernel, dim3(grid_for(n)), dim3(256), 0, stream, idx, n, inv, status);
+  return hipGetLastError();
+}
+
+hipError_t gather_cols_scaled_launch(int dtype, int64_t m, const void* in, int64_t ldi, int64_t nin, const int* p,
+                                     int64_t ncols, double alpha, int accumulate, void* out, int64_t ldo, int* status,
+                                     hipStream_t stream) {
+  if (m <= 0 || ncols <= 0) return hipSuccess;
+  const unsigned g = grid_for(m * ncols);
+  if (dtype == 1)
+    hipLaunchKernelGGL(gather_cols_scaled_kernel<float>, dim3(g), dim3(256), 0, stream, m, static_cast<const float*>(in),
+                       ldi, nin, p, ncols, alpha, accumulate, static_cast<float*>(out), ldo, status);
+  else
+    hipLaunchKernelGGL(gather_cols_scaled_kernel<double>, dim3(g), dim3(256), 0, stream, m,
+                       static_cast<const double*>(in), ldi, nin, p, ncols, alpha, accumulate, static_cast<double*>(out),
+                       ldo, status);
   return hipGetLastError();
 }
 
