@@ -53,7 +53,14 @@ typedef enum {
 
 typedef enum { IDCUR_F64 = 0, IDCUR_F32 = 1 } idcur_dtype;
 
-/* Input precision of the sketch and power-step GEMMs (accumulation is FP32). */
+/* Input precision of the sketch and power-step GEMMs (accumulation is FP32).
+ * BF16 / FP16 need IDCUR_F32 data (IDCUR_EDTYPE otherwise): A and the thin operand
+ * (Omega, or the orthonormal basis of a power step) are rounded to nearest even in
+ * 16 bits as the matrix cores read them, products are accumulated in FP32 and
+ * split-K partial sums in FP64. FP16 first multiplies A by 2^(15-e), where
+ * max|A| lies in [2^(e-1), 2^e), so that A's entries stay clear of the FP16
+ * subnormal range, and divides the FP32 result by the same power of two. Every
+ * later step (orthonormalisation, CPQR, T, row ID, U) runs as in NATIVE. */
 typedef enum { IDCUR_PREC_NATIVE = 0, IDCUR_PREC_BF16 = 1, IDCUR_PREC_FP16 = 2 } idcur_prec;
 
 /* How the CPQR keeps the trailing column norms between pivots: downdated
@@ -65,7 +72,9 @@ typedef enum {
   IDCUR_OP_ID_COL = 0,
   IDCUR_OP_ID_ROW = 1,
   IDCUR_OP_TWO_SIDED = 2,
-  IDCUR_OP_CUR = 3
+  IDCUR_OP_CUR = 3,
+  IDCUR_OP_SKETCH = 4,      /* idcur_sketch of A (the sketch an ID_COL call takes)  */
+  IDCUR_OP_SKETCH_ROW = 5   /* idcur_sketch of A^T (the sketch an ID_ROW call takes) */
 } idcur_op;
 
 typedef struct {
@@ -161,6 +170,22 @@ idcur_status idcur_cur(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, cons
                        const idcur_opts* opts, void* ws, size_t ws_bytes, int32_t* k_out,
                        int32_t* J, int32_t* I, void* U, int64_t ldu,
                        void* C, int64_t ldc, void* R, int64_t ldr);
+
+/* The randomized sketch alone (Section 5.1, eq. (Y=OmegaA); power steps of
+ * Section 5.3): the matrix Y whose k-step pivoted QR selects the skeleton.
+ *   op = IDCUR_OP_SKETCH:      Y = Omega A   (l x n, Omega l x m),
+ *   op = IDCUR_OP_SKETCH_ROW:  Y = Omega A^T (l x m, Omega l x n),
+ * then opts->q times Y <- orth(orth(Y) B^T) B with B the sketched matrix (A or
+ * A^T) and orth(.) an orthonormal basis of the row space (Cholesky QR with an FP64
+ * Gram matrix). l = k + p (kmax + p in tolerance mode); requires p >= 0 and l
+ * below the sketched dimension (m for SKETCH, n for SKETCH_ROW), else
+ * IDCUR_EINVAL. Omega and the precision are taken from opts exactly as the ID
+ * calls take them, so the same opts give the Y those calls factor.
+ *   Yt   device, dtype: Y^T, row c at Yt + c*ldy (c < n, or c < m for
+ *        SKETCH_ROW), ldy >= l.
+ * Workspace from idcur_workspace_bytes with the same op. */
+idcur_status idcur_sketch(idcur_ctx* ctx, int32_t op, int32_t dtype, int64_t m, int64_t n, const void* A,
+                          int64_t lda, const idcur_opts* opts, void* ws, size_t ws_bytes, void* Yt, int64_t ldy);
 
 /* Error measurement (the relative Frobenius errors reported with every result).
  * Both write out[0] = |A - C W|_F^2 and out[1] = |A|_F^2 (device doubles), with

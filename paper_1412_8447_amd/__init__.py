@@ -16,6 +16,8 @@ Decompositions"):
 * ``id_two_sided``  two-sided ID, Section 2.4 / Algorithm 2
 * ``cur``           CUR-ID, Section 3 / Algorithm 3
 * ``gaussian``      the Philox4x32-10 Gaussian sketch matrix of Section 5.1
+* ``sketch``        the randomized sketch Y = Omega A (Section 5.1) with the power
+                    steps of Section 5.3, in FP32 or on BF16 / FP16 matrix cores
 """
 from __future__ import annotations
 
@@ -46,7 +48,7 @@ OK, EINVAL, EDTYPE, EWORKSPACE, EHIP, ERANKCAP, ENONFINITE, ETIMEOUT = 0, -1, -2
 F64, F32 = 0, 1
 PREC_NATIVE, PREC_BF16, PREC_FP16 = 0, 1, 2
 NORMS_DOWNDATE, NORMS_EXACT = 0, 1
-OP_ID_COL, OP_ID_ROW, OP_TWO_SIDED, OP_CUR = 0, 1, 2, 3
+OP_ID_COL, OP_ID_ROW, OP_TWO_SIDED, OP_CUR, OP_SKETCH, OP_SKETCH_ROW = 0, 1, 2, 3, 4, 5
 
 STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", EDTYPE: "EDTYPE", EWORKSPACE: "EWORKSPACE", EHIP: "EHIP",
                 ERANKCAP: "ERANKCAP", ENONFINITE: "ENONFINITE", ETIMEOUT: "ETIMEOUT"}
@@ -83,6 +85,7 @@ _lib.idcur_id_row.argtypes = _common + [_vp, _vp, _i64]
 _lib.idcur_id_two_sided.argtypes = _common + [_vp, _vp, _i64, _vp, _vp, _i64]
 _lib.idcur_cur.argtypes = _common + [_vp, _vp, _vp, _i64, _vp, _i64, _vp, _i64]
 _lib.idcur_gaussian.argtypes = [_vp, _i32, _i64, _i64, _u64, _u64, _vp, _i64]
+_lib.idcur_sketch.argtypes = [_vp, _i32, _i32, _i64, _i64, _vp, _i64, ctypes.POINTER(Opts), _vp, _sz, _vp, _i64]
 _lib.idcur_error_workspace_bytes.argtypes = [_vp, _i32, _i32, _i64, _i64, _i32, ctypes.POINTER(_sz)]
 _lib.idcur_id_error.argtypes = [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _i32, _vp, _sz, _vp]
 _lib.idcur_cur_error.argtypes = [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i32, _vp,
@@ -95,15 +98,16 @@ _lib.idcur_timing_read.argtypes = [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c
 for _f in ("idcur_error_workspace_bytes", "idcur_id_error", "idcur_cur_error", "idcur_id_col_backward_workspace_bytes",
            "idcur_id_col_backward",
            "idcur_timing_enable", "idcur_timing_read", "idcur_create", "idcur_set_stream", "idcur_destroy", "idcur_sync_status", "idcur_workspace_bytes",
-           "idcur_id_col", "idcur_id_row", "idcur_id_two_sided", "idcur_cur", "idcur_gaussian"):
+           "idcur_id_col", "idcur_id_row", "idcur_id_two_sided", "idcur_cur", "idcur_gaussian", "idcur_sketch"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("idcur_opts_default", "idcur_create", "idcur_set_stream", "idcur_destroy", "idcur_last_error",
             "idcur_sync_status", "idcur_workspace_bytes", "idcur_id_col", "idcur_id_row", "idcur_id_two_sided",
             "idcur_cur", "idcur_gaussian", "idcur_timing_enable", "idcur_timing_read", "idcur_error_workspace_bytes",
-            "idcur_id_error", "idcur_cur_error", "idcur_id_col_backward_workspace_bytes", "idcur_id_col_backward")
+            "idcur_id_error", "idcur_cur_error", "idcur_id_col_backward_workspace_bytes", "idcur_id_col_backward",
+            "idcur_sketch")
 
-STAGES = ("omega", "sketch_gemm", "orth", "cpqr", "trsm", "gather", "row_id", "u_solve", "error", "backward")
+STAGES = ("omega", "pack", "sketch_gemm", "orth", "cpqr", "trsm", "gather", "row_id", "u_solve", "error", "backward")
 
 
 class IDCurError(RuntimeError):
@@ -193,6 +197,24 @@ def _ws(h, op, A, o, workspace):
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(need, dtype=torch.uint8, device=A.device)
     return workspace
+
+
+def sketch(A: torch.Tensor, k: int = 0, *, row: bool = False, workspace=None, **kw) -> torch.Tensor:
+    """The sketch an ID call with the same options factors: Y = Omega A (or
+    Omega A^T with ``row=True``), l = k + p rows, returned transposed as the
+    library writes it (``Yt``: n x l, or m x l). Keyword options as
+    :func:`make_opts` (``p >= 0`` required; ``prec`` selects the matrix-core
+    input precision)."""
+    h = _prep(A, kw.get("omega"))
+    o = make_opts(k, **kw)
+    m, n = A.shape
+    l = (o.k if o.k > 0 else o.kmax) + o.p
+    op = OP_SKETCH_ROW if row else OP_SKETCH
+    ws = _ws(h, op, A, o, workspace)
+    Yt = torch.empty(m if row else n, max(l, 1), dtype=A.dtype, device=A.device)
+    _check(h, _lib.idcur_sketch(h, op, _dtype_code(A), m, n, A.data_ptr(), A.stride(0), ctypes.byref(o),
+                                ws.data_ptr(), ws.numel(), Yt.data_ptr(), Yt.stride(0)))
+    return Yt
 
 
 @dataclass

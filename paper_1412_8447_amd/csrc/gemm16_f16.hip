@@ -1,0 +1,8 @@
+// 16-bit sketch GEMM instantiations with FP16 operands.
+#include "gemm16_kernel.hpp"
+
+namespace idcur {
+namespace g16 {
+hipError_t launch_fp16(int nt, const Args& a, bool akc, hipStream_t s) { return launch_h<true>(nt, a, akc, s); }
+}  // namespace g16
+}  // namespace idcur

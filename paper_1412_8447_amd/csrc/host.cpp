@@ -197,6 +197,134 @@ double default_rank_tol(int dtype, int64_t l) {
   return 10.0 * std::sqrt((double)std::max<int64_t>(l, 1)) * (dtype == IDCUR_F32 ? kU32 : kU64);
 }
 
+// The sketch of the view X (Section 5.1, eq. (Y=OmegaA)) with q orthonormalised
+// power steps (Section 5.3): Y^T (nc x l, row-major, ld round_up(l, 4)) in the
+// workspace, or X itself when no sketch is taken (p < 0 or k + p >= rows).
+// With a 16-bit precision the GEMMs round A and the thin operand to BF16 or FP16
+// (FP16: A prescaled by a power of two, undone on the FP32 result).
+struct SketchOut {
+  const void* Y;
+  int64_t rs, cs;   // Y(i, c) at Y[i*rs + c*cs]
+  int l;
+  bool sketched;
+};
+
+SketchOut sketch(const Ctx& x, int dtype, const View& X, const idcur_opts& o, int kcap, bool allow_sketch) {
+  SketchOut r{X.A, X.xr, X.xc, (int)X.rows, false};
+  const int64_t mr = X.rows, nc = X.cols;
+  if (!(allow_sketch && o.p >= 0 && (int64_t)kcap + o.p < mr)) return r;
+  const int l = kcap + o.p;
+  // the thin sketch matrices are row-major with their width l padded to a
+  // multiple of 4 elements, so that every row starts 16-byte aligned and the
+  // GEMMs read them with vector loads
+  const int64_t ll = round_up(l, 4);
+  const bool lowp = o.prec == IDCUR_PREC_BF16 || o.prec == IDCUR_PREC_FP16;
+  const int fp16 = o.prec == IDCUR_PREC_FP16;
+  void* Omt = (lowp && o.omega) ? nullptr : x.ar->take((size_t)mr * ll * esz(dtype));   // Omega^T, mr x l
+  void* Yt = x.ar->take((size_t)nc * ll * esz(dtype));    // Y^T,     nc x l
+  void* Zt = o.q > 0 ? x.ar->take((size_t)mr * ll * esz(dtype)) : nullptr;
+  void* Qyt = o.q > 0 ? x.ar->take((size_t)nc * ll * esz(dtype)) : nullptr;   // orth(Y)^T
+  void* Qzt = o.q > 0 ? x.ar->take((size_t)mr * ll * esz(dtype)) : nullptr;   // orth(Z)^T
+  // 16-bit thin operand, packed as B^T (l x K, k contiguous), and the FP16 scale
+  const int64_t ldb16 = round_up(std::max(mr, nc), 8);
+  void* B16 = lowp ? x.ar->take((size_t)l * ldb16 * 2) : nullptr;
+  float* scale = (lowp && fp16) ? static_cast<float*>(x.ar->take(2 * sizeof(float))) : nullptr;
+  float* spart = (lowp && fp16) ? static_cast<float*>(x.ar->take(kScaleParts * sizeof(float))) : nullptr;
+
+  auto pack = [&](int64_t K, const void* src, int64_t sj, int64_t sk) {
+    if (!x.dry)
+      x.check(pack16_launch(fp16, l, K, static_cast<const float*>(src), sj, sk, l, round_up(K, 8), B16, ldb16, x.s),
+              "pack16");
+  };
+  auto gemm_lp = [&](int64_t M, int64_t K, int64_t sam, int64_t sak, void* Cm) {   // Cm = X' * B16^T
+    Gemm16Desc g{};
+    g.M = M; g.N = l; g.K = K;
+    g.A = static_cast<const float*>(X.A); g.sam = sam; g.sak = sak;
+    g.B = B16; g.ldb = ldb16;
+    g.C = static_cast<float*>(Cm); g.ldc = ll;
+    g.fp16 = fp16; g.scale = scale;
+    g.splitk = gemm16_pick_splitk(M, l, K, x.c->num_cus);
+    void* part = x.ar->take(gemm16_part_bytes(g));
+    if (x.dry) return;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (x.c->timing) {
+      a = x.c->get_event();
+      b = x.c->get_event();
+    }
+    x.check(gemm16_launch(g, part, x.s, a, b), "gemm16");
+    if (a && b) x.c->marks.push_back({"sketch_gemm", a, b});
+  };
+  auto mul_t = [&](const void* Bm) {   // Y^T = X^T * Bm   (Bm: mr x l, ld ll)
+    if (lowp) {
+      {
+        Stage st(x, "pack");
+        pack(mr, Bm, 1, ll);
+      }
+      gemm_lp(nc, mr, X.xc, X.xr, Yt);
+      return;
+    }
+    GemmDesc g{};
+    g.M = nc; g.N = l; g.K = mr;
+    g.A = X.A; g.sam = X.xc; g.sak = X.xr;
+    g.B = Bm; g.sbk = ll; g.sbn = 1;
+    g.C = Yt; g.ldc = ll;
+    g.in_type = dtype; g.acc_type = dtype == IDCUR_F32 ? 1 : 0; g.out_type = dtype;
+    g.alpha = 1.0; g.beta = 0.0;
+    gemm(x, g, "sketch_gemm");
+  };
+  {
+    Stage st(x, "omega");
+    if (!x.dry && fp16) {
+      // power-of-two prescale from max |A| over the stored matrix
+      const bool rowmaj = X.xc == 1;
+      x.check(fp16_scale_launch(rowmaj ? X.rows : X.cols, rowmaj ? X.cols : X.rows, static_cast<const float*>(X.A),
+                                rowmaj ? X.xr : X.xc, spart, scale, x.s),
+              "fp16 scale");
+    }
+    if (!x.dry) {
+      if (o.omega && lowp)
+        pack(mr, o.omega, mr, 1);
+      else if (o.omega)
+        x.check(copy2d_launch(dtype, l, mr, o.omega, mr, 1, Omt, 1, ll, x.s), "omega copy");
+      else
+        x.check(gaussian_launch(dtype, l, mr, o.seed, 0, Omt, 1, ll, x.s), "omega");
+    }
+  }
+  if (o.omega && lowp)
+    gemm_lp(nc, mr, X.xc, X.xr, Yt);
+  else
+    mul_t(Omt);
+  for (int it = 0; it < o.q; ++it) {
+    {
+      Stage st(x, "orth");
+      orth_rows(x, dtype, Yt, Qyt, nc, l, ll);
+    }
+    if (lowp) {   // Z^T = X * orth(Y)^T
+      {
+        Stage st(x, "pack");
+        pack(nc, Qyt, 1, ll);
+      }
+      gemm_lp(mr, nc, X.xr, X.xc, Zt);
+    } else {
+      GemmDesc g{};
+      g.M = mr; g.N = l; g.K = nc;
+      g.A = X.A; g.sam = X.xr; g.sak = X.xc;
+      g.B = Qyt; g.sbk = ll; g.sbn = 1;
+      g.C = Zt; g.ldc = ll;
+      g.in_type = dtype; g.acc_type = dtype == IDCUR_F32 ? 1 : 0; g.out_type = dtype;
+      g.alpha = 1.0; g.beta = 0.0;
+      gemm(x, g, "sketch_gemm");
+    }
+    {
+      Stage st(x, "orth");
+      orth_rows(x, dtype, Zt, Qzt, mr, l, ll);
+    }
+    mul_t(Qzt);
+  }
+  r.Y = Yt; r.rs = 1; r.cs = ll; r.l = l; r.sketched = true;
+  return r;
+}
+
 // Column ID of the view X: J (cols), T (kcap x (cols-k), ldt), k_out (device).
 // Returns the S buffer (kcap x cols, by original column) for later use.
 struct ColId {
@@ -207,65 +335,13 @@ struct ColId {
 ColId column_id(const Ctx& x, int dtype, const View& X, const idcur_opts& o, int* k_out, int* J, void* T,
                 int64_t ldt, bool allow_sketch) {
   ColId r;
-  const int64_t mr = X.rows, nc = X.cols;
+  const int64_t nc = X.cols;
   const int kcap = o.k > 0 ? o.k : o.kmax;
   r.kcap = kcap;
-  const bool sketch = allow_sketch && o.p >= 0 && (int64_t)kcap + o.p < mr;
-  const int l = sketch ? kcap + o.p : (int)mr;
-
-  const void* Ymat = X.A;
-  int64_t yrs = X.xr, ycs = X.xc;
-  if (sketch) {
-    // the thin sketch matrices are row-major with their width l padded to a
-    // multiple of 4 elements, so that every row starts 16-byte aligned and the
-    // GEMMs read them with vector loads
-    const int64_t ll = round_up(l, 4);
-    void* Omt = x.ar->take((size_t)mr * ll * esz(dtype));   // Omega^T, mr x l
-    void* Yt = x.ar->take((size_t)nc * ll * esz(dtype));    // Y^T,     nc x l
-    void* Zt = o.q > 0 ? x.ar->take((size_t)mr * ll * esz(dtype)) : nullptr;
-    void* Qyt = o.q > 0 ? x.ar->take((size_t)nc * ll * esz(dtype)) : nullptr;   // orth(Y)^T
-    void* Qzt = o.q > 0 ? x.ar->take((size_t)mr * ll * esz(dtype)) : nullptr;   // orth(Z)^T
-    auto mul_t = [&](const void* Bm) {   // Y^T = X^T * Bm   (Bm: mr x l)
-      GemmDesc g{};
-      g.M = nc; g.N = l; g.K = mr;
-      g.A = X.A; g.sam = X.xc; g.sak = X.xr;
-      g.B = Bm; g.sbk = ll; g.sbn = 1;
-      g.C = Yt; g.ldc = ll;
-      g.in_type = dtype; g.acc_type = dtype == IDCUR_F32 ? 1 : 0; g.out_type = dtype;
-      g.alpha = 1.0; g.beta = 0.0;
-      gemm(x, g, "sketch_gemm");
-    };
-    {
-      Stage st(x, "omega");
-      if (!x.dry) {
-        if (o.omega)
-          x.check(copy2d_launch(dtype, l, mr, o.omega, mr, 1, Omt, 1, ll, x.s), "omega copy");
-        else
-          x.check(gaussian_launch(dtype, l, mr, o.seed, 0, Omt, 1, ll, x.s), "omega");
-      }
-    }
-    mul_t(Omt);
-    for (int it = 0; it < o.q; ++it) {
-      {
-        Stage st(x, "orth");
-        orth_rows(x, dtype, Yt, Qyt, nc, l, ll);
-      }
-      GemmDesc g{};   // Z^T = X * orth(Y)^T
-      g.M = mr; g.N = l; g.K = nc;
-      g.A = X.A; g.sam = X.xr; g.sak = X.xc;
-      g.B = Qyt; g.sbk = ll; g.sbn = 1;
-      g.C = Zt; g.ldc = ll;
-      g.in_type = dtype; g.acc_type = dtype == IDCUR_F32 ? 1 : 0; g.out_type = dtype;
-      g.alpha = 1.0; g.beta = 0.0;
-      gemm(x, g, "sketch_gemm");
-      {
-        Stage st(x, "orth");
-        orth_rows(x, dtype, Zt, Qzt, mr, l, ll);
-      }
-      mul_t(Qzt);
-    }
-    Ymat = Yt; yrs = 1; ycs = ll;
-  }
+  const SketchOut sk = sketch(x, dtype, X, o, kcap, allow_sketch);
+  const int l = sk.l;
+  const void* Ymat = sk.Y;
+  const int64_t yrs = sk.rs, ycs = sk.cs;
 
   // CPQR on Y (l x nc)
   const CpqrPlan pl = cpqr_plan((int)esz(dtype), l, (int)nc, kcap, x.c->num_cus);
@@ -372,7 +448,7 @@ void solve_u(const Ctx& x, int dtype, const void* R, int64_t ldr, int64_t n, int
   prod(kcap, kcap, kcap, Y1, 1, kcap, 0, L1i, kcap, 1, 0, U, ldu, dtype, k_dev, kr_dev, kr_dev);
 }
 
-enum Op { OP_COL = 0, OP_ROW = 1, OP_TWO = 2, OP_CUR = 3 };
+enum Op { OP_COL = 0, OP_ROW = 1, OP_TWO = 2, OP_CUR = 3, OP_SKETCH = 4, OP_SKETCH_ROW = 5 };
 
 struct Outs {
   int* k_out = nullptr;
@@ -381,6 +457,7 @@ struct Outs {
   void* U = nullptr; int64_t ldu = 0;
   void* C = nullptr; int64_t ldc = 0;
   void* R = nullptr; int64_t ldr = 0;
+  void* Yt = nullptr; int64_t ldy = 0;
 };
 
 void validate(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const void* A, int64_t lda,
@@ -388,13 +465,17 @@ void validate(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const voi
   if (!ctx) throw Fail{IDCUR_EINVAL};
   if (!opts) fail(ctx, IDCUR_EINVAL, "opts is NULL");
   if (dtype != IDCUR_F32 && dtype != IDCUR_F64) fail(ctx, IDCUR_EDTYPE, "dtype must be IDCUR_F32 or IDCUR_F64");
-  if (opts->prec != IDCUR_PREC_NATIVE) fail(ctx, IDCUR_EDTYPE, "only native-precision sketches are available");
-  if (op < 0 || op > 3) fail(ctx, IDCUR_EINVAL, "unknown op");
+  if (opts->prec != IDCUR_PREC_NATIVE && opts->prec != IDCUR_PREC_BF16 && opts->prec != IDCUR_PREC_FP16)
+    fail(ctx, IDCUR_EINVAL, "unknown precision");
+  if (opts->prec != IDCUR_PREC_NATIVE && dtype != IDCUR_F32)
+    fail(ctx, IDCUR_EDTYPE, "BF16 / FP16 sketches take FP32 data");
+  if (op < 0 || op > 5) fail(ctx, IDCUR_EINVAL, "unknown op");
   if (m <= 0 || n <= 0) fail(ctx, IDCUR_EINVAL, "m and n must be positive");
   if (m > (1LL << 30) || n > (1LL << 30)) fail(ctx, IDCUR_EINVAL, "m and n must be below 2^30");
   if (lda < n) fail(ctx, IDCUR_EINVAL, "lda must be >= n");
   (void)A;
-  const int64_t mr = op == OP_ROW ? n : m, nc = op == OP_ROW ? m : n;
+  const bool rowop = op == OP_ROW || op == OP_SKETCH_ROW;
+  const int64_t mr = rowop ? n : m, nc = rowop ? m : n;
   const int64_t mn = std::min(m, n);
   if (opts->k < 0) fail(ctx, IDCUR_EINVAL, "k must be >= 0");
   if (opts->k > 0) {
@@ -408,6 +489,8 @@ void validate(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const voi
   if (opts->q < 0) fail(ctx, IDCUR_EINVAL, "q must be >= 0");
   if (opts->p >= 0 && (int64_t)kcap + opts->p < mr && kcap + opts->p > 256)
     fail(ctx, IDCUR_EINVAL, "sketch width k + p must be <= 256");
+  if ((op == OP_SKETCH || op == OP_SKETCH_ROW) && !(opts->p >= 0 && (int64_t)kcap + opts->p < mr))
+    fail(ctx, IDCUR_EINVAL, "a sketch needs p >= 0 and k + p below the sketched dimension");
   if (opts->rank_tol < 0 || !std::isfinite(opts->rank_tol)) fail(ctx, IDCUR_EINVAL, "rank_tol must be >= 0");
   if (opts->norms != IDCUR_NORMS_DOWNDATE && opts->norms != IDCUR_NORMS_EXACT) fail(ctx, IDCUR_EINVAL, "bad norms");
   (void)nc;
@@ -418,6 +501,13 @@ void execute(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const void
   Ctx x{ctx, ctx->stream, ar.dry, &ar};
   const int kcap = o.k > 0 ? o.k : o.kmax;
   View X{A, m, n, lda, 1};
+  if (op == OP_SKETCH || op == OP_SKETCH_ROW) {
+    const View V = op == OP_SKETCH ? X : View{A, n, m, 1, lda};
+    const SketchOut s = sketch(x, dtype, V, o, kcap, true);
+    if (!ar.dry)
+      x.check(copy2d_launch(dtype, V.cols, s.l, s.Y, s.cs, s.rs, out.Yt, out.ldy, 1, x.s), "sketch out");
+    return;
+  }
   if (op == OP_ROW) {
     View Xt{A, n, m, 1, lda};
     column_id(x, dtype, Xt, o, out.k_out, out.I, out.Tr, out.ldtr, true);
@@ -677,10 +767,14 @@ idcur_status run(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const 
   try {
     validate(ctx, op, dtype, m, n, A, lda, opts);
     if (!A) fail(ctx, IDCUR_EINVAL, "A is NULL");
-    if (!out.k_out) fail(ctx, IDCUR_EINVAL, "k_out is NULL");
     const int kcap = opts->k > 0 ? opts->k : opts->kmax;
     const int64_t nc = op == OP_ROW ? m : n;
-    if (op == OP_ROW) {
+    if (op == OP_SKETCH || op == OP_SKETCH_ROW) {
+      if (!out.Yt) fail(ctx, IDCUR_EINVAL, "Yt is NULL");
+      if (out.ldy < kcap + opts->p) fail(ctx, IDCUR_EINVAL, "ldy too small");
+    } else if (!out.k_out) {
+      fail(ctx, IDCUR_EINVAL, "k_out is NULL");
+    } else if (op == OP_ROW) {
       if (!out.I || !out.Tr) fail(ctx, IDCUR_EINVAL, "I and Tr are required");
       if (out.ldtr < (opts->k > 0 ? m - kcap : m)) fail(ctx, IDCUR_EINVAL, "ldtr too small");
     } else {
@@ -846,6 +940,17 @@ idcur_status idcur_cur(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, cons
   Outs o;
   o.k_out = k_out; o.J = J; o.I = I; o.U = U; o.ldu = ldu; o.C = C; o.ldc = ldc; o.R = R; o.ldr = ldr;
   return run(ctx, OP_CUR, dtype, m, n, A, lda, opts, ws, ws_bytes, o);
+}
+
+idcur_status idcur_sketch(idcur_ctx* ctx, int32_t op, int32_t dtype, int64_t m, int64_t n, const void* A,
+                          int64_t lda, const idcur_opts* opts, void* ws, size_t ws_bytes, void* Yt, int64_t ldy) {
+  if (op != IDCUR_OP_SKETCH && op != IDCUR_OP_SKETCH_ROW) {
+    if (ctx) ctx->err = "op must be IDCUR_OP_SKETCH or IDCUR_OP_SKETCH_ROW";
+    return IDCUR_EINVAL;
+  }
+  Outs o;
+  o.Yt = Yt; o.ldy = ldy;
+  return run(ctx, op, dtype, m, n, A, lda, opts, ws, ws_bytes, o);
 }
 
 idcur_status idcur_error_workspace_bytes(idcur_ctx* ctx, int32_t which, int32_t dtype, int64_t m, int64_t n,

@@ -101,6 +101,38 @@ hipError_t gemm_resid_launch(int x_type, int64_t M, int64_t N, int64_t K, const 
                              double* part, double* out, hipStream_t stream);
 
 // ---------------------------------------------------------------------------
+// 16-bit MFMA GEMM (gemm16.hip): C (M x N, FP32, row-major ldc) = A (M x K) * B
+// (K x N) with A FP32 in memory (A(i, k) = A[i*sam + k*sak], sak == 1 or
+// sam == 1) rounded to BF16 / FP16 after multiplication by scale[0], and B
+// packed as 16-bit B^T: B(k, j) = B[j*ldb + k]. FP32 accumulation; the result is
+// multiplied by scale[1] (scale NULL: no scaling). Split-K partials (splitk * M *
+// N floats) are summed in split order in FP64.
+// ---------------------------------------------------------------------------
+struct Gemm16Desc {
+  int64_t M, N, K;
+  const float* A; int64_t sam, sak;
+  const void* B; int64_t ldb;
+  float* C; int64_t ldc;
+  int fp16;             // 0: BF16, 1: FP16
+  const float* scale;   // device {s, 1/s} or NULL
+  int splitk;
+};
+int gemm16_pick_splitk(int64_t M, int64_t N, int64_t K, int num_cus);
+size_t gemm16_part_bytes(const Gemm16Desc& d);
+hipError_t gemm16_launch(const Gemm16Desc& d, void* part, hipStream_t stream, hipEvent_t ev0 = nullptr,
+                         hipEvent_t ev1 = nullptr);
+// out(j, k) = round16(in(j, k)) (round to nearest even), in(j, k) = in[j*sj + k*sk],
+// for j < rows, k < cols, zero up to rows_pad x cols_pad; out row-major ldo.
+hipError_t pack16_launch(int fp16, int64_t rows, int64_t cols, const float* in, int64_t sj, int64_t sk,
+                         int64_t rows_pad, int64_t cols_pad, void* out, int64_t ldo, hipStream_t stream);
+// FP16 prescale of a rows x cols FP32 matrix (ld lda): scale = {2^(15-e), 2^(e-15)}
+// with max|A| in [2^(e-1), 2^e) ({1, 1} for a zero or non-finite maximum).
+// part: kScaleParts floats.
+constexpr int kScaleParts = 1024;
+hipError_t fp16_scale_launch(int64_t rows, int64_t cols, const float* A, int64_t lda, float* part, float* scale,
+                             hipStream_t stream);
+
+// ---------------------------------------------------------------------------
 // Cholesky factor and triangular inverse (chol.hip), FP64, c <= 256, one workgroup.
 //   mode 0: G = L L^T (G(i,j) = G[i*gr + j*gc], optional diagonal shift
 //           shift_rel * max diag) -> L (row-major, zeros above) and X = L^{-1}
