@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+PEAK_16BIT_MFMA_TFLOPS = 2500.0   # dense BF16 / FP16
 
 
 def log(*a):
@@ -74,6 +75,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the BF16 / FP16 sketch measurements")
     ap.add_argument("--seed", type=int, default=20260)
     ap.add_argument("--input-cache", default=None,
                     help="load A from this file when it exists, else generate it and save it there")
@@ -188,6 +190,47 @@ def main():
         "roofline": roofline,
     }
 
+    # the same step with the sketch and power-step GEMMs on BF16 / FP16 matrix cores
+    if not args.no_mixed:
+        mixed = {}
+        for prec in ("bf16", "fp16"):
+            o = P.make_opts(k, p=p, q=q, seed=args.seed + 1, prec=prec)
+            wsm = torch.empty(P.workspace_bytes(P.OP_CUR, A, o), dtype=torch.uint8, device=dev)
+            outm = {kk: torch.empty_like(v) for kk, v in out.items()}
+            for _ in range(2):
+                P.cur(A, k, workspace=wsm, out=outm, sync=False, prec=prec, **kw)
+            P.sync_status(dev)
+            P.timing_enable(True, dev)
+            reps = max(3, args.steps)
+            e0.record()
+            for _ in range(reps):
+                P.cur(A, k, workspace=wsm, out=outm, sync=False, prec=prec, **kw)
+            e1.record()
+            torch.cuda.synchronize()
+            ms_m = e0.elapsed_time(e1) / reps
+            st_m = P.timing_read(dev)
+            P.timing_enable(False, dev)
+            P.sync_status(dev)
+            er = P.cur_error(A, outm["C"], outm["U"], outm["R"], outm["kout"], k).tolist()
+            em = math.sqrt(er[0] / er[1])
+            gm, gc = st_m["sketch_gemm"]
+            gavg = gm / max(gc, 1)
+            # per step: Y^T = A^T Omega^T and Y^T = A^T Q'^T (K = m, rows n), Z^T = A Q^T (K = n, rows m)
+            bytes_step = (2 * q + 1) * 4.0 * m * n + (q + 1) * (2.0 * l * m + 4.0 * l * n) + q * (2.0 * l * n + 4.0 * l * m)
+            gbs = bytes_step / (2 * q + 1) / (gavg * 1e-3) / 1e9
+            tfl = 2.0 * l * m * n / (gavg * 1e-3) / 1e12
+            mixed[prec] = {"ms_per_step": round(ms_m, 4), "gflops": round(flops["total"] / (ms_m * 1e-3) / 1e9, 2),
+                           "matrices_per_s": round(1000.0 / ms_m, 3), "rel_fro_error": em,
+                           "error_ratio_vs_fp32": round(em / e_cur, 4),
+                           "stages_ms_per_step": {sname: round(v[0] / reps, 4) for sname, v in st_m.items() if v[1]},
+                           "sketch_gemm": {"avg_launch_ms": round(gavg, 4), "launches": gc,
+                                           "hbm_GBps": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4),
+                                           "TFLOPs": round(tfl, 2),
+                                           "mfma_frac": round(tfl / PEAK_16BIT_MFMA_TFLOPS, 4)}}
+            log(prec, mixed[prec])
+            del wsm, outm
+        result["mixed_precision"] = mixed
+
     # plain FP32 GPU CPQR comparator (no sketch) and the equal-error sweep
     if not args.no_comparator:
         log("comparator: deterministic FP32 CPQR CUR-ID on A")
@@ -270,6 +313,8 @@ def main():
                                   "leading_pivots_identical": int(np.array_equal(Jg[:lead], ref.ts.col.J[:lead])),
                                   "clear_pivots": lead}
         log(f"oracle {tcpu:.1f}s e={e_orc:.4e}")
+        for prec, r in result.get("mixed_precision", {}).items():
+            r["error_ratio_vs_fp64_oracle"] = round(r["rel_fro_error"] / e_orc, 4)
 
     print(json.dumps(result), flush=True)
 

@@ -78,8 +78,9 @@ typedef enum {
 } idcur_op;
 
 typedef struct {
-  int32_t k;          /* > 0: fixed rank, k < min(m, n). 0: tolerance mode.            */
-  int32_t kmax;       /* rank cap in tolerance mode (ignored when k > 0).               */
+  int32_t k;          /* > 0: fixed rank, k < min(m, n), k <= 4096. 0: tolerance mode. */
+  int32_t kmax;       /* rank cap in tolerance mode (ignored when k > 0), <= 4096; the
+                         sketch width k + p (kmax + p) is also at most 4096.           */
   double tol;         /* tolerance mode: smallest k with |Y_res|_F <= tol |Y|_F
                          (Section 3: continue the QR until |E| is below a threshold). */
   double rank_tol;    /* stop early (exact rank deficiency, Section 2.3) when the
@@ -219,7 +220,7 @@ idcur_status idcur_cur_error(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n
  *   omega  l x m row-major (ld m), same dtype, or NULL; k <= l <= m.
  *   J      device int32[n], a permutation (e.g. from idcur_id_col); values out of
  *          range are reported as IDCUR_EINVAL by idcur_sync_status.
- *   k      rank, 0 < k < min(m, n), k <= 256 (host value).
+ *   k      rank, 0 < k < min(m, n), k <= 4096 (host value).
  *   T      k x (n-k) (ld ldt >= n-k), dtype: the interpolation matrix of that ID.
  * Workspace from idcur_id_col_backward_workspace_bytes(dtype, m, n, k, l,
  * sketched = omega != NULL). */

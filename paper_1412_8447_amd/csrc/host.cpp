@@ -55,6 +55,7 @@ namespace idcur {
 namespace {
 
 constexpr double kU32 = 5.9604644775390625e-08;   // 2^-24
+constexpr int kMaxRank = 4096;   // largest k (and k + p): bounds the k x k FP64 work buffers
 constexpr double kU64 = 1.1102230246251565e-16;   // 2^-53
 
 struct Fail {
@@ -136,6 +137,68 @@ void gemm(const Ctx& x, GemmDesc d, const char* stage = nullptr) {
   if (a && b) x.c->marks.push_back({stage, a, b});
 }
 
+// Cholesky factor and triangular inverse of any order. Up to kCholDirect the
+// one-workgroup kernel does it all; above, a right-looking blocked form runs the
+// same kernel on diagonal blocks of at most kCholDirect and FP64 matrix-core
+// products for the rest:
+//   mode 0:  L_pp X_pp = chol/inverse of P_pp;  L_rp = P_rp X_pp^T;
+//            P_rr -= L_rp L_rp^T  (P = G, shifted, updated in place)
+//   mode 1:  X_pp = inverse of the given factor's diagonal block;
+// then, block row by block row, X(r, 0:o) = -X_rr (F(r, 0:o) X(0:o, 0:o)) with F
+// the lower factor. A device order c_dev is handled by padding G with the
+// identity, whose factor and inverse are the identity.
+constexpr int kCholDirect = 256;
+
+void chol_inv(const Ctx& x, int mode, const double* G, int64_t gr, int64_t gc, int c, const int* c_dev, double* L,
+              int64_t ldl, double* X, int64_t ldx, double shift_rel, const char* what) {
+  if (c <= kCholDirect) {
+    if (!x.dry) x.check(chol_inv_launch(mode, G, gr, gc, c, c_dev, L, ldl, X, ldx, shift_rel, x.c->dstatus, x.s), what);
+    return;
+  }
+  const int nb = (int)ceil_div(c, kCholDirect);
+  const int b = (int)std::min<int64_t>(kCholDirect, round_up(ceil_div(c, nb), 32));
+  double* P = static_cast<double*>(x.ar->take((size_t)c * c * 8));
+  double* W = static_cast<double*>(x.ar->take((size_t)c * c * 8));
+  double* sh = (mode == 0 && shift_rel > 0.0) ? static_cast<double*>(x.ar->take(8)) : nullptr;
+  if (!x.dry) {
+    if (sh) x.check(diag_shift_launch(G, gr, gc, c, c_dev, shift_rel, sh, x.s), what);
+    x.check(pad_square_launch(G, gr, gc, c, c_dev, mode == 1 ? 1 : 0, sh, P, c, x.s), what);
+    if (mode == 0) x.check(zero2d_launch(L, c, c, ldl, x.s), what);
+    x.check(zero2d_launch(X, c, c, ldx, x.s), what);
+  }
+  auto mm = [&](int64_t M, int64_t N, int64_t K, const double* Am, int64_t sam, int64_t sak, const double* Bm,
+                int64_t sbk, int64_t sbn, double* Cm, int64_t ldc, double alpha, double beta) {
+    GemmDesc g{};
+    g.M = M; g.N = N; g.K = K;
+    g.A = Am; g.sam = sam; g.sak = sak;
+    g.B = Bm; g.sbk = sbk; g.sbn = sbn;
+    g.C = Cm; g.ldc = ldc;
+    g.in_type = 0; g.acc_type = 0; g.out_type = 0;
+    g.alpha = alpha; g.beta = beta;
+    gemm(x, g);
+  };
+  for (int p = 0; p < nb; ++p) {
+    const int o = p * b, sp = std::min(b, c - o);
+    if (!x.dry)
+      x.check(chol_inv_launch(mode, P + (int64_t)o * c + o, c, 1, sp, nullptr, mode == 0 ? L + (int64_t)o * ldl + o : nullptr,
+                              ldl, X + (int64_t)o * ldx + o, ldx, 0.0, x.c->dstatus, x.s),
+              what);
+    const int r = c - o - sp;
+    if (mode == 0 && r > 0) {
+      double* Lrp = L + (int64_t)(o + sp) * ldl + o;
+      mm(r, sp, sp, P + (int64_t)(o + sp) * c + o, c, 1, X + (int64_t)o * ldx + o, 1, ldx, Lrp, ldl, 1.0, 0.0);
+      mm(r, r, sp, Lrp, ldl, 1, Lrp, 1, ldl, P + (int64_t)(o + sp) * c + (o + sp), c, -1.0, 1.0);
+    }
+  }
+  const double* F = mode == 0 ? L : P;
+  const int64_t ldf = mode == 0 ? ldl : c;
+  for (int p = 1; p < nb; ++p) {
+    const int o = p * b, sp = std::min(b, c - o);
+    mm(sp, o, o, F + (int64_t)o * ldf, ldf, 1, X, ldx, 1, W, o, 1.0, 0.0);
+    mm(sp, o, sp, X + (int64_t)o * ldx + o, ldx, 1, W, o, 1, X + (int64_t)o * ldx, ldx, -1.0, 0.0);
+  }
+}
+
 // Row-orthonormalise V (l x N), stored transposed as Vt (N x l, row-major),
 // into Qt (same layout): Cholesky QR, G = V V^T + s I = L L^T, Q = L^{-1} V,
 // with an FP64 Gram matrix, factor and inverse, and Q^T = V^T L^{-T} as one
@@ -155,7 +218,7 @@ void orth_rows(const Ctx& x, int dtype, const void* Vt, void* Qt, int64_t N, int
   g.in_type = dtype; g.acc_type = 0; g.out_type = 0;
   g.alpha = 1.0; g.beta = 0.0;
   gemm(x, g);
-  if (!x.dry) x.check(chol_inv_launch(0, G, l, 1, l, nullptr, L, l, Li, l, 1e-14, x.c->dstatus, x.s), "chol");
+  chol_inv(x, 0, G, l, 1, l, nullptr, L, l, Li, l, 1e-14, "chol");
   GemmDesc q{};   // Q^T = V^T L^{-T}
   q.M = N; q.N = l; q.K = l;
   q.A = Vt; q.sam = ld; q.sak = 1;
@@ -180,8 +243,8 @@ void interp_matrix(const Ctx& x, int dtype, const void* S, int64_t ldS, const in
     x.check(gather_s11_launch(dtype, S, ldS, J, kcap, k_dev, S11, x.s), "gather S11");
     x.check(gather_s12_launch(dtype, S, ldS, J, n, kcap, k_dev, S12, ldo, ncol, x.s), "gather S12");
     // view S11^T as lower: element (i, j) = S11[j][i]
-    x.check(chol_inv_launch(1, S11, 1, kcap, kcap, k_dev, nullptr, 0, S11it, kcap, 0.0, x.c->dstatus, x.s), "S11 inverse");
   }
+  chol_inv(x, 1, S11, 1, kcap, kcap, k_dev, nullptr, 0, S11it, kcap, 0.0, "S11 inverse");
   GemmDesc g{};   // T = S11^{-1} S12, A(i, kk) = S11it[kk][i]
   g.M = kcap; g.N = std::min<int64_t>(n - 1, ldt); g.K = kcap;
   g.A = S11it; g.sam = 1; g.sak = kcap;
@@ -432,12 +495,12 @@ void solve_u(const Ctx& x, int dtype, const void* R, int64_t ldr, int64_t n, int
   };
   // G1 = R R^T, L1 L1^T = G1
   prod(kcap, kcap, n, R, ldr, 1, dtype, R, 1, ldr, dtype, G, kcap, 0, kr_dev, kr_dev, nullptr);
-  if (!x.dry) x.check(chol_inv_launch(0, G, kcap, 1, kcap, kr_dev, L1, kcap, L1i, kcap, 1e-15, x.c->dstatus, x.s), "chol(R)");
+  chol_inv(x, 0, G, kcap, 1, kcap, kr_dev, L1, kcap, L1i, kcap, 1e-15, "chol(R)");
   // Q1^T = L1^{-1} R
   prod(kcap, n, kcap, L1i, kcap, 1, 0, R, ldr, 1, dtype, Q1t, n, 0, kr_dev, nullptr, kr_dev);
   // G2 = Q1^T Q1, L2 L2^T = G2, Q^T = L2^{-1} Q1^T
   prod(kcap, kcap, n, Q1t, n, 1, 0, Q1t, 1, n, 0, G, kcap, 0, kr_dev, kr_dev, nullptr);
-  if (!x.dry) x.check(chol_inv_launch(0, G, kcap, 1, kcap, kr_dev, L2, kcap, L2i, kcap, 0.0, x.c->dstatus, x.s), "chol(Q1)");
+  chol_inv(x, 0, G, kcap, 1, kcap, kr_dev, L2, kcap, L2i, kcap, 0.0, "chol(Q1)");
   prod(kcap, n, kcap, L2i, kcap, 1, 0, Q1t, n, 1, 0, Qt, n, 0, kr_dev, nullptr, kr_dev);
   // Bls = Q^T V (kr x k)
   if (!x.dry) x.check(build_v_launch(dtype, T, ldt, J, n, kcap, k_dev, V, kcap, x.s), "build V");
@@ -485,10 +548,9 @@ void validate(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const voi
     if (opts->kmax <= 0 || opts->kmax >= mn) fail(ctx, IDCUR_EINVAL, "tolerance mode needs 0 < kmax < min(m, n)");
   }
   const int kcap = opts->k > 0 ? opts->k : opts->kmax;
-  if (kcap > 256 && (op == OP_CUR)) fail(ctx, IDCUR_EINVAL, "cur supports k <= 256");
   if (opts->q < 0) fail(ctx, IDCUR_EINVAL, "q must be >= 0");
-  if (opts->p >= 0 && (int64_t)kcap + opts->p < mr && kcap + opts->p > 256)
-    fail(ctx, IDCUR_EINVAL, "sketch width k + p must be <= 256");
+  if (kcap > kMaxRank || (opts->p >= 0 && (int64_t)kcap + opts->p > kMaxRank))
+    fail(ctx, IDCUR_EINVAL, "k (kmax) and k + p must be <= 4096");
   if ((op == OP_SKETCH || op == OP_SKETCH_ROW) && !(opts->p >= 0 && (int64_t)kcap + opts->p < mr))
     fail(ctx, IDCUR_EINVAL, "a sketch needs p >= 0 and k + p below the sketched dimension");
   if (opts->rank_tol < 0 || !std::isfinite(opts->rank_tol)) fail(ctx, IDCUR_EINVAL, "rank_tol must be >= 0");
@@ -700,8 +762,7 @@ void id_col_backward(const Ctx& x, int dtype, int64_t m, int64_t n, const void* 
   } else {
     mm(k, k, m, Aj, 1, n, dtype, Aj, n, 1, dtype, Gr, k, F64, 1.0, 0.0, 0);
   }
-  if (!x.dry)
-    x.check(chol_inv_launch(0, Gr, k, 1, k, nullptr, Lf, k, Li, k, 0.0, x.c->dstatus, x.s), "chol(Y1^T Y1)");
+  chol_inv(x, 0, Gr, k, 1, k, nullptr, Lf, k, Li, k, 0.0, "chol(Y1^T Y1)");
   // M = Li^T (Li Tbar) = (Y1^T Y1)^{-1} Tbar;  TMt = T M^T
   mm(k, n2, k, Li, k, 1, F64, Tb, n2, 1, F64, W, n2, F64, 1.0, 0.0, 0);
   mm(k, n2, k, Li, 1, k, F64, W, n2, 1, F64, M, n2, F64, 1.0, 0.0, 0);
@@ -737,7 +798,8 @@ idcur_status run_bwd(idcur_ctx* ctx, int dtype, int64_t m, int64_t n, const void
     if (!ctx) return IDCUR_EINVAL;
     if (dtype != IDCUR_F32 && dtype != IDCUR_F64) fail(ctx, IDCUR_EDTYPE, "bad dtype");
     if (m <= 0 || n <= 0 || lda < n) fail(ctx, IDCUR_EINVAL, "bad sizes");
-    if (b.k <= 0 || b.k >= std::min(m, n) || b.k > 256) fail(ctx, IDCUR_EINVAL, "k must satisfy 0 < k < min(m, n), k <= 256");
+    if (b.k <= 0 || b.k >= std::min(m, n) || b.k > kMaxRank)
+      fail(ctx, IDCUR_EINVAL, "k must satisfy 0 < k < min(m, n), k <= 4096");
     if (b.omega && (b.l < b.k || b.l > m)) fail(ctx, IDCUR_EINVAL, "sketch rows l must satisfy k <= l <= m");
     Arena dry;
     Ctx xd{ctx, ctx->stream, true, &dry};

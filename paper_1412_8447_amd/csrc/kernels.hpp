@@ -133,7 +133,8 @@ hipError_t fp16_scale_launch(int64_t rows, int64_t cols, const float* A, int64_t
                              hipStream_t stream);
 
 // ---------------------------------------------------------------------------
-// Cholesky factor and triangular inverse (chol.hip), FP64, c <= 256, one workgroup.
+// Cholesky factor and triangular inverse (chol.hip), FP64, c <= 256, one workgroup
+// (larger c: the blocked driver in host.cpp).
 //   mode 0: G = L L^T (G(i,j) = G[i*gr + j*gc], optional diagonal shift
 //           shift_rel * max diag) -> L (row-major, zeros above) and X = L^{-1}
 //   mode 1: G is a lower-triangular factor (strided view) -> X = G^{-1}
@@ -189,6 +190,15 @@ hipError_t build_vstar_launch(int dtype, const void* T, int64_t ldt, const int* 
 // out = sum of squares of the m x n matrix A (FP64 accumulation; part: 1024 doubles).
 hipError_t sumsq_launch(int dtype, int64_t m, int64_t n, const void* A, int64_t lda, double* part, double* out,
                         hipStream_t stream);
+// P (c_host x c_host, ld ldp) = G's active c x c block (c = min(*c_dev, c_host),
+// G(i, j) = G[i*gr + j*gc]) padded with the identity; lower_only zeroes the upper
+// triangle; *shift (device, optional) is added to the active diagonal.
+hipError_t pad_square_launch(const double* G, int64_t gr, int64_t gc, int c_host, const int* c_dev, int lower_only,
+                             const double* shift, double* P, int64_t ldp, hipStream_t stream);
+// *out = rel * max_i G(i, i) over the active diagonal.
+hipError_t diag_shift_launch(const double* G, int64_t gr, int64_t gc, int c_host, const int* c_dev, double rel,
+                             double* out, hipStream_t stream);
+hipError_t zero2d_launch(double* p, int64_t rows, int64_t cols, int64_t ld, hipStream_t stream);
 hipError_t add_gathered_launch(const double* Q, int64_t ldq, const int* J, int ka_host, const int* ka_dev,
                                int kb_host, const int* kb_dev, double* out, int64_t ldo, hipStream_t stream);
 

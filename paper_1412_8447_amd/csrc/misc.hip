@@ -123,6 +123,42 @@ __global__ void zero_kernel(uint32_t* p, size_t nwords) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < nwords; e += (size_t)gridDim.x * blockDim.x) p[e] = 0u;
 }
 
+// P (c_host x c_host, row-major ldp) = the active c x c block of G (c = min(*c_dev,
+// c_host)), identity outside it; lower_only zeroes the part above the diagonal;
+// *shift (when given) is added to the active diagonal.
+__global__ void pad_square_kernel(const double* G, int64_t gr, int64_t gc, int c_host, const int* c_dev,
+                                  int lower_only, const double* shift, double* P, int64_t ldp) {
+  const int c = c_dev ? min(*c_dev, c_host) : c_host;
+  const double sh = shift ? *shift : 0.0;
+  const int64_t total = (int64_t)c_host * c_host;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / c_host), j = (int)(e % c_host);
+    double v;
+    if (i < c && j < c) v = (lower_only && j > i) ? 0.0 : G[(int64_t)i * gr + (int64_t)j * gc] + (i == j ? sh : 0.0);
+    else v = i == j ? 1.0 : 0.0;
+    P[(int64_t)i * ldp + j] = v;
+  }
+}
+
+// *out = rel * max_i G(i, i) over the active diagonal (one workgroup).
+__global__ __launch_bounds__(256) void diag_shift_kernel(const double* G, int64_t gr, int64_t gc, int c_host,
+                                                         const int* c_dev, double rel, double* out) {
+  __shared__ double ws[4];
+  const int c = c_dev ? min(*c_dev, c_host) : c_host;
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < c; i += 256) mx = fmax(mx, G[(int64_t)i * gr + (int64_t)i * gc]);
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = rel * fmax(fmax(ws[0], ws[1]), fmax(ws[2], ws[3]));
+}
+
+__global__ void zero2d_kernel(double* p, int64_t rows, int64_t cols, int64_t ld) {
+  const int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+    p[(e / cols) * ld + e % cols] = 0.0;
+}
+
 __global__ void add_gathered_kernel(const double* Q, int64_t ldq, const int* J, int ka_host, const int* ka_dev,
                                     int kb_host, const int* kb_dev, double* out, int64_t ldo) {
   const int ka = ka_dev ? min(*ka_dev, ka_host) : ka_host;
@@ -364,6 +400,26 @@ hipError_t sumsq_launch(int dtype, int64_t m, int64_t n, const void* A, int64_t 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(sum1024, dim3(1), dim3(256), 0, stream, part, out);
+  return hipGetLastError();
+}
+
+hipError_t pad_square_launch(const double* G, int64_t gr, int64_t gc, int c_host, const int* c_dev, int lower_only,
+                             const double* shift, double* P, int64_t ldp, hipStream_t stream) {
+  if (c_host <= 0) return hipSuccess;
+  hipLaunchKernelGGL(pad_square_kernel, dim3(grid_for((int64_t)c_host * c_host)), dim3(256), 0, stream, G, gr, gc,
+                     c_host, c_dev, lower_only, shift, P, ldp);
+  return hipGetLastError();
+}
+
+hipError_t diag_shift_launch(const double* G, int64_t gr, int64_t gc, int c_host, const int* c_dev, double rel,
+                             double* out, hipStream_t stream) {
+  hipLaunchKernelGGL(diag_shift_kernel, dim3(1), dim3(256), 0, stream, G, gr, gc, c_host, c_dev, rel, out);
+  return hipGetLastError();
+}
+
+hipError_t zero2d_launch(double* p, int64_t rows, int64_t cols, int64_t ld, hipStream_t stream) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero2d_kernel, dim3(grid_for(rows * cols)), dim3(256), 0, stream, p, rows, cols, ld);
   return hipGetLastError();
 }
 
