@@ -192,6 +192,20 @@ def _prep(A: torch.Tensor, omega):
     return _context(A.device)
 
 
+def _mat(t: torch.Tensor, name: str, dtype=None) -> None:
+    """A matrix argument: a 2-D device tensor with unit column stride (row r at
+    data_ptr + r * stride(0)), of ``dtype`` when given."""
+    if not t.is_cuda or t.dim() != 2 or (t.shape[1] > 1 and t.stride(1) != 1):
+        raise IDCurError(EINVAL, f"{name} must be a 2-D row-major device tensor (unit column stride)")
+    if dtype is not None and t.dtype != dtype:
+        raise IDCurError(EINVAL, f"{name} must have dtype {dtype}")
+
+
+def _idx(t: torch.Tensor, name: str) -> None:
+    if not t.is_cuda or t.dtype != torch.int32 or not t.is_contiguous():
+        raise IDCurError(EINVAL, f"{name} must be a contiguous int32 device tensor")
+
+
 def _ws(h, op, A, o, workspace):
     need = workspace_bytes(op, A, o)
     if workspace is None or workspace.numel() < need:
@@ -375,6 +389,10 @@ def _err_ws(which, A, kcap, workspace):
 def id_error(A: torch.Tensor, J: torch.Tensor, T: torch.Tensor, kout: torch.Tensor, kcap: int, *, workspace=None,
              out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Device [|A - C V*|_F^2, |A|_F^2] (float64) for the column ID (J, T)."""
+    _mat(A, "A")
+    _mat(T, "T", A.dtype)
+    _idx(J, "J")
+    _idx(kout, "kout")
     h, ws = _err_ws(0, A, kcap, workspace)
     if out is None:
         out = torch.zeros(2, dtype=torch.float64, device=A.device)
@@ -387,6 +405,10 @@ def id_error(A: torch.Tensor, J: torch.Tensor, T: torch.Tensor, kout: torch.Tens
 def cur_error(A: torch.Tensor, C: torch.Tensor, U: torch.Tensor, R: torch.Tensor, kout: torch.Tensor, kcap: int, *,
               workspace=None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Device [|A - C U R|_F^2, |A|_F^2] (float64)."""
+    _mat(A, "A")
+    for t, nm in ((C, "C"), (U, "U"), (R, "R")):
+        _mat(t, nm, A.dtype)
+    _idx(kout, "kout")
     h, ws = _err_ws(1, A, kcap, workspace)
     if out is None:
         out = torch.zeros(2, dtype=torch.float64, device=A.device)
@@ -413,8 +435,8 @@ def id_col_backward(A: torch.Tensor, J: torch.Tensor, T: torch.Tensor, k: int, *
         workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=A.device)
     if out is None:
         out = torch.empty(m, n, dtype=A.dtype, device=A.device)
-    if J.dtype != torch.int32 or not J.is_contiguous() or T.stride(1) != 1:
-        raise IDCurError(EINVAL, "J must be contiguous int32 and T row-major")
+    _idx(J, "J")
+    _mat(T, "T", A.dtype)
     _check(h, _lib.idcur_id_col_backward(h, _dtype_code(A), m, n, A.data_ptr(), A.stride(0),
                                          omega.data_ptr() if omega is not None else None, l, J.data_ptr(), int(k),
                                          T.data_ptr(), T.stride(0), float(scale), out.data_ptr(), out.stride(0),

@@ -89,7 +89,9 @@ __global__ __launch_bounds__(256, 2) void gemm16_kernel(Args p) {
   const int64_t W = tiles_total(p), per = (W + 7) / 8;
   const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
   if (tile >= W) return;
-  const int bx = (int)(tile % p.gx), by = (int)((tile / p.gx) % p.gy), bz = (int)(tile / ((int64_t)p.gx * p.gy));
+  // column tiles of one row stripe are adjacent (same XCD, dispatched together),
+  // so the stripe of A they all read comes from HBM once and from L2 after that
+  const int by = (int)(tile % p.gy), bx = (int)((tile / p.gy) % p.gx), bz = (int)(tile / ((int64_t)p.gx * p.gy));
   const int64_t m0 = (int64_t)bx * BM, n0 = (int64_t)by * BN;
   const int64_t kb = (int64_t)bz * p.kps, ke = min(p.K, kb + p.kps);
   const float s_in = p.scale ? p.scale[0] : 1.0f;
