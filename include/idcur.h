@@ -116,11 +116,12 @@ idcur_status idcur_sync_status(idcur_ctx* ctx);
 
 /* Per-stage GPU timers for measurement. With timing enabled, every later call on
  * this context records a pair of HIP events on the context's stream around each
- * stage: "omega", "sketch_gemm" (the sketch / power-step GEMM kernels alone,
- * without their split-K reduction), "orth", "cpqr", "trsm", "gather", "row_id",
- * "u_solve", "error". Enabling (or disabling) synchronises the stream and clears the
- * accumulated marks. idcur_timing_read synchronises and returns the summed
- * elapsed milliseconds and the number of marks of one stage (host outputs). */
+ * stage: "omega", "pack", "sketch_gemm" (the sketch / power-step GEMM kernels
+ * alone, without their split-K reduction), "orth", "cpqr", "trsm", "gather",
+ * "row_id", "u_solve", "error", "backward", "batched". Enabling (or disabling)
+ * synchronises the stream and clears the accumulated marks. idcur_timing_read
+ * synchronises and returns the summed elapsed milliseconds and the number of
+ * marks of one stage (host outputs). */
 idcur_status idcur_timing_enable(idcur_ctx* ctx, int32_t enable);
 idcur_status idcur_timing_read(idcur_ctx* ctx, const char* stage, double* total_ms /* host */,
                                int32_t* count /* host */);
@@ -229,6 +230,58 @@ idcur_status idcur_id_col_backward_workspace_bytes(idcur_ctx* ctx, int32_t dtype
 idcur_status idcur_id_col_backward(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, const void* A, int64_t lda,
                                    const void* omega, int32_t l, const int32_t* J, int32_t k, const void* T,
                                    int64_t ldt, double scale, void* dA, int64_t ldda, void* ws, size_t ws_bytes);
+
+/* Batched adaptive-rank column ID: nblk independent FP32 blocks in one persistent
+ * launch (Section 3's tolerance variant of the column ID of Section 2.3, on the
+ * randomized sketch of Section 5.1 / Algorithm 4). For block b (m[b] x n[b],
+ * row-major at A[b] with leading dimension lda[b]):
+ *   Y = Omega(:l, :m_b) A_b with one Omega (l_cap x mmax, i.i.d. N(0,1), drawn
+ *   from opts->seed as idcur_gaussian(rows = l_cap, cols = mmax, stream 0) would,
+ *   or opts->omega: l_cap x mmax row-major FP32, ld mmax) shared by all blocks;
+ *   column-pivoted Householder QR of Y with exact column norms.
+ *   Tolerance mode (opts->k == 0): the rank is the smallest k with
+ *   |Y_res|_F <= opts->tol |Y|_F, at most l - p steps; l starts at
+ *   min(32, l_cap) and doubles up to l_cap = opts->kmax + opts->p when the
+ *   tolerance is not met (a block that misses it at l_cap keeps l_cap - p steps
+ *   and sets IDCUR_ERANKCAP in the device status). Fixed rank (opts->k > 0):
+ *   l = k + p, k steps. Exact rank deficiency stops early: when the largest
+ *   remaining column norm is <= opts->rank_tol times the largest initial column
+ *   norm of Y (opts->rank_tol == 0 selects sqrt(l_cap) u32, u32 = 2^-24, so that
+ *   in tolerance mode the Frobenius rule decides unless pivots reach rounding
+ *   level).
+ *   T = S11^{-1} S12 by FP64 back-substitution.
+ * Limits: 1 <= n_b <= nmax <= 512, 1 <= m_b <= mmax, (k or kmax) + p <= 64,
+ * p >= 1, q = 0, NATIVE precision, dtype IDCUR_F32. A block outside its limits
+ * gets k_out[b] = -1 and IDCUR_EINVAL from idcur_sync_status.
+ * All arrays are DEVICE arrays of nblk entries: m, n (int32), A (pointers to
+ * const float), lda (int64), and the outputs k_out (int32), J (pointers to
+ * int32[n_b]: pivots first, then the other columns in increasing order), T
+ * (pointers to float, k_out[b] x (n_b - k_out[b]) written with leading
+ * dimension ldt[b] >= n_b; the caller sizes each T as (k or kmax) x n_b).
+ * The call only enqueues kernels on the context's stream (no allocation, no
+ * host synchronisation, no memset node), so it can be captured in a hipGraph.
+ * Results do not depend on the launch variant. Workspace from
+ * idcur_id_col_batched_workspace_bytes. */
+idcur_status idcur_id_col_batched_workspace_bytes(idcur_ctx* ctx, int32_t dtype, int32_t nblk, int32_t mmax,
+                                                  int32_t nmax, const idcur_opts* opts, size_t* bytes /* host out */);
+idcur_status idcur_id_col_batched(idcur_ctx* ctx, int32_t dtype, int32_t nblk, int32_t mmax, int32_t nmax,
+                                  const int32_t* m, const int32_t* n, const void* const* A, const int64_t* lda,
+                                  const idcur_opts* opts, void* ws, size_t ws_bytes, int32_t* k_out, int32_t* const* J,
+                                  void* const* T, const int64_t* ldt);
+/* Autotuner: runs the batched call once per launch variant (sketch prefetch
+ * depth, workgroups per CU, largest-first ordering), times each with HIP events
+ * on the context's stream (synchronising it), keeps the fastest for this size
+ * class (nblk rounded up to a power of two, mmax, nmax, l_cap, mode) in the
+ * context, and leaves that variant's results in the outputs. *variant (host)
+ * receives the choice. Later idcur_id_col_batched calls of the same class use it. */
+idcur_status idcur_id_col_batched_autotune(idcur_ctx* ctx, int32_t dtype, int32_t nblk, int32_t mmax, int32_t nmax,
+                                           const int32_t* m, const int32_t* n, const void* const* A,
+                                           const int64_t* lda, const idcur_opts* opts, void* ws, size_t ws_bytes,
+                                           int32_t* k_out, int32_t* const* J, void* const* T, const int64_t* ldt,
+                                           int32_t* variant /* host out */);
+/* Force a launch variant (0 .. 7) for every later batched call on this context;
+ * -1 returns to the tuned or default choice. */
+idcur_status idcur_id_col_batched_set_variant(idcur_ctx* ctx, int32_t variant);
 
 /* The Gaussian sketch matrix alone (Section 5.1: i.i.d. N(0,1) entries): writes
  * Omega(r, i), r < rows, i < cols, to out + r*ldo + i. Entry (r, i) is defined by

@@ -18,6 +18,9 @@ Decompositions"):
 * ``gaussian``      the Philox4x32-10 Gaussian sketch matrix of Section 5.1
 * ``sketch``        the randomized sketch Y = Omega A (Section 5.1) with the power
                     steps of Section 5.3, in FP32 or on BF16 / FP16 matrix cores
+* ``BatchedID``     adaptive-rank column IDs of many FP32 blocks in one persistent
+                    launch (Section 3's tolerance variant on the sketch of Section
+                    5.1), capturable in a graph, with a launch autotuner
 """
 from __future__ import annotations
 
@@ -85,6 +88,11 @@ _lib.idcur_id_row.argtypes = _common + [_vp, _vp, _i64]
 _lib.idcur_id_two_sided.argtypes = _common + [_vp, _vp, _i64, _vp, _vp, _i64]
 _lib.idcur_cur.argtypes = _common + [_vp, _vp, _vp, _i64, _vp, _i64, _vp, _i64]
 _lib.idcur_gaussian.argtypes = [_vp, _i32, _i64, _i64, _u64, _u64, _vp, _i64]
+_lib.idcur_id_col_batched_workspace_bytes.argtypes = [_vp, _i32, _i32, _i32, _i32, ctypes.POINTER(Opts), ctypes.POINTER(_sz)]
+_batched_args = [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, ctypes.POINTER(Opts), _vp, _sz, _vp, _vp, _vp, _vp]
+_lib.idcur_id_col_batched.argtypes = _batched_args
+_lib.idcur_id_col_batched_autotune.argtypes = _batched_args + [ctypes.POINTER(_i32)]
+_lib.idcur_id_col_batched_set_variant.argtypes = [_vp, _i32]
 _lib.idcur_sketch.argtypes = [_vp, _i32, _i32, _i64, _i64, _vp, _i64, ctypes.POINTER(Opts), _vp, _sz, _vp, _i64]
 _lib.idcur_error_workspace_bytes.argtypes = [_vp, _i32, _i32, _i64, _i64, _i32, ctypes.POINTER(_sz)]
 _lib.idcur_id_error.argtypes = [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _i32, _vp, _sz, _vp]
@@ -98,16 +106,20 @@ _lib.idcur_timing_read.argtypes = [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c
 for _f in ("idcur_error_workspace_bytes", "idcur_id_error", "idcur_cur_error", "idcur_id_col_backward_workspace_bytes",
            "idcur_id_col_backward",
            "idcur_timing_enable", "idcur_timing_read", "idcur_create", "idcur_set_stream", "idcur_destroy", "idcur_sync_status", "idcur_workspace_bytes",
-           "idcur_id_col", "idcur_id_row", "idcur_id_two_sided", "idcur_cur", "idcur_gaussian", "idcur_sketch"):
+           "idcur_id_col", "idcur_id_row", "idcur_id_two_sided", "idcur_cur", "idcur_gaussian", "idcur_sketch",
+           "idcur_id_col_batched_workspace_bytes", "idcur_id_col_batched", "idcur_id_col_batched_autotune",
+           "idcur_id_col_batched_set_variant"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("idcur_opts_default", "idcur_create", "idcur_set_stream", "idcur_destroy", "idcur_last_error",
             "idcur_sync_status", "idcur_workspace_bytes", "idcur_id_col", "idcur_id_row", "idcur_id_two_sided",
             "idcur_cur", "idcur_gaussian", "idcur_timing_enable", "idcur_timing_read", "idcur_error_workspace_bytes",
             "idcur_id_error", "idcur_cur_error", "idcur_id_col_backward_workspace_bytes", "idcur_id_col_backward",
-            "idcur_sketch")
+            "idcur_sketch", "idcur_id_col_batched_workspace_bytes", "idcur_id_col_batched",
+            "idcur_id_col_batched_autotune", "idcur_id_col_batched_set_variant")
 
-STAGES = ("omega", "pack", "sketch_gemm", "orth", "cpqr", "trsm", "gather", "row_id", "u_solve", "error", "backward")
+STAGES = ("omega", "pack", "sketch_gemm", "orth", "cpqr", "trsm", "gather", "row_id", "u_solve", "error", "backward",
+          "batched")
 
 
 class IDCurError(RuntimeError):
@@ -472,3 +484,117 @@ class IDReconLoss(torch.autograd.Function):
 def recon_loss(A: torch.Tensor, k: int, omega: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Differentiable column-ID reconstruction loss (see IDReconLoss)."""
     return IDReconLoss.apply(A, k, omega)
+
+
+# ---------------------------------------------------------------------------
+# Batched adaptive-rank column ID (one persistent launch)
+# ---------------------------------------------------------------------------
+@dataclass
+class BlockID:
+    J: torch.Tensor   # int32 (n_b,)
+    T: torch.Tensor   # (k_b, n_b - k_b)
+    k: int
+
+
+class BatchedID:
+    """Column IDs of many FP32 blocks (each 2-D, row-major, n_b <= 512) in one
+    persistent launch (idcur_id_col_batched). Tolerance mode with ``tol`` and the
+    rank cap ``kmax``, or a fixed rank ``k``; oversampling ``p``.
+
+    The plan owns every device array the call reads or writes (block pointers and
+    sizes, outputs, workspace), so :meth:`run` only enqueues kernels on the
+    current stream and can be captured in a graph (``torch.cuda.CUDAGraph``)."""
+
+    def __init__(self, blocks, *, tol: float = 0.0, kmax: int = 0, k: int = 0, p: int = 8, seed: int = 0,
+                 omega: Optional[torch.Tensor] = None, rank_tol: float = 0.0):
+        if not blocks:
+            raise IDCurError(EINVAL, "no blocks")
+        dev = blocks[0].device
+        for b in blocks:
+            _mat(b, "block", torch.float32)
+            if b.device != dev:
+                raise IDCurError(EINVAL, "all blocks must be on one device")
+        if omega is not None:
+            _mat(omega, "omega", torch.float32)
+            omega = omega.contiguous()
+        self.h = _context(dev)
+        self.device = dev
+        self.blocks = list(blocks)
+        self.omega = omega
+        ms = [int(b.shape[0]) for b in blocks]
+        ns = [int(b.shape[1]) for b in blocks]
+        self.ms, self.ns = ms, ns
+        self.nblk = len(blocks)
+        self.mmax, self.nmax = max(ms), max(ns)
+        self.opts = make_opts(k, tol=tol, kmax=kmax, p=p, seed=seed, omega=omega, rank_tol=rank_tol)
+        self.kcap = k if k > 0 else kmax
+        i32, i64 = torch.int32, torch.int64
+        self.m = torch.tensor(ms, dtype=i32, device=dev)
+        self.n = torch.tensor(ns, dtype=i32, device=dev)
+        self.A = torch.tensor([b.data_ptr() for b in blocks], dtype=i64, device=dev)
+        self.lda = torch.tensor([b.stride(0) for b in blocks], dtype=i64, device=dev)
+        offj, offt, oj, ot = [], [], 0, 0
+        for nb in ns:
+            offj.append(oj)
+            offt.append(ot)
+            oj += nb
+            ot += max(self.kcap, 1) * nb
+        self.offj, self.offt = offj, offt
+        self.Jbuf = torch.empty(oj, dtype=i32, device=dev)
+        self.Tbuf = torch.zeros(ot, dtype=torch.float32, device=dev)
+        self.Jp = torch.tensor([self.Jbuf.data_ptr() + 4 * o for o in offj], dtype=i64, device=dev)
+        self.Tp = torch.tensor([self.Tbuf.data_ptr() + 4 * o for o in offt], dtype=i64, device=dev)
+        self.ldt = torch.tensor(ns, dtype=i64, device=dev)
+        self.kout = torch.zeros(self.nblk, dtype=i32, device=dev)
+        nbytes = ctypes.c_size_t(0)
+        _check(self.h, _lib.idcur_id_col_batched_workspace_bytes(self.h, F32, self.nblk, self.mmax, self.nmax,
+                                                                 ctypes.byref(self.opts), ctypes.byref(nbytes)))
+        self.ws = torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device=dev)
+
+    def _args(self):
+        return (self.h, F32, self.nblk, self.mmax, self.nmax, self.m.data_ptr(), self.n.data_ptr(),
+                self.A.data_ptr(), self.lda.data_ptr(), ctypes.byref(self.opts), self.ws.data_ptr(),
+                self.ws.numel(), self.kout.data_ptr(), self.Jp.data_ptr(), self.Tp.data_ptr(), self.ldt.data_ptr())
+
+    def run(self) -> None:
+        """Enqueue the batched launch on the current stream (no synchronisation)."""
+        _lib.idcur_set_stream(self.h, _vp(torch.cuda.current_stream(self.device).cuda_stream))
+        _check(self.h, _lib.idcur_id_col_batched(*self._args()))
+
+    def autotune(self) -> int:
+        """Time every launch variant on this batch, keep the fastest for its size
+        class in the context; returns the variant (results are left in place)."""
+        _lib.idcur_set_stream(self.h, _vp(torch.cuda.current_stream(self.device).cuda_stream))
+        v = _i32(-1)
+        _check(self.h, _lib.idcur_id_col_batched_autotune(*self._args(), ctypes.byref(v)))
+        return int(v.value)
+
+    def results(self) -> list:
+        """Synchronise and return one BlockID per block (views into the plan's
+        output buffers: copy them before the next run)."""
+        st = _lib.idcur_sync_status(self.h)
+        if st not in (OK, ERANKCAP):
+            raise IDCurError(st, _lib.idcur_last_error(self.h).decode())
+        ks = self.kout.tolist()
+        out = []
+        for b, kb in enumerate(ks):
+            nb = self.ns[b]
+            J = self.Jbuf[self.offj[b]: self.offj[b] + nb]
+            Tfull = self.Tbuf[self.offt[b]: self.offt[b] + max(self.kcap, 1) * nb].view(max(self.kcap, 1), nb)
+            out.append(BlockID(J, Tfull[:max(kb, 0), : nb - max(kb, 0)], kb))
+        return out
+
+
+def set_batched_variant(variant: int, device=None) -> None:
+    """Force a batched launch variant (0..7) on the device's context; -1 restores
+    the tuned / default choice."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    h = _context(dev)
+    _check(h, _lib.idcur_id_col_batched_set_variant(h, int(variant)))
+
+
+def id_col_batched(blocks, **kw) -> list:
+    """Column IDs of a list of FP32 blocks in one launch (see :class:`BatchedID`)."""
+    plan = BatchedID(blocks, **kw)
+    plan.run()
+    return plan.results()

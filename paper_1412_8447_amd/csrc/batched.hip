@@ -1,0 +1,490 @@
+// Batched adaptive-rank column ID: many independent blocks A_b (m_b x n_b, FP32,
+// n_b <= 512) compressed in one persistent launch. Per block, one workgroup
+// runs the tolerance variant of Section 3 on the randomized sketch of Section
+// 5.1 (Algorithm 4):
+//
+//   1. Y = Omega(:l, :m_b) A_b on the FP32 matrix cores (v_mfma_f32_16x16x4f32,
+//      FP32 sums over 16-k chunks added in FP64), written straight into LDS
+//      (column-major, odd column stride);
+//   2. column-pivoted Householder QR of Y in LDS with the column norms
+//      recomputed exactly after every update; before each step the residual
+//      |Y_res|_F is compared with tol |Y|_F; at most l - p steps are taken;
+//      when the tolerance is not met, l doubles (up to l_cap = kmax + p) and
+//      the block is sketched and factored again;
+//   3. T = S11^{-1} S12 by back-substitution in FP64 registers (Section 4.1),
+//      written with J = [pivots, the other columns in increasing order].
+//
+// One Omega (l_cap x m_max, stored transposed) serves every block. Workgroups
+// take blocks from an atomic counter, in the order of a one-workgroup bitonic
+// sort by m_b n_b (largest first) so the last blocks to start are the smallest.
+// Results do not depend on which workgroup takes a block or on the launch
+// shape: every reduction inside a block has a fixed order.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace idcur {
+namespace {
+
+constexpr int kBT = 256;        // threads per workgroup
+constexpr int kBL0 = 32;        // first sketch width
+constexpr int kBLmax = 64;      // largest sketch width
+constexpr int kBNmax = 512;     // largest block width
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+struct BArgs {
+  int nblk;
+  const int* m; const int* n;
+  const float* const* A; const int64_t* lda;
+  int* const* J; float* const* T; const int64_t* ldt;
+  int* k_out;
+  const float* omt; int ldom;      // Omega^T: mpad x ldom, zero outside l_cap x m_max
+  int mmax, nmax, lcap, p, kfix;   // kfix > 0: fixed rank k, l = k + p
+  double tol, rank_tol;
+  const int* order;                // processing order, or NULL
+  int* queue;                      // block counter, zero at launch
+  int* status;
+  int ldy;                         // LDS column stride of Y (odd)
+};
+
+// ---- block-wide reductions (256 threads, fixed order) ------------------------
+struct Best {
+  double v;
+  int o;   // original column index (tie-break)
+  int pos; // position in the factorisation
+};
+__device__ __forceinline__ bool beats(const Best& a, const Best& b) {
+  return a.v > b.v || (a.v == b.v && a.o < b.o);
+}
+
+__device__ Best block_best_sum(Best b, double& s, Best* sb, double* ss) {
+  for (int o = 32; o > 0; o >>= 1) {
+    Best c{__shfl_xor(b.v, o, 64), __shfl_xor(b.o, o, 64), __shfl_xor(b.pos, o, 64)};
+    if (beats(c, b)) b = c;
+    s += __shfl_xor(s, o, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) { sb[w] = b; ss[w] = s; }
+  __syncthreads();
+  Best r = sb[0];
+  double t = ss[0];
+#pragma unroll
+  for (int i = 1; i < kBT / 64; ++i) {
+    if (beats(sb[i], r)) r = sb[i];
+    t += ss[i];
+  }
+  s = t;
+  return r;
+}
+
+// ---- 1. sketch: rows r0 .. r0 + 16 RT - 1 of Y = Omega A (LDS, Y(i, c) at
+// Ys[c*LDY + i]). The 16-column tiles are spread over the waves, four per wave
+// and pass (tiles w + 4t + 16g for pass g). Products are summed on the matrix
+// cores in FP32 over chunks of 16 consecutive k (four 16x16x4 steps) and the
+// chunks are added in FP64: at the tolerances this path serves (1e-6 on smooth
+// kernels, about 16 u32) FP32 sums over all m_b terms would put rounding noise
+// of the tolerance's own size into Y. PF chunks of loads are issued together.
+template <int RT, int PF, int LDY>
+__device__ __forceinline__ void sketch_rows(const BArgs& a, const float* __restrict__ A, int64_t lda, int m, int n,
+                                            int r0, float* Ys) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int kq = lane >> 4, col = lane & 15;
+  const int ctn = (n + 15) >> 4;
+  const int mq = (m + 3) & ~3;
+  for (int g = 0; g < 2; ++g) {
+    if (wv + 16 * g >= ctn) break;   // this wave has no tile in this pass
+    double tot[RT][4][4];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) tot[r][t][q] = 0.0;
+    for (int k0 = 0; k0 < mq; k0 += 16 * PF) {
+      float av[PF][4][RT], bv[PF][4][4];
+#pragma unroll
+      for (int c = 0; c < PF; ++c)
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int k = k0 + 16 * c + 4 * st + kq;
+          const bool kin = k < m;
+#pragma unroll
+          for (int r = 0; r < RT; ++r) av[c][st][r] = kin ? a.omt[(int64_t)k * a.ldom + r0 + r * 16 + col] : 0.0f;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int j = (wv + 4 * t + 16 * g) * 16 + col;
+            bv[c][st][t] = (kin && j < n) ? A[(int64_t)k * lda + j] : 0.0f;
+          }
+        }
+#pragma unroll
+      for (int c = 0; c < PF; ++c) {
+        f32x4 acc[RT][4];
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) acc[r][t] = f32x4{0, 0, 0, 0};
+#pragma unroll
+        for (int st = 0; st < 4; ++st)
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            if (wv + 4 * t + 16 * g < ctn)
+#pragma unroll
+              for (int r = 0; r < RT; ++r)
+                acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c][st][r], bv[c][st][t], acc[r][t], 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) tot[r][t][q] += (double)acc[r][t][q];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int j = (wv + 4 * t + 16 * g) * 16 + col;
+      if (wv + 4 * t + 16 * g < ctn && j < n)
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) Ys[j * LDY + r0 + r * 16 + 4 * kq + q] = (float)tot[r][t][q];
+    }
+  }
+}
+
+// Rows 0 .. l-1 (rounded up to 16) in passes of at most 32 rows.
+template <int PF, int LDY>
+__device__ __forceinline__ void sketch_any(const BArgs& a, const float* A, int64_t lda, int m, int n, int l, float* Ys) {
+  for (int r0 = 0; r0 < l; r0 += 32) {
+    if (l - r0 > 16) sketch_rows<2, PF, LDY>(a, A, lda, m, n, r0, Ys);
+    else sketch_rows<1, PF, LDY>(a, A, lda, m, n, r0, Ys);
+  }
+}
+
+// ---- 3. T = S11^{-1} S12 (Section 4.1) -----------------------------------------
+// S11 is copied into an identity-padded KP x KP square Sp (column-major,
+// Sp[i*KP + q] = S(q, i)) with FP64 reciprocals of its diagonal, KP = 16, 32 or
+// 64 >= k, so every column's back-substitution runs over KP rows with no
+// per-row conditions: padded rows only ever meet zeros above the diagonal.
+// The right-hand side sits in 32 FP64 registers (static indices); with KP = 64
+// the lower 32 rows are solved and stored first, then folded into the upper 32.
+// Solutions overwrite the column in LDS, and T is written from there.
+template <int KP, int LDY>
+__device__ __forceinline__ void solve_rows(const float* Sp, const double* dinv, int base, double (&r)[32]) {
+  constexpr int R = KP < 32 ? KP : 32;
+#pragma unroll
+  for (int i = R - 1; i >= 0; --i) {
+    const double ti = r[i] * dinv[base + i];
+    r[i] = ti;
+#pragma unroll
+    for (int q = 0; q < i; ++q) r[q] -= (double)Sp[(base + i) * KP + base + q] * ti;
+  }
+}
+
+template <int KP, int LDY>
+__device__ __forceinline__ void solve_columns(float* Ys, const float* Sp, const double* dinv, int k, int n) {
+  constexpr int R = KP < 32 ? KP : 32;
+  for (int c = k + threadIdx.x; c < n; c += kBT) {
+    float* y = Ys + c * LDY;
+    double r[32];
+    if (KP == 64) {
+#pragma unroll
+      for (int i = 0; i < 32; ++i) r[i] = (double)y[32 + i];
+      solve_rows<KP, LDY>(Sp, dinv, 32, r);
+#pragma unroll
+      for (int i = 0; i < 32; ++i) y[32 + i] = (float)r[i];
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) r[i] = (double)y[i];
+    if (KP == 64) {
+      for (int i = 32; i < 64; ++i) {
+        const double ti = (double)y[i];
+#pragma unroll
+        for (int q = 0; q < 32; ++q) r[q] -= (double)Sp[i * KP + q] * ti;
+      }
+    }
+    solve_rows<KP, LDY>(Sp, dinv, 0, r);
+#pragma unroll
+    for (int i = 0; i < R; ++i) y[i] = (float)r[i];
+  }
+}
+
+template <int PF, int LDY>
+__global__ __launch_bounds__(kBT, (LDY < 64 ? 2 : 1)) void batched_id_kernel(BArgs a) {
+  // every region at a compile-time offset, the small ones first: unrolled accesses
+  // then fold their constant offsets (< 64 KiB) into the LDS instructions
+  extern __shared__ __align__(16) unsigned char bsm[];
+  constexpr int kSpBytes = (LDY - 1) * (LDY - 1) * (int)sizeof(float);
+  float* Sp = reinterpret_cast<float*>(bsm);
+  double* nu = reinterpret_cast<double*>(bsm + kSpBytes);
+  int* perm = reinterpret_cast<int*>(bsm + kSpBytes + kBNmax * sizeof(double));
+  int* cpos = reinterpret_cast<int*>(nu);          // reuses nu once the QR is done
+  float* Ys = reinterpret_cast<float*>(bsm + kSpBytes + kBNmax * (sizeof(double) + sizeof(int)));
+  __shared__ double vsh[kBLmax];
+  __shared__ double dinv[kBLmax];
+  __shared__ Best sb[kBT / 64];
+  __shared__ double ss[kBT / 64];
+  __shared__ double sbeta;
+  __shared__ int sblk;
+  const int tid = threadIdx.x, lane = tid & 63;
+  // rows of Y beyond a block's sketch width are read (and multiplied by zeros)
+  // by the padded back-substitution: keep them finite
+  for (int e = tid; e < kBNmax * LDY; e += kBT) Ys[e] = 0.0f;
+
+  for (;;) {
+    if (tid == 0) sblk = atomicAdd(a.queue, 1);
+    __syncthreads();
+    const int slot = sblk;
+    __syncthreads();
+    if (slot >= a.nblk) break;
+    const int b = a.order ? a.order[slot] : slot;
+    const int m = a.m[b], n = a.n[b];
+    if (m < 1 || m > a.mmax || n < 1 || n > a.nmax) {
+      if (tid == 0) {
+        a.k_out[b] = -1;
+        set_status(a.status, ST_BADINDEX);
+      }
+      continue;
+    }
+    const float* A = a.A[b];
+    const int64_t lda = a.lda[b];
+    const bool tolmode = a.kfix <= 0;
+    const int lcap = a.lcap;
+    int l = tolmode ? min(kBL0, lcap) : lcap;
+    int k = 0;
+    bool met = false;
+    for (;;) {
+      // ---- sketch ----------------------------------------------------------------
+      sketch_any<PF, LDY>(a, A, lda, m, n, l, Ys);
+      __syncthreads();
+      for (int c = tid; c < n; c += kBT) {
+        double s = 0.0;
+        for (int i = 0; i < l; ++i) {
+          const double y = (double)Ys[c * LDY + i];
+          s += y * y;
+        }
+        nu[c] = s;
+        perm[c] = c;
+      }
+      // |Y|_F^2 and the largest initial column norm
+      Best b0{-1.0, 0x7fffffff, 0};
+      double y0 = 0.0;
+      for (int c = tid; c < n; c += kBT) {
+        y0 += nu[c];
+        Best cb{nu[c], c, c};
+        if (beats(cb, b0)) b0 = cb;
+      }
+      b0 = block_best_sum(b0, y0, sb, ss);
+      const double nu0max = b0.v;
+      const int cap = min(tolmode ? l - a.p : a.kfix, n);
+      // ---- pivoted QR ------------------------------------------------------------
+      int j = 0;
+      met = !tolmode;
+      for (;;) {
+        Best bb{-1.0, 0x7fffffff, 0};
+        double rs = 0.0;
+        for (int c = j + tid; c < n; c += kBT) {
+          rs += nu[c];
+          Best cb{nu[c], perm[c], c};
+          if (beats(cb, bb)) bb = cb;
+        }
+        bb = block_best_sum(bb, rs, sb, ss);
+        if (tolmode && rs <= a.tol * a.tol * y0) { met = true; break; }
+        if (j >= cap) break;
+        if (bb.v <= a.rank_tol * a.rank_tol * nu0max) { met = true; break; }
+        // swap positions j and the pivot
+        const int pp = bb.pos;
+        if (pp != j) {
+          for (int i = tid; i < l; i += kBT) {
+            const float t0 = Ys[j * LDY + i];
+            Ys[j * LDY + i] = Ys[pp * LDY + i];
+            Ys[pp * LDY + i] = t0;
+          }
+          if (tid == 0) {
+            const double tn = nu[j]; nu[j] = nu[pp]; nu[pp] = tn;
+            const int tp = perm[j]; perm[j] = perm[pp]; perm[pp] = tp;
+          }
+          __syncthreads();
+        }
+        // Householder reflector of Y(j:l, j) (wave 0, one lane per row)
+        if (tid < 64) {
+          const int i = j + lane;
+          const double x = i < l ? (double)Ys[j * LDY + i] : 0.0;
+          double s2 = x * x;
+          for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, 64);
+          const double x0 = __shfl(x, 0, 64);
+          const double normx = sqrt(s2);
+          const double alpha = x0 >= 0.0 ? -normx : normx;
+          const double v = lane == 0 ? x0 - alpha : x;
+          double vv = v * v;
+          for (int o = 32; o > 0; o >>= 1) vv += __shfl_xor(vv, o, 64);
+          if (i < l) {
+            vsh[lane] = v;
+            Ys[j * LDY + i] = lane == 0 ? (float)alpha : 0.0f;
+          }
+          if (lane == 0) sbeta = vv > 0.0 ? 2.0 / vv : 0.0;
+        }
+        __syncthreads();
+        const double beta = sbeta;
+        for (int c = j + 1 + tid; c < n; c += kBT) {
+          float* y = Ys + c * LDY;
+          double w = 0.0;
+          for (int i = j; i < l; ++i) w += vsh[i - j] * (double)y[i];
+          w *= beta;
+          double s = 0.0;
+          for (int i = j; i < l; ++i) {
+            const float yn = (float)((double)y[i] - w * vsh[i - j]);
+            y[i] = yn;
+            if (i > j) s += (double)yn * (double)yn;
+          }
+          nu[c] = s;
+        }
+        __syncthreads();
+        ++j;
+      }
+      k = j;
+      if (met || !tolmode || l >= lcap) break;
+      l = min(2 * l, lcap);
+      __syncthreads();
+    }
+    if (!met && tid == 0) set_status(a.status, ST_RANKCAP);
+    __syncthreads();
+    // ---- T = S11^{-1} S12, written with J = [pivots, the rest ascending] ----------
+    const int KP = k <= 16 ? 16 : (k <= 32 ? 32 : 64);
+    for (int e = tid; e < KP * KP; e += kBT) {
+      const int i = e / KP, q = e % KP;
+      Sp[e] = i < k ? (q <= i ? Ys[i * LDY + q] : 0.0f) : (q == i ? 1.0f : 0.0f);
+    }
+    for (int i = tid; i < KP; i += kBT) dinv[i] = i < k ? 1.0 / (double)Ys[i * LDY + i] : 1.0;
+    int* J = a.J[b];
+    for (int c = tid; c < n; c += kBT) {
+      const int orig = perm[c];
+      if (c < k) {
+        J[c] = orig;
+      } else {
+        int below = 0;
+        for (int q = 0; q < k; ++q) below += perm[q] < orig ? 1 : 0;
+        const int tc = orig - below;   // rank among the unselected columns
+        J[k + tc] = orig;
+        cpos[tc] = c;
+      }
+    }
+    __syncthreads();
+    if (k > 0) {
+      if (KP == 16) solve_columns<16, LDY>(Ys, Sp, dinv, k, n);
+      else if (KP == 32) solve_columns<32, LDY>(Ys, Sp, dinv, k, n);
+      else solve_columns<64, LDY>(Ys, Sp, dinv, k, n);
+    }
+    __syncthreads();
+    {
+      float* T = a.T[b];
+      const int64_t ldt = a.ldt[b];
+      const int nt = n - k;
+      for (int e = tid; e < k * nt; e += kBT) {
+        const int i = e / nt, tc = e % nt;
+        T[(int64_t)i * ldt + tc] = Ys[cpos[tc] * LDY + i];
+      }
+    }
+    if (tid == 0) a.k_out[b] = k;
+    __syncthreads();
+  }
+}
+
+// Processing order: block indices by m_b n_b, largest first (ties: smaller index
+// first), by a bitonic sort of 64-bit keys in LDS (one workgroup, nblk <= 8192).
+constexpr int kSortMax = 8192;
+__global__ __launch_bounds__(1024) void batch_order_kernel(const int* m, const int* n, int nblk, int* order) {
+  __shared__ unsigned long long key[kSortMax];
+  int P = 1;
+  while (P < nblk) P <<= 1;
+  for (int i = threadIdx.x; i < P; i += 1024) {
+    unsigned long long kv = ~0ull;
+    if (i < nblk) {
+      // 43 bits of (2^43 - 1 - m n) above 20 bits of index: larger blocks first
+      const unsigned long long w = (unsigned long long)max(m[i], 0) * (unsigned long long)max(n[i], 0);
+      const unsigned long long w43 = (1ull << 43) - 1ull;
+      kv = ((w43 - min(w, w43)) << 20) | (unsigned long long)i;
+    }
+    key[i] = kv;
+  }
+  __syncthreads();
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < P; i += 1024) {
+        const int pj = i ^ stride;
+        if (pj > i) {
+          const bool up = (i & size) == 0;
+          const unsigned long long x = key[i], y = key[pj];
+          if ((x > y) == up) { key[i] = y; key[pj] = x; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < nblk; i += 1024) order[i] = (int)(key[i] & 0xFFFFFull);
+}
+
+template <int PF>
+const void* kernel_pf(int ldy) {
+  switch (ldy) {
+    case 17: return (const void*)batched_id_kernel<PF, 17>;
+    case 33: return (const void*)batched_id_kernel<PF, 33>;
+    default: return (const void*)batched_id_kernel<PF, 65>;
+  }
+}
+const void* kernel_for(int pf, int ldy) { return pf == 0 ? kernel_pf<1>(ldy) : kernel_pf<2>(ldy); }
+
+}  // namespace
+
+// Rows of the LDS copy of Y (and columns of the stored Omega^T): 16, 32 or 64, so
+// that the padded back-substitution (order 16, 32 or 64 >= k) stays inside a column.
+int batched_ldom(int lcap) { return lcap <= 16 ? 16 : (lcap <= 32 ? 32 : 64); }
+int batched_mpad(int mmax) { return (int)round_up(std::max(mmax, 1), 4); }
+int batched_max_width() { return kBNmax; }
+int batched_max_sketch() { return kBLmax; }
+
+size_t batched_lds_bytes(int lcap, int nmax) {
+  (void)nmax;
+  const int ldom = batched_ldom(lcap);
+  const int ldy = ldom + 1;
+  return (((size_t)kBNmax * ldy * sizeof(float) + 15) & ~(size_t)15) + (size_t)kBNmax * (sizeof(double) + sizeof(int)) +
+         (size_t)ldom * ldom * sizeof(float);
+}
+
+// Variant v: sketch prefetch depth PF = 1 + v % 2 (16-k chunks of loads issued together);
+// workgroups per CU = 1 + (v / 2) % 2 (when LDS allows two); largest-first
+// processing order when v / 4 == 0. Results do not depend on the variant.
+int batched_num_variants() { return 8; }
+
+hipError_t batched_launch(const BatchedArgs& ba, int variant, int num_cus, hipStream_t stream) {
+  if (ba.nblk <= 0) return hipSuccess;
+  if (ba.nblk > (1 << 20) || ba.nmax > kBNmax || ba.lcap > kBLmax || ba.lcap < 1) return hipErrorInvalidValue;
+  BArgs a{};
+  a.nblk = ba.nblk;
+  a.m = ba.m; a.n = ba.n; a.A = ba.A; a.lda = ba.lda; a.J = ba.J; a.T = ba.T; a.ldt = ba.ldt; a.k_out = ba.k_out;
+  a.omt = ba.omt; a.ldom = batched_ldom(ba.lcap);
+  a.mmax = ba.mmax; a.nmax = ba.nmax; a.lcap = ba.lcap; a.p = ba.p; a.kfix = ba.kfix;
+  a.tol = ba.tol; a.rank_tol = ba.rank_tol;
+  a.queue = ba.queue; a.status = ba.status;
+  a.ldy = a.ldom + 1;
+  const int pf = variant % 2, occ_pick = (variant / 2) % 2, lpt = (variant / 4) == 0;
+  hipError_t e = zero_launch(ba.queue, sizeof(int), stream);
+  if (e != hipSuccess) return e;
+  a.order = nullptr;
+  if (lpt && ba.nblk <= kSortMax && ba.order) {
+    hipLaunchKernelGGL(batch_order_kernel, dim3(1), dim3(1024), 0, stream, ba.m, ba.n, ba.nblk, ba.order);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    a.order = ba.order;
+  }
+  const size_t lds = batched_lds_bytes(ba.lcap, ba.nmax);
+  const int per_cu = (occ_pick == 1 && 2 * lds <= 160 * 1024) ? 2 : 1;
+  const int grid = std::max(1, std::min(ba.nblk, per_cu * num_cus));
+  const void* fn = kernel_for(pf, a.ldy);
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  void* args[] = {&a};
+  return hipLaunchKernel(fn, dim3(grid), dim3(kBT), args, lds, stream);
+}
+
+}  // namespace idcur

@@ -32,6 +32,10 @@ struct idcur_ctx {
   };
   std::vector<Mark> marks;
   std::vector<hipEvent_t> pool;
+  // batched launch variant per (size class of the batch): from the autotuner,
+  // or forced with idcur_id_col_batched_set_variant (>= 0)
+  std::map<std::vector<int64_t>, int> batched_tuned;
+  int batched_forced = -1;
   hipEvent_t get_event() {
     if (!pool.empty()) {
       hipEvent_t e = pool.back();
@@ -824,6 +828,141 @@ idcur_status run_bwd(idcur_ctx* ctx, int dtype, int64_t m, int64_t n, const void
   }
 }
 
+// ---------------------------------------------------------------------------
+// Batched adaptive-rank column ID (one persistent launch, batched.hip)
+// ---------------------------------------------------------------------------
+struct BatchedCall {
+  int nblk, mmax, nmax;
+  const int32_t* m; const int32_t* n; const void* const* A; const int64_t* lda;
+  int32_t* k_out; int32_t* const* J; void* const* T; const int64_t* ldt;
+};
+
+void batched_validate(idcur_ctx* ctx, int dtype, const BatchedCall& c, const idcur_opts* o) {
+  if (!ctx) throw Fail{IDCUR_EINVAL};
+  if (!o) fail(ctx, IDCUR_EINVAL, "opts is NULL");
+  if (dtype != IDCUR_F32) fail(ctx, IDCUR_EDTYPE, "the batched ID takes FP32 blocks");
+  if (o->prec != IDCUR_PREC_NATIVE) fail(ctx, IDCUR_EDTYPE, "the batched ID sketches in FP32");
+  if (c.nblk < 0 || c.nblk > (1 << 20)) fail(ctx, IDCUR_EINVAL, "nblk must be in [0, 2^20]");
+  if (c.mmax < 1 || c.mmax > (1 << 24)) fail(ctx, IDCUR_EINVAL, "mmax must be in [1, 2^24]");
+  if (c.nmax < 1 || c.nmax > batched_max_width()) fail(ctx, IDCUR_EINVAL, "nmax must be in [1, 512]");
+  if (o->p < 1) fail(ctx, IDCUR_EINVAL, "the batched ID needs oversampling p >= 1");
+  if (o->q != 0) fail(ctx, IDCUR_EINVAL, "the batched ID takes no power steps (q = 0)");
+  if (o->k < 0) fail(ctx, IDCUR_EINVAL, "k must be >= 0");
+  if (o->k == 0) {
+    if (!(o->tol > 0.0) || !std::isfinite(o->tol)) fail(ctx, IDCUR_EINVAL, "tolerance mode needs tol > 0");
+    if (o->kmax < 1) fail(ctx, IDCUR_EINVAL, "tolerance mode needs kmax >= 1");
+  }
+  const int kcap = o->k > 0 ? o->k : o->kmax;
+  if ((int64_t)kcap + o->p > batched_max_sketch()) fail(ctx, IDCUR_EINVAL, "k (kmax) + p must be <= 64");
+  if (o->rank_tol < 0 || !std::isfinite(o->rank_tol)) fail(ctx, IDCUR_EINVAL, "rank_tol must be >= 0");
+}
+
+std::vector<int64_t> batched_key(const BatchedCall& c, const idcur_opts& o) {
+  int lg = 0;
+  while ((1 << lg) < c.nblk) ++lg;
+  return {lg, c.mmax, c.nmax, (o.k > 0 ? o.k : o.kmax) + o.p, o.k > 0 ? 1 : 0};
+}
+
+// Carves the workspace and (unless dry) enqueues: Omega^T, then the launch.
+void batched_run(const Ctx& x, const BatchedCall& c, const idcur_opts& o, int variant) {
+  const int kcap = o.k > 0 ? o.k : o.kmax;
+  const int lcap = kcap + o.p;
+  const int ldom = batched_ldom(lcap), mpad = batched_mpad(c.mmax);
+  float* omt = static_cast<float*>(x.ar->take((size_t)mpad * ldom * sizeof(float)));
+  int* order = static_cast<int*>(x.ar->take((size_t)std::max(c.nblk, 1) * sizeof(int)));
+  int* queue = static_cast<int*>(x.ar->take(256));
+  if (x.dry || c.nblk == 0) return;
+  Stage st(x, "batched");
+  x.check(zero_launch(omt, (size_t)mpad * ldom * sizeof(float), x.s), "zero Omega");
+  if (o.omega)
+    x.check(copy2d_launch(IDCUR_F32, lcap, c.mmax, o.omega, c.mmax, 1, omt, 1, ldom, x.s), "Omega copy");
+  else
+    x.check(gaussian_launch(IDCUR_F32, lcap, c.mmax, o.seed, 0, omt, 1, ldom, x.s), "Omega");
+  BatchedArgs a{};
+  a.nblk = c.nblk;
+  a.m = c.m; a.n = c.n;
+  a.A = reinterpret_cast<const float* const*>(c.A); a.lda = c.lda;
+  a.J = c.J; a.T = reinterpret_cast<float* const*>(c.T); a.ldt = c.ldt;
+  a.k_out = c.k_out;
+  a.omt = omt;
+  a.mmax = c.mmax; a.nmax = c.nmax; a.lcap = lcap; a.p = o.p; a.kfix = o.k;
+  a.tol = o.k > 0 ? 0.0 : o.tol;
+  // default sqrt(l_cap) u32: a pivot column at that relative norm is rounding
+  // noise of an l-row FP32 column; a coarser test would stop tolerance mode
+  // ahead of the Frobenius rule on smooth kernels (pivot norms of a few 1e-6
+  // at tol = 1e-6 are still well resolved in FP32)
+  a.rank_tol = o.rank_tol > 0 ? o.rank_tol : std::sqrt((double)lcap) * kU32;
+  a.order = order; a.queue = queue; a.status = x.c->dstatus;
+  x.check(batched_launch(a, variant, x.c->num_cus, x.s), "batched launch");
+}
+
+int batched_default_variant() { return 2; }   // prefetch 1, two workgroups per CU, largest first
+
+idcur_status run_batched(idcur_ctx* ctx, int dtype, const BatchedCall& c, const idcur_opts* opts, void* ws,
+                         size_t ws_bytes, size_t* bytes_only, int tune, int* variant_out) {
+  try {
+    batched_validate(ctx, dtype, c, opts);
+    Arena dry;
+    Ctx xd{ctx, ctx->stream, true, &dry};
+    batched_run(xd, c, *opts, 0);
+    if (bytes_only) {
+      *bytes_only = dry.off + 256;
+      return IDCUR_OK;
+    }
+    if (c.nblk > 0 && (!c.m || !c.n || !c.A || !c.lda || !c.k_out || !c.J || !c.T || !c.ldt))
+      fail(ctx, IDCUR_EINVAL, "null array");
+    if (!ws || ws_bytes < dry.off) fail(ctx, IDCUR_EWORKSPACE, "workspace missing or too small");
+    hipcheck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    Arena ar;
+    ar.dry = false;
+    ar.base = static_cast<char*>(ws);
+    ar.cap = ws_bytes;
+    Ctx x{ctx, ctx->stream, false, &ar};
+    const auto key = batched_key(c, *opts);
+    if (!tune) {
+      int v = ctx->batched_forced;
+      if (v < 0) {
+        auto it = ctx->batched_tuned.find(key);
+        v = it != ctx->batched_tuned.end() ? it->second : batched_default_variant();
+      }
+      batched_run(x, c, *opts, v);
+      if (variant_out) *variant_out = v;
+      return IDCUR_OK;
+    }
+    // autotune: time every variant (two untimed launches, then three timed), keep
+    // the fastest for this size class, and leave its results in the outputs
+    hipEvent_t e0 = ctx->get_event(), e1 = ctx->get_event();
+    if (!e0 || !e1) fail(ctx, IDCUR_EHIP, "event creation failed");
+    int best = batched_default_variant();
+    float best_ms = 0.0f;
+    for (int v = 0; v < batched_num_variants(); ++v) {
+      for (int r = 0; r < 2; ++r) {
+        ar.off = 0;
+        batched_run(x, c, *opts, v);
+      }
+      hipcheck(ctx, hipEventRecord(e0, ctx->stream), "event");
+      for (int r = 0; r < 3; ++r) {
+        ar.off = 0;
+        batched_run(x, c, *opts, v);
+      }
+      hipcheck(ctx, hipEventRecord(e1, ctx->stream), "event");
+      hipcheck(ctx, hipEventSynchronize(e1), "event sync");
+      float ms = 0.0f;
+      hipcheck(ctx, hipEventElapsedTime(&ms, e0, e1), "event time");
+      if (v == 0 || ms < best_ms) { best_ms = ms; best = v; }
+    }
+    ctx->pool.push_back(e0);
+    ctx->pool.push_back(e1);
+    ctx->batched_tuned[key] = best;
+    ar.off = 0;
+    batched_run(x, c, *opts, best);
+    if (variant_out) *variant_out = best;
+    return IDCUR_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  }
+}
+
 idcur_status run(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const void* A, int64_t lda,
                  const idcur_opts* opts, void* ws, size_t ws_bytes, const Outs& out) {
   try {
@@ -1058,6 +1197,53 @@ idcur_status idcur_id_col_backward(idcur_ctx* ctx, int32_t dtype, int64_t m, int
   idcur::BwdArgs b;
   b.omega = omega; b.l = l; b.J = J; b.k = k; b.T = T; b.ldt = ldt; b.scale = scale; b.dA = dA; b.ldda = ldda;
   return idcur::run_bwd(ctx, dtype, m, n, A, lda, b, ws, ws_bytes, nullptr);
+}
+
+idcur_status idcur_id_col_batched_workspace_bytes(idcur_ctx* ctx, int32_t dtype, int32_t nblk, int32_t mmax,
+                                                  int32_t nmax, const idcur_opts* opts, size_t* bytes) {
+  if (!bytes) return IDCUR_EINVAL;
+  idcur::BatchedCall c{};
+  c.nblk = nblk; c.mmax = mmax; c.nmax = nmax;
+  return idcur::run_batched(ctx, dtype, c, opts, nullptr, 0, bytes, 0, nullptr);
+}
+
+static idcur::BatchedCall batched_call(int32_t nblk, int32_t mmax, int32_t nmax, const int32_t* m, const int32_t* n,
+                                       const void* const* A, const int64_t* lda, int32_t* k_out, int32_t* const* J,
+                                       void* const* T, const int64_t* ldt) {
+  idcur::BatchedCall c{};
+  c.nblk = nblk; c.mmax = mmax; c.nmax = nmax;
+  c.m = m; c.n = n; c.A = A; c.lda = lda; c.k_out = k_out; c.J = J; c.T = T; c.ldt = ldt;
+  return c;
+}
+
+idcur_status idcur_id_col_batched(idcur_ctx* ctx, int32_t dtype, int32_t nblk, int32_t mmax, int32_t nmax,
+                                  const int32_t* m, const int32_t* n, const void* const* A, const int64_t* lda,
+                                  const idcur_opts* opts, void* ws, size_t ws_bytes, int32_t* k_out, int32_t* const* J,
+                                  void* const* T, const int64_t* ldt) {
+  return idcur::run_batched(ctx, dtype, batched_call(nblk, mmax, nmax, m, n, A, lda, k_out, J, T, ldt), opts, ws,
+                            ws_bytes, nullptr, 0, nullptr);
+}
+
+idcur_status idcur_id_col_batched_autotune(idcur_ctx* ctx, int32_t dtype, int32_t nblk, int32_t mmax, int32_t nmax,
+                                           const int32_t* m, const int32_t* n, const void* const* A,
+                                           const int64_t* lda, const idcur_opts* opts, void* ws, size_t ws_bytes,
+                                           int32_t* k_out, int32_t* const* J, void* const* T, const int64_t* ldt,
+                                           int32_t* variant) {
+  int v = -1;
+  const idcur_status st = idcur::run_batched(ctx, dtype, batched_call(nblk, mmax, nmax, m, n, A, lda, k_out, J, T, ldt),
+                                             opts, ws, ws_bytes, nullptr, 1, &v);
+  if (variant) *variant = v;
+  return st;
+}
+
+idcur_status idcur_id_col_batched_set_variant(idcur_ctx* ctx, int32_t variant) {
+  if (!ctx) return IDCUR_EINVAL;
+  if (variant < -1 || variant >= idcur::batched_num_variants()) {
+    ctx->err = "variant out of range";
+    return IDCUR_EINVAL;
+  }
+  ctx->batched_forced = variant;
+  return IDCUR_OK;
 }
 
 idcur_status idcur_gaussian(idcur_ctx* ctx, int32_t dtype, int64_t rows, int64_t cols, uint64_t seed, uint64_t stream,

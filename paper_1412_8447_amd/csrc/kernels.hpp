@@ -133,6 +133,31 @@ hipError_t fp16_scale_launch(int64_t rows, int64_t cols, const float* A, int64_t
                              hipStream_t stream);
 
 // ---------------------------------------------------------------------------
+// Batched adaptive-rank column ID (batched.hip): one persistent launch over
+// nblk independent FP32 blocks. All per-block arrays are device arrays.
+// ---------------------------------------------------------------------------
+struct BatchedArgs {
+  int nblk;
+  const int* m; const int* n;
+  const float* const* A; const int64_t* lda;
+  int* const* J; float* const* T; const int64_t* ldt;
+  int* k_out;
+  const float* omt;        // Omega^T: batched_mpad(mmax) x batched_ldom(lcap), zero outside
+  int mmax, nmax, lcap, p, kfix;
+  double tol, rank_tol;
+  int* order;              // nblk ints of scratch for the processing order (or NULL)
+  int* queue;              // one int of scratch (zeroed by the launch)
+  int* status;
+};
+int batched_ldom(int lcap);
+int batched_mpad(int mmax);
+int batched_max_width();
+int batched_max_sketch();
+size_t batched_lds_bytes(int lcap, int nmax);
+int batched_num_variants();
+hipError_t batched_launch(const BatchedArgs& a, int variant, int num_cus, hipStream_t stream);
+
+// ---------------------------------------------------------------------------
 // Cholesky factor and triangular inverse (chol.hip), FP64, c <= 256, one workgroup
 // (larger c: the blocked driver in host.cpp).
 //   mode 0: G = L L^T (G(i,j) = G[i*gr + j*gc], optional diagonal shift

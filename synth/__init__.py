@@ -33,6 +33,7 @@ __all__ = [
     "sigma_logspace",
     "kernel_block",
     "kernel_block_sizes",
+    "kernel_blocks_torch",
     "CONFIGS",
     "Config",
 ]
@@ -136,6 +137,27 @@ def kernel_block(mb: int, nb: int, seed: int, block_id: int, dtype=np.float64) -
     y[:, 0] += 4.0
     d = np.sqrt(((x[:, None, :] - y[None, :, :]) ** 2).sum(axis=2))
     return np.ascontiguousarray((1.0 / d).astype(dtype))
+
+
+def kernel_blocks_torch(nblk: int, seed: int, device, lo: int = 64, hi: int = 512):
+    """The blocks of :func:`kernel_block` for block ids 0..nblk-1 with the sizes of
+    :func:`kernel_block_sizes`: points drawn with NumPy exactly as there, the
+    distances formed with torch on ``device`` in FP64 (same formula), returned as
+    a list of contiguous FP32 device tensors."""
+    import torch
+
+    ms, ns = kernel_block_sizes(nblk, seed, lo, hi)
+    out = []
+    for b in range(nblk):
+        g = rng(seed * 1_000_003 + 17 * b + 1)
+        x = g.random((int(ms[b]), 3)) - 0.5
+        y = g.random((int(ns[b]), 3)) - 0.5
+        y[:, 0] += 4.0
+        xt = torch.as_tensor(x, device=device)
+        yt = torch.as_tensor(y, device=device)
+        d = ((xt[:, None, :] - yt[None, :, :]) ** 2).sum(dim=2).sqrt()
+        out.append((1.0 / d).to(torch.float32).contiguous())
+    return out
 
 
 # ----------------------------------------------------------------------------
