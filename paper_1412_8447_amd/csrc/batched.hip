@@ -6,8 +6,10 @@
 //   1. Y = Omega(:l, :m_b) A_b on the FP32 matrix cores (v_mfma_f32_16x16x4f32,
 //      FP32 sums over 16-k chunks added in FP64), written straight into LDS
 //      (column-major, odd column stride);
-//   2. column-pivoted Householder QR of Y in LDS with the column norms
-//      recomputed exactly after every update; before each step the residual
+//   2. column-pivoted Householder QR of Y with each thread's two columns in
+//      registers (columns stay in place; a pivot list records the order), the
+//      pivot column shared through LDS, every wave forming the reflector itself,
+//      and the column norms recomputed exactly after every update; before each step the residual
 //      |Y_res|_F is compared with tol |Y|_F; at most l - p steps are taken;
 //      when the tolerance is not met, l doubles (up to l_cap = kmax + p) and
 //      the block is sketched and factored again;
@@ -84,16 +86,85 @@ __device__ Best block_best_sum(Best b, double& s, Best* sb, double* ss) {
 // cores in FP32 over chunks of 16 consecutive k (four 16x16x4 steps) and the
 // chunks are added in FP64: at the tolerances this path serves (1e-6 on smooth
 // kernels, about 16 u32) FP32 sums over all m_b terms would put rounding noise
-// of the tolerance's own size into Y. PF chunks of loads are issued together.
-template <int RT, int PF, int LDY>
+// of the tolerance's own size into Y. The next chunk's operands are loaded
+// while the current chunk is multiplied (two register buffers); rows and
+// columns past the block are read at a clamped in-range address and zeroed.
+template <int RT>
+struct Chunk {
+  float av[4][RT];
+  float bv[4][4];
+};
+
+// A load whose result is always used (so the compiler cannot sink it into a
+// branch on the validity test, which serialises the loads behind full waits),
+// from the global address space, zeroed by a bit mask when out of range.
+typedef const __attribute__((address_space(1))) float gfloat;
+__device__ __forceinline__ float ld_keep(const float* p, unsigned keep) {
+  const float v = *(gfloat*)p;
+  return __builtin_bit_cast(float, __builtin_bit_cast(unsigned, v) & keep);
+}
+
+template <int RT>
+__device__ __forceinline__ void load_chunk(Chunk<RT>& ch, const BArgs& a, const float* __restrict__ A, int64_t lda,
+                                           int m, int c, int kq, int ocol, const int (&jt)[4], const bool (&jv)[4]) {
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int k = 16 * c + 4 * st + kq;
+    const unsigned kk = k < m ? ~0u : 0u;
+    const int kc = k < m ? k : m - 1;
+    const float* orow = a.omt + (int64_t)kc * a.ldom + ocol;
+    const float* arow = A + (int64_t)kc * lda;
+#pragma unroll
+    for (int r = 0; r < RT; ++r) ch.av[st][r] = ld_keep(orow + r * 16, kk);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) ch.bv[st][t] = ld_keep(arow + jt[t], kk & (jv[t] ? ~0u : 0u));
+  }
+}
+
+template <int RT>
+__device__ __forceinline__ void mul_chunk(const Chunk<RT>& ch, double (&tot)[RT][4][4], int ntile) {
+  f32x4 acc[RT][4];
+#pragma unroll
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[r][t] = f32x4{0, 0, 0, 0};
+#pragma unroll
+  for (int st = 0; st < 4; ++st)
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (t < ntile)
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+          acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ch.av[st][r], ch.bv[st][t], acc[r][t], 0, 0, 0);
+#pragma unroll
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) tot[r][t][q] += (double)acc[r][t][q];
+}
+
+template <int RT, int LDY>
 __device__ __forceinline__ void sketch_rows(const BArgs& a, const float* __restrict__ A, int64_t lda, int m, int n,
                                             int r0, float* Ys) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // the wave index is uniform within a wave: say so, so that the tile guards
+  // below are scalar branches and not masked lanes with full waits
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int kq = lane >> 4, col = lane & 15;
   const int ctn = (n + 15) >> 4;
-  const int mq = (m + 3) & ~3;
+  const int nch = (m + 15) >> 4;
   for (int g = 0; g < 2; ++g) {
     if (wv + 16 * g >= ctn) break;   // this wave has no tile in this pass
+    // tiles of this wave in this pass: t < ntile (wave-uniform)
+    const int ntile = min(4, (ctn - (wv + 16 * g) + 3) >> 2);
+    int jt[4];
+    bool jv[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int j = (wv + 4 * t + 16 * g) * 16 + col;
+      jv[t] = j < n;
+      jt[t] = jv[t] ? j : n - 1;
+    }
     double tot[RT][4][4];
 #pragma unroll
     for (int r = 0; r < RT; ++r)
@@ -101,53 +172,22 @@ __device__ __forceinline__ void sketch_rows(const BArgs& a, const float* __restr
       for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int q = 0; q < 4; ++q) tot[r][t][q] = 0.0;
-    for (int k0 = 0; k0 < mq; k0 += 16 * PF) {
-      float av[PF][4][RT], bv[PF][4][4];
-#pragma unroll
-      for (int c = 0; c < PF; ++c)
-#pragma unroll
-        for (int st = 0; st < 4; ++st) {
-          const int k = k0 + 16 * c + 4 * st + kq;
-          const bool kin = k < m;
-#pragma unroll
-          for (int r = 0; r < RT; ++r) av[c][st][r] = kin ? a.omt[(int64_t)k * a.ldom + r0 + r * 16 + col] : 0.0f;
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int j = (wv + 4 * t + 16 * g) * 16 + col;
-            bv[c][st][t] = (kin && j < n) ? A[(int64_t)k * lda + j] : 0.0f;
-          }
-        }
-#pragma unroll
-      for (int c = 0; c < PF; ++c) {
-        f32x4 acc[RT][4];
-#pragma unroll
-        for (int r = 0; r < RT; ++r)
-#pragma unroll
-          for (int t = 0; t < 4; ++t) acc[r][t] = f32x4{0, 0, 0, 0};
-#pragma unroll
-        for (int st = 0; st < 4; ++st)
-#pragma unroll
-          for (int t = 0; t < 4; ++t)
-            if (wv + 4 * t + 16 * g < ctn)
-#pragma unroll
-              for (int r = 0; r < RT; ++r)
-                acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c][st][r], bv[c][st][t], acc[r][t], 0, 0, 0);
-#pragma unroll
-        for (int r = 0; r < RT; ++r)
-#pragma unroll
-          for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) tot[r][t][q] += (double)acc[r][t][q];
-      }
+    Chunk<RT> c0, c1;
+    load_chunk<RT>(c0, a, A, lda, m, 0, kq, r0 + col, jt, jv);
+    for (int c = 0; c < nch; c += 2) {
+      if (c + 1 < nch) load_chunk<RT>(c1, a, A, lda, m, c + 1, kq, r0 + col, jt, jv);
+      mul_chunk<RT>(c0, tot, ntile);
+      if (c + 1 >= nch) break;
+      if (c + 2 < nch) load_chunk<RT>(c0, a, A, lda, m, c + 2, kq, r0 + col, jt, jv);
+      mul_chunk<RT>(c1, tot, ntile);
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const int j = (wv + 4 * t + 16 * g) * 16 + col;
-      if (wv + 4 * t + 16 * g < ctn && j < n)
+      if (t < ntile && jv[t])
 #pragma unroll
         for (int r = 0; r < RT; ++r)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) Ys[j * LDY + r0 + r * 16 + 4 * kq + q] = (float)tot[r][t][q];
+          for (int q = 0; q < 4; ++q) Ys[jt[t] * LDY + r0 + r * 16 + 4 * kq + q] = (float)tot[r][t][q];
     }
   }
 }
@@ -156,8 +196,8 @@ __device__ __forceinline__ void sketch_rows(const BArgs& a, const float* __restr
 template <int PF, int LDY>
 __device__ __forceinline__ void sketch_any(const BArgs& a, const float* A, int64_t lda, int m, int n, int l, float* Ys) {
   for (int r0 = 0; r0 < l; r0 += 32) {
-    if (l - r0 > 16) sketch_rows<2, PF, LDY>(a, A, lda, m, n, r0, Ys);
-    else sketch_rows<1, PF, LDY>(a, A, lda, m, n, r0, Ys);
+    if (l - r0 > 16) sketch_rows<2, LDY>(a, A, lda, m, n, r0, Ys);
+    else sketch_rows<1, LDY>(a, A, lda, m, n, r0, Ys);
   }
 }
 
@@ -182,9 +222,10 @@ __device__ __forceinline__ void solve_rows(const float* Sp, const double* dinv, 
 }
 
 template <int KP, int LDY>
-__device__ __forceinline__ void solve_columns(float* Ys, const float* Sp, const double* dinv, int k, int n) {
+__device__ __forceinline__ void solve_columns(float* Ys, const float* Sp, const double* dinv, const int* ord, int n) {
   constexpr int R = KP < 32 ? KP : 32;
-  for (int c = k + threadIdx.x; c < n; c += kBT) {
+  for (int c = threadIdx.x; c < n; c += kBT) {
+    if (ord[c] >= 0) continue;   // a selected column
     float* y = Ys + c * LDY;
     double r[32];
     if (KP == 64) {
@@ -211,20 +252,20 @@ __device__ __forceinline__ void solve_columns(float* Ys, const float* Sp, const 
 
 template <int PF, int LDY>
 __global__ __launch_bounds__(kBT, (LDY < 64 ? 2 : 1)) void batched_id_kernel(BArgs a) {
+  constexpr int LR = LDY - 1;   // rows kept per column (>= the sketch width)
   // every region at a compile-time offset, the small ones first: unrolled accesses
   // then fold their constant offsets (< 64 KiB) into the LDS instructions
   extern __shared__ __align__(16) unsigned char bsm[];
-  constexpr int kSpBytes = (LDY - 1) * (LDY - 1) * (int)sizeof(float);
+  constexpr int kSpBytes = LR * LR * (int)sizeof(float);
   float* Sp = reinterpret_cast<float*>(bsm);
-  double* nu = reinterpret_cast<double*>(bsm + kSpBytes);
-  int* perm = reinterpret_cast<int*>(bsm + kSpBytes + kBNmax * sizeof(double));
-  int* cpos = reinterpret_cast<int*>(nu);          // reuses nu once the QR is done
-  float* Ys = reinterpret_cast<float*>(bsm + kSpBytes + kBNmax * (sizeof(double) + sizeof(int)));
-  __shared__ double vsh[kBLmax];
+  int* ord = reinterpret_cast<int*>(bsm + kSpBytes);    // pivot step of a column, -1 if unselected
+  int* cpos = ord + kBNmax;                               // column of the tc-th unselected column
+  float* Ys = reinterpret_cast<float*>(bsm + kSpBytes + 2 * kBNmax * sizeof(int));
+  __shared__ float xcol[kBLmax];
+  __shared__ int piv[kBLmax];
   __shared__ double dinv[kBLmax];
   __shared__ Best sb[kBT / 64];
   __shared__ double ss[kBT / 64];
-  __shared__ double sbeta;
   __shared__ int sblk;
   const int tid = threadIdx.x, lane = tid & 63;
   // rows of Y beyond a block's sketch width are read (and multiplied by zeros)
@@ -253,26 +294,32 @@ __global__ __launch_bounds__(kBT, (LDY < 64 ? 2 : 1)) void batched_id_kernel(BAr
     int l = tolmode ? min(kBL0, lcap) : lcap;
     int k = 0;
     bool met = false;
+    // this thread's columns c = tid and tid + 256, kept in registers through the
+    // pivoted QR; columns never move (the pivot list records the order)
+    float y[2][LR];
     for (;;) {
       // ---- sketch ----------------------------------------------------------------
       sketch_any<PF, LDY>(a, A, lda, m, n, l, Ys);
       __syncthreads();
-      for (int c = tid; c < n; c += kBT) {
-        double s = 0.0;
-        for (int i = 0; i < l; ++i) {
-          const double y = (double)Ys[c * LDY + i];
-          s += y * y;
-        }
-        nu[c] = s;
-        perm[c] = c;
-      }
-      // |Y|_F^2 and the largest initial column norm
+      double nu[2];   // squared trailing norm of a candidate column, -1 once selected or absent
       Best b0{-1.0, 0x7fffffff, 0};
       double y0 = 0.0;
-      for (int c = tid; c < n; c += kBT) {
-        y0 += nu[c];
-        Best cb{nu[c], c, c};
-        if (beats(cb, b0)) b0 = cb;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int c = tid + q * kBT;
+        const bool own = c < n;
+        double sq = 0.0;
+#pragma unroll
+        for (int i = 0; i < LR; ++i) {
+          y[q][i] = (own && i < l) ? Ys[(own ? c : 0) * LDY + i] : 0.0f;
+          sq += (double)y[q][i] * (double)y[q][i];
+        }
+        nu[q] = own ? sq : -1.0;
+        if (own) {
+          y0 += sq;
+          Best cb{sq, c, c};
+          if (beats(cb, b0)) b0 = cb;
+        }
       }
       b0 = block_best_sum(b0, y0, sb, ss);
       const double nu0max = b0.v;
@@ -283,63 +330,66 @@ __global__ __launch_bounds__(kBT, (LDY < 64 ? 2 : 1)) void batched_id_kernel(BAr
       for (;;) {
         Best bb{-1.0, 0x7fffffff, 0};
         double rs = 0.0;
-        for (int c = j + tid; c < n; c += kBT) {
-          rs += nu[c];
-          Best cb{nu[c], perm[c], c};
-          if (beats(cb, bb)) bb = cb;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          if (nu[q] >= 0.0) {
+            rs += nu[q];
+            const int c = tid + q * kBT;
+            Best cb{nu[q], c, c};
+            if (beats(cb, bb)) bb = cb;
+          }
         }
         bb = block_best_sum(bb, rs, sb, ss);
         if (tolmode && rs <= a.tol * a.tol * y0) { met = true; break; }
         if (j >= cap) break;
         if (bb.v <= a.rank_tol * a.rank_tol * nu0max) { met = true; break; }
-        // swap positions j and the pivot
-        const int pp = bb.pos;
-        if (pp != j) {
-          for (int i = tid; i < l; i += kBT) {
-            const float t0 = Ys[j * LDY + i];
-            Ys[j * LDY + i] = Ys[pp * LDY + i];
-            Ys[pp * LDY + i] = t0;
+        const int P = bb.pos;
+        // the pivot's owner publishes the column and takes it out of the candidates
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          if (P == tid + q * kBT) {
+#pragma unroll
+            for (int i = 0; i < LR; ++i) xcol[i] = y[q][i];
+            nu[q] = -1.0;
           }
-          if (tid == 0) {
-            const double tn = nu[j]; nu[j] = nu[pp]; nu[pp] = tn;
-            const int tp = perm[j]; perm[j] = perm[pp]; perm[pp] = tp;
-          }
-          __syncthreads();
         }
-        // Householder reflector of Y(j:l, j) (wave 0, one lane per row)
-        if (tid < 64) {
-          const int i = j + lane;
-          const double x = i < l ? (double)Ys[j * LDY + i] : 0.0;
-          double s2 = x * x;
-          for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, 64);
-          const double x0 = __shfl(x, 0, 64);
-          const double normx = sqrt(s2);
-          const double alpha = x0 >= 0.0 ? -normx : normx;
-          const double v = lane == 0 ? x0 - alpha : x;
-          double vv = v * v;
-          for (int o = 32; o > 0; o >>= 1) vv += __shfl_xor(vv, o, 64);
-          if (i < l) {
-            vsh[lane] = v;
-            Ys[j * LDY + i] = lane == 0 ? (float)alpha : 0.0f;
-          }
-          if (lane == 0) sbeta = vv > 0.0 ? 2.0 / vv : 0.0;
-        }
+        if (tid == 0) piv[j] = P;
         __syncthreads();
-        const double beta = sbeta;
-        for (int c = j + 1 + tid; c < n; c += kBT) {
-          float* y = Ys + c * LDY;
-          double w = 0.0;
-          for (int i = j; i < l; ++i) w += vsh[i - j] * (double)y[i];
-          w *= beta;
-          double s = 0.0;
-          for (int i = j; i < l; ++i) {
-            const float yn = (float)((double)y[i] - w * vsh[i - j]);
-            y[i] = yn;
-            if (i > j) s += (double)yn * (double)yn;
+        // every wave forms the reflector of rows j..l-1 itself (lane = row)
+        const double xd = (lane < LR && lane >= j) ? (double)xcol[lane < LR ? lane : 0] : 0.0;
+        double s2 = xd * xd;
+        for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, 64);
+        const double x0 = __shfl(xd, j, 64);
+        const double normx = sqrt(s2);
+        const double alpha = x0 >= 0.0 ? -normx : normx;
+        const float vf = (float)(lane == j ? x0 - alpha : xd);
+        double vv = (double)vf * (double)vf;
+        for (int o = 32; o > 0; o >>= 1) vv += __shfl_xor(vv, o, 64);
+        const double beta = vv > 0.0 ? 2.0 / vv : 0.0;
+        float v[LR];
+#pragma unroll
+        for (int i = 0; i < LR; ++i)
+          v[i] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, vf), i));
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          if (nu[q] >= 0.0) {
+            double w = 0.0;
+#pragma unroll
+            for (int i = 0; i < LR; ++i) w += (double)v[i] * (double)y[q][i];
+            w *= beta;
+            double sq = 0.0;
+#pragma unroll
+            for (int i = 0; i < LR; ++i) {
+              y[q][i] = (float)((double)y[q][i] - w * (double)v[i]);
+              sq += i > j ? (double)y[q][i] * (double)y[q][i] : 0.0;
+            }
+            nu[q] = sq;
+          } else if (P == tid + q * kBT) {
+            // the pivot column becomes column j of S: alpha on the diagonal, zeros below
+#pragma unroll
+            for (int i = 0; i < LR; ++i) y[q][i] = i < j ? y[q][i] : (i == j ? (float)alpha : 0.0f);
           }
-          nu[c] = s;
         }
-        __syncthreads();
         ++j;
       }
       k = j;
@@ -348,32 +398,42 @@ __global__ __launch_bounds__(kBT, (LDY < 64 ? 2 : 1)) void batched_id_kernel(BAr
       __syncthreads();
     }
     if (!met && tid == 0) set_status(a.status, ST_RANKCAP);
+    // columns back to LDS (rows 0..k-1 hold S, the rest the residual)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int c = tid + q * kBT;
+      if (c < n) {
+#pragma unroll
+        for (int i = 0; i < LR; ++i) Ys[c * LDY + i] = y[q][i];
+        ord[c] = -1;
+      }
+    }
     __syncthreads();
+    if (tid < k) ord[piv[tid]] = tid;
     // ---- T = S11^{-1} S12, written with J = [pivots, the rest ascending] ----------
     const int KP = k <= 16 ? 16 : (k <= 32 ? 32 : 64);
     for (int e = tid; e < KP * KP; e += kBT) {
       const int i = e / KP, q = e % KP;
-      Sp[e] = i < k ? (q <= i ? Ys[i * LDY + q] : 0.0f) : (q == i ? 1.0f : 0.0f);
+      Sp[e] = i < k ? (q <= i ? Ys[piv[i] * LDY + q] : 0.0f) : (q == i ? 1.0f : 0.0f);
     }
-    for (int i = tid; i < KP; i += kBT) dinv[i] = i < k ? 1.0 / (double)Ys[i * LDY + i] : 1.0;
+    for (int i = tid; i < KP; i += kBT) dinv[i] = i < k ? 1.0 / (double)Ys[piv[i] * LDY + i] : 1.0;
+    __syncthreads();
     int* J = a.J[b];
     for (int c = tid; c < n; c += kBT) {
-      const int orig = perm[c];
-      if (c < k) {
-        J[c] = orig;
+      if (ord[c] >= 0) {
+        J[ord[c]] = c;
       } else {
         int below = 0;
-        for (int q = 0; q < k; ++q) below += perm[q] < orig ? 1 : 0;
-        const int tc = orig - below;   // rank among the unselected columns
-        J[k + tc] = orig;
+        for (int q = 0; q < k; ++q) below += piv[q] < c ? 1 : 0;
+        const int tc = c - below;   // rank among the unselected columns
+        J[k + tc] = c;
         cpos[tc] = c;
       }
     }
-    __syncthreads();
     if (k > 0) {
-      if (KP == 16) solve_columns<16, LDY>(Ys, Sp, dinv, k, n);
-      else if (KP == 32) solve_columns<32, LDY>(Ys, Sp, dinv, k, n);
-      else solve_columns<64, LDY>(Ys, Sp, dinv, k, n);
+      if (KP == 16) solve_columns<16, LDY>(Ys, Sp, dinv, ord, n);
+      else if (KP == 32) solve_columns<32, LDY>(Ys, Sp, dinv, ord, n);
+      else solve_columns<64, LDY>(Ys, Sp, dinv, ord, n);
     }
     __syncthreads();
     {
@@ -447,8 +507,7 @@ size_t batched_lds_bytes(int lcap, int nmax) {
   (void)nmax;
   const int ldom = batched_ldom(lcap);
   const int ldy = ldom + 1;
-  return (((size_t)kBNmax * ldy * sizeof(float) + 15) & ~(size_t)15) + (size_t)kBNmax * (sizeof(double) + sizeof(int)) +
-         (size_t)ldom * ldom * sizeof(float);
+  return (size_t)ldom * ldom * sizeof(float) + 2 * (size_t)kBNmax * sizeof(int) + (size_t)kBNmax * ldy * sizeof(float);
 }
 
 // Variant v: sketch prefetch depth PF = 1 + v % 2 (16-k chunks of loads issued together);
