@@ -39,32 +39,160 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-GEMM_SOURCES = ("gemm_kernel.hpp", "gemm.hip", "gemm_f32.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sketch_gemm_fp32_20000x10000_l210_traffic.md")
+# Committed counter summaries (profiles/): HBM bytes per launch of a kernel,
+# valid while its sources hash to the recorded value.
+TRAFFIC = {
+    "fp32": ("sketch_gemm_fp32_20000x10000_l210_traffic.md", ("gemm_kernel.hpp", "gemm.hip", "gemm_f32.hip"),
+             "gemm_sources_sha"),
+    "g16": ("sketch_gemm16_20000x10000_l210_traffic.md", ("gemm16_kernel.hpp", "gemm16.hip", "gemm16_f16.hip"),
+            "gemm16_sources_sha"),
+    "batched": ("batched_id_4096_kernel_blocks_traffic.md", ("batched.hip",), "batched_sources_sha"),
+}
 
 
-def gemm_source_hash():
+def source_hash(files):
     h = hashlib.sha256()
-    for f in GEMM_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, "paper_1412_8447_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per sketch-GEMM launch from the committed counter summary, or
-    None when the GEMM sources changed since the counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+def read_traffic(which="fp32"):
+    """HBM bytes per launch of a kernel from its committed counter summary, or
+    None when the kernel's sources changed since the counters were taken."""
+    fname, sources, key = TRAFFIC[which]
+    path = os.path.join(ROOT, "profiles", fname)
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             m = re.match(r"^\s*(\w+)\s*=\s*(\S+)\s*$", line)
             if m:
                 kv[m.group(1)] = m.group(2)
-    if kv.get("gemm_sources_sha") != gemm_source_hash() or "traffic_bytes_per_launch" not in kv:
+    if kv.get(key) != source_hash(sources) or "traffic_bytes_per_launch" not in kv:
         return None
     return int(float(kv["traffic_bytes_per_launch"]))
+
+
+def bench_batched(args, P, synth, torch, dev, nblk=4096, tol=1e-6, kmax=24, p=8):
+    """4096 blocks K_ij = 1/|x_i - y_j| (sizes uniform in 64..512), FP32, tolerance
+    tol: launch time from graph replays, throughput, the HBM roofline of the
+    launch (A read once), errors against the FP64 oracle on a sample of blocks,
+    and the plain FP32 GPU CPQR (deterministic tolerance-mode ID of each block
+    by its own idcur_id_col call) on a sample, with a tolerance sweep for the
+    equal-error comparison."""
+    import numpy as np
+    from paper_1412_8447_amd.flops import batched_flops
+    t0 = time.time()
+    blocks = synth.kernel_blocks_torch(nblk, seed=args.seed, device=dev)
+    torch.cuda.synchronize()
+    log(f"batched: {nblk} kernel blocks ready in {time.time() - t0:.1f}s")
+    ms = [int(b.shape[0]) for b in blocks]
+    ns = [int(b.shape[1]) for b in blocks]
+    abytes = float(sum(m * n for m, n in zip(ms, ns))) * 4.0
+
+    def run_plan(tl, reps=10):
+        plan = P.BatchedID(blocks, tol=tl, kmax=kmax, p=p, seed=args.seed + 3)
+        plan.run()
+        plan.results()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            plan.run()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            plan.run()
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        P.sync_status(dev)
+        return plan, e0.elapsed_time(e1) / reps
+
+    plan, ms_b = run_plan(tol)
+    ks = plan.kout.cpu().numpy()
+    l = kmax + p
+    fl = batched_flops(ms, ns, ks, l)
+    gbs = abytes / (ms_b * 1e-3) / 1e9
+    out = {"workload": f"{nblk} kernel blocks 1/|x-y|, m,n uniform 64..512, FP32, tol {tol}",
+           "launch": "one persistent launch replayed from a captured graph",
+           "ms_per_batch": round(ms_b, 4), "blocks_per_s": round(nblk / (ms_b * 1e-3), 1),
+           "gflops": round(fl / (ms_b * 1e-3) / 1e9, 2), "rank_min": int(ks.min()), "rank_max": int(ks.max()),
+           "rank_mean": round(float(ks.mean()), 3),
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": read_traffic("batched"),
+                        "bytes_per_launch": abytes, "note": "algorithmic bytes: every block read once"}}
+    log("batched", {k: out[k] for k in ("ms_per_batch", "blocks_per_s", "gflops", "rank_min", "rank_max")})
+    # accuracy on a sample against the oracle (same Omega, FP64)
+    import oracle
+    from oracle import batched as obatched
+    res = plan.results()
+    mmax = max(ms)
+    om = P.gaussian(l, mmax, seed=args.seed + 3, dtype=torch.float32).cpu().numpy().astype(np.float64)
+    sample = list(range(0, nblk, nblk // 32))
+    ratios, errs = [], []
+    for b in sample:
+        A = blocks[b].cpu().numpy().astype(np.float64)
+        ref = obatched.id_col_adaptive(A, om, p, tol=tol, kmax=kmax, rank_tol=np.sqrt(l) * 2.0 ** -24)
+        e_g = oracle.e_id(A, res[b].J.cpu().numpy(), res[b].T.cpu().numpy())
+        errs.append(e_g)
+        ratios.append(e_g / oracle.e_id(A, ref.id.J, ref.id.T))
+    out["oracle_sample"] = {"blocks": len(sample), "error_ratio_median": round(float(np.median(ratios)), 4),
+                            "error_ratio_max": round(float(np.max(ratios)), 4),
+                            "rel_fro_error_mean": float(np.mean(errs))}
+    if args.no_comparator:
+        return out
+    # plain FP32 GPU CPQR on a sample: one deterministic tolerance-mode ID per block
+    nplain = 128
+    idx = list(range(0, nblk, nblk // nplain))
+    perr = []
+    for b in idx[:4]:
+        P.id_col(blocks[b], 0, tol=tol, kmax=min(ms[b], ns[b]) - 1)
+    torch.cuda.synchronize()
+    tt = time.time()
+    outs = [P.id_col(blocks[b], 0, tol=tol, kmax=min(ms[b], ns[b]) - 1, sync=False) for b in idx]
+    torch.cuda.synchronize()
+    t_plain = (time.time() - tt) / len(idx)
+    P.sync_status(dev)
+    for b, r in zip(idx[:32], outs[:32]):
+        kk = int(r.kout[0])
+        A = blocks[b].cpu().numpy().astype(np.float64)
+        n_b = ns[b]
+        perr.append(oracle.e_id(A, r.J.cpu().numpy(), r.T[:kk, : n_b - kk].cpu().numpy()))
+    e_plain = float(np.mean(perr))
+    plain_ms = t_plain * nblk * 1e3
+    out["comparator"] = {"name": "plain FP32 GPU CPQR per block (deterministic, Y = A, tolerance mode)",
+                         "ms_per_batch_extrapolated": round(plain_ms, 2),
+                         "sample_blocks": len(idx), "rel_fro_error_mean": e_plain,
+                         "speedup_nominal": round(plain_ms / ms_b, 2)}
+    # equal error: the largest tolerance whose sampled mean error is within 1.05x
+    # of the plain CPQR's
+    sweep = []
+    best = None
+    for tl in ((tol,) if args.no_sweep else (tol, tol / 2, tol / 4)):
+        pl, msb = (plan, ms_b) if tl == tol else run_plan(tl)
+        rr = pl.results()
+        ee = [oracle.e_id(blocks[b].cpu().numpy().astype(np.float64), rr[b].J.cpu().numpy(), rr[b].T.cpu().numpy())
+              for b in idx[:32]]
+        row = {"tol": tl, "ms_per_batch": round(msb, 4), "rel_fro_error_mean": float(np.mean(ee)),
+               "ratio_to_plain": round(float(np.mean(ee)) / e_plain, 4)}
+        sweep.append(row)
+        log("batched sweep", row)
+        if best is None and row["ratio_to_plain"] <= 1.05:
+            best = row
+    out["equal_error_sweep"] = sweep
+    if best is not None:
+        out["equal_error"] = dict(best, blocks_per_s=round(nblk / (best["ms_per_batch"] * 1e-3), 1),
+                                  speedup_vs_plain=round(plain_ms / best["ms_per_batch"], 2))
+    return out
 
 
 def main():
@@ -76,6 +204,9 @@ def main():
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the BF16 / FP16 sketch measurements")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched kernel-block measurement")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched kernel-block measurement (one JSON object, for profiling)")
     ap.add_argument("--seed", type=int, default=20260)
     ap.add_argument("--input-cache", default=None,
                     help="load A from this file when it exists, else generate it and save it there")
@@ -102,6 +233,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calib_bytes_read": nbytes, "copy_calib_bytes_written": nbytes, "launches": 3}))
+        return
+    if args.batched_only:
+        print(json.dumps({"batched": bench_batched(args, P, synth, torch, dev)}), flush=True)
         return
     cfg = synth.CONFIGS["rand_fp32_20000x10000_k200"]
     m, n, k, p, q = cfg.m, cfg.n, cfg.k, cfg.p, cfg.q
@@ -224,12 +358,18 @@ def main():
                            "error_ratio_vs_fp32": round(em / e_cur, 4),
                            "stages_ms_per_step": {sname: round(v[0] / reps, 4) for sname, v in st_m.items() if v[1]},
                            "sketch_gemm": {"avg_launch_ms": round(gavg, 4), "launches": gc,
+                                           "traffic": read_traffic("g16"),
                                            "hbm_GBps": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4),
                                            "TFLOPs": round(tfl, 2),
                                            "mfma_frac": round(tfl / PEAK_16BIT_MFMA_TFLOPS, 4)}}
             log(prec, mixed[prec])
             del wsm, outm
         result["mixed_precision"] = mixed
+
+    # batched adaptive-rank IDs of 4096 kernel blocks (one persistent launch,
+    # replayed from a captured graph)
+    if not args.no_batched:
+        result["batched"] = bench_batched(args, P, synth, torch, dev)
 
     # plain FP32 GPU CPQR comparator (no sketch) and the equal-error sweep
     if not args.no_comparator:

@@ -85,7 +85,8 @@ typedef struct {
                          (Section 3: continue the QR until |E| is below a threshold). */
   double rank_tol;    /* stop early (exact rank deficiency, Section 2.3) when the
                          largest remaining column norm <= rank_tol * largest initial
-                         norm; 0 selects 10 sqrt(l) u with u the unit roundoff of dtype */
+                         norm; 0 selects 10 sqrt(l) u with a fixed rank and sqrt(l) u
+                         in tolerance mode, u the unit roundoff of dtype        */
   int32_t p;          /* oversampling (Section 5.1); < 0: deterministic, Y = A.         */
   int32_t q;          /* orthonormalised power steps (Section 5.3), >= 0.               */
   uint64_t seed;      /* Philox4x32-10 key for Omega when omega == NULL.                */
@@ -246,9 +247,9 @@ idcur_status idcur_id_col_backward(idcur_ctx* ctx, int32_t dtype, int64_t m, int
  *   and sets IDCUR_ERANKCAP in the device status). Fixed rank (opts->k > 0):
  *   l = k + p, k steps. Exact rank deficiency stops early: when the largest
  *   remaining column norm is <= opts->rank_tol times the largest initial column
- *   norm of Y (opts->rank_tol == 0 selects sqrt(l_cap) u32, u32 = 2^-24, so that
- *   in tolerance mode the Frobenius rule decides unless pivots reach rounding
- *   level).
+ *   norm of Y (opts->rank_tol == 0 selects sqrt(l_cap) u32 in tolerance mode,
+ *   u32 = 2^-24, so that the Frobenius rule decides unless pivots reach rounding
+ *   level, and 10 sqrt(l_cap) u32 with a fixed rank).
  *   T = S11^{-1} S12 by FP64 back-substitution.
  * Limits: 1 <= n_b <= nmax <= 512, 1 <= m_b <= mmax, (k or kmax) + p <= 64,
  * p >= 1, q = 0, NATIVE precision, dtype IDCUR_F32. A block outside its limits

@@ -260,8 +260,13 @@ void interp_matrix(const Ctx& x, int dtype, const void* S, int64_t ldS, const in
   gemm(x, g);
 }
 
-double default_rank_tol(int dtype, int64_t l) {
-  return 10.0 * std::sqrt((double)std::max<int64_t>(l, 1)) * (dtype == IDCUR_F32 ? kU32 : kU64);
+// Exact rank deficiency (Section 2.3), relative to the largest initial column
+// norm: 10 sqrt(l) u with a fixed rank (a safe margin over the rounding noise of
+// an l-row column), sqrt(l) u in tolerance mode, where the Frobenius rule
+// already stops at noise level and a coarser test would stop ahead of it (FP32
+// pivots of a few 1e-6 at tol = 1e-6 are well resolved).
+double default_rank_tol(int dtype, int64_t l, bool tolmode) {
+  return (tolmode ? 1.0 : 10.0) * std::sqrt((double)std::max<int64_t>(l, 1)) * (dtype == IDCUR_F32 ? kU32 : kU64);
 }
 
 // The sketch of the view X (Section 5.1, eq. (Y=OmegaA)) with q orthonormalised
@@ -425,7 +430,7 @@ ColId column_id(const Ctx& x, int dtype, const View& X, const idcur_opts& o, int
     a.l_host = l; a.l_dev = nullptr; a.n = (int)nc;
     a.kmax_host = kcap; a.kmax_dev = nullptr;
     a.tol = o.k > 0 ? 0.0 : o.tol;
-    a.rank_tol = o.rank_tol > 0 ? o.rank_tol : default_rank_tol(dtype, l);
+    a.rank_tol = o.rank_tol > 0 ? o.rank_tol : default_rank_tol(dtype, l, o.k == 0);
     a.norms_exact = o.norms == IDCUR_NORMS_EXACT;
     a.S = S; a.ldS = nc; a.J = J; a.k_out = k_out; a.status = x.c->dstatus;
     a.gslab = gslab; a.rec = rec; a.cvals = cvals;
@@ -887,11 +892,7 @@ void batched_run(const Ctx& x, const BatchedCall& c, const idcur_opts& o, int va
   a.omt = omt;
   a.mmax = c.mmax; a.nmax = c.nmax; a.lcap = lcap; a.p = o.p; a.kfix = o.k;
   a.tol = o.k > 0 ? 0.0 : o.tol;
-  // default sqrt(l_cap) u32: a pivot column at that relative norm is rounding
-  // noise of an l-row FP32 column; a coarser test would stop tolerance mode
-  // ahead of the Frobenius rule on smooth kernels (pivot norms of a few 1e-6
-  // at tol = 1e-6 are still well resolved in FP32)
-  a.rank_tol = o.rank_tol > 0 ? o.rank_tol : std::sqrt((double)lcap) * kU32;
+  a.rank_tol = o.rank_tol > 0 ? o.rank_tol : default_rank_tol(IDCUR_F32, lcap, o.k == 0);
   a.order = order; a.queue = queue; a.status = x.c->dstatus;
   x.check(batched_launch(a, variant, x.c->num_cus, x.s), "batched launch");
 }

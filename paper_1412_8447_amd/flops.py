@@ -42,3 +42,14 @@ def flop_model(op: str, m: int, n: int, k: int, p: int = -1, q: int = 0, orth_pa
         out["u"] = u_passes * (2.0 * n * k * k + k ** 3 / 3.0 + n * k * k) + 2.0 * n * k * k + 2.0 * k ** 3
     out["total"] = float(sum(out.values()))
     return out
+
+
+def batched_flops(ms, ns, ks, l: int) -> float:
+    """Batched column IDs (one sketch width l per block): sketch 2 l m n, the
+    k-step pivoted QR of the l x n sketch, and the k x k triangular solve with
+    n - k right-hand sides, summed over blocks."""
+    tot = 0.0
+    for m, n, k in zip(ms, ns, ks):
+        k = max(int(k), 0)
+        tot += 2.0 * l * m * n + cpqr_flops(l, n, k) + float(k) * k * (n - k)
+    return tot
