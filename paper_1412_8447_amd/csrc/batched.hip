@@ -17,7 +17,7 @@
 //      written with J = [pivots, the other columns in increasing order].
 //
 // One Omega (l_cap x m_max, stored transposed) serves every block. Workgroups
-// take blocks from an atomic counter, in the order of a one-workgroup bitonic
+// take blocks from an atomic counter, in the order of a one-workgroup counting
 // sort by m_b n_b (largest first) so the last blocks to start are the smallest.
 // Results do not depend on which workgroup takes a block or on the launch
 // shape: every reduction inside a block has a fixed order.
@@ -450,38 +450,31 @@ __global__ __launch_bounds__(kBT, (LDY < 64 ? 2 : 1)) void batched_id_kernel(BAr
   }
 }
 
-// Processing order: block indices by m_b n_b, largest first (ties: smaller index
-// first), by a bitonic sort of 64-bit keys in LDS (one workgroup, nblk <= 8192).
-constexpr int kSortMax = 8192;
+// Processing order: block indices by size class m_b n_b / 1024 (0 .. 256 for
+// blocks up to 512 x 512), largest class first, by a counting sort in one
+// workgroup. The order inside a class (set by LDS atomics) only changes which
+// workgroup takes a block when, never a block's result.
+constexpr int kClasses = 257;
 __global__ __launch_bounds__(1024) void batch_order_kernel(const int* m, const int* n, int nblk, int* order) {
-  __shared__ unsigned long long key[kSortMax];
-  int P = 1;
-  while (P < nblk) P <<= 1;
-  for (int i = threadIdx.x; i < P; i += 1024) {
-    unsigned long long kv = ~0ull;
-    if (i < nblk) {
-      // 43 bits of (2^43 - 1 - m n) above 20 bits of index: larger blocks first
-      const unsigned long long w = (unsigned long long)max(m[i], 0) * (unsigned long long)max(n[i], 0);
-      const unsigned long long w43 = (1ull << 43) - 1ull;
-      kv = ((w43 - min(w, w43)) << 20) | (unsigned long long)i;
+  __shared__ int cnt[kClasses];
+  __shared__ int start[kClasses];
+  for (int c = threadIdx.x; c < kClasses; c += 1024) cnt[c] = 0;
+  __syncthreads();
+  auto cls = [&](int i) {
+    const long long w = (long long)max(m[i], 0) * (long long)max(n[i], 0);
+    return (int)min(w >> 10, (long long)(kClasses - 1));
+  };
+  for (int i = threadIdx.x; i < nblk; i += 1024) atomicAdd(&cnt[cls(i)], 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {   // exclusive scan from the largest class down
+    int run = 0;
+    for (int c = kClasses - 1; c >= 0; --c) {
+      start[c] = run;
+      run += cnt[c];
     }
-    key[i] = kv;
   }
   __syncthreads();
-  for (int size = 2; size <= P; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = threadIdx.x; i < P; i += 1024) {
-        const int pj = i ^ stride;
-        if (pj > i) {
-          const bool up = (i & size) == 0;
-          const unsigned long long x = key[i], y = key[pj];
-          if ((x > y) == up) { key[i] = y; key[pj] = x; }
-        }
-      }
-      __syncthreads();
-    }
-  }
-  for (int i = threadIdx.x; i < nblk; i += 1024) order[i] = (int)(key[i] & 0xFFFFFull);
+  for (int i = threadIdx.x; i < nblk; i += 1024) order[atomicAdd(&start[cls(i)], 1)] = i;
 }
 
 template <int PF>
@@ -530,7 +523,7 @@ hipError_t batched_launch(const BatchedArgs& ba, int variant, int num_cus, hipSt
   hipError_t e = zero_launch(ba.queue, sizeof(int), stream);
   if (e != hipSuccess) return e;
   a.order = nullptr;
-  if (lpt && ba.nblk <= kSortMax && ba.order) {
+  if (lpt && ba.order) {
     hipLaunchKernelGGL(batch_order_kernel, dim3(1), dim3(1024), 0, stream, ba.m, ba.n, ba.nblk, ba.order);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
