@@ -42,8 +42,8 @@ def log(*a):
 # Committed counter summaries (profiles/): HBM bytes per launch of a kernel,
 # valid while its sources hash to the recorded value.
 TRAFFIC = {
-    "fp32": ("sketch_gemm_fp32_20000x10000_l210_traffic.md", ("gemm_kernel.hpp", "gemm.hip", "gemm_f32.hip"),
-             "gemm_sources_sha"),
+    "fp32": ("sketch_gemm_fp32_20000x10000_l210_traffic.md",
+             ("gemm_kernel.hpp", "gemm_thin_kernel.hpp", "gemm_thin.hip", "gemm.hip"), "gemm_sources_sha"),
     "g16": ("sketch_gemm16_20000x10000_l210_traffic.md", ("gemm16_kernel.hpp", "gemm16.hip", "gemm16_f16.hip"),
             "gemm16_sources_sha"),
     "batched": ("batched_id_4096_kernel_blocks_traffic.md", ("batched.hip",), "batched_sources_sha"),

@@ -82,8 +82,24 @@ int gemm_pick_splitk(int64_t M, int64_t N, int64_t K, int num_cus) {
   return s;
 }
 
+int gemm_pick_splitk_desc(const GemmDesc& d, int num_cus) {
+  if (thin_f32_eligible(d)) return thin_f32_pick_splitk(d.M, d.N, d.K, num_cus);
+  return gemm_pick_splitk(d.M, d.N, d.K, num_cus);
+}
+
 hipError_t gemm_launch(const GemmDesc& d, void* part, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1) {
   if (d.M <= 0 || d.N <= 0) return hipSuccess;
+  if (thin_f32_eligible(d)) {
+    const int splitk = std::max(1, d.splitk);
+    if (ev0) (void)hipEventRecord(ev0, stream);
+    hipError_t e = thin_f32_launch(d, splitk, part, stream);
+    if (ev1) (void)hipEventRecord(ev1, stream);
+    if (e != hipSuccess || splitk == 1) return e;
+    const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(d.M * d.N, 256), 4096);
+    hipLaunchKernelGGL(splitk_reduce<float>, dim3(blocks), dim3(256), 0, stream, static_cast<const float*>(part),
+                       splitk, d.M, d.N, d.C, d.ldc, 1, d.alpha, d.beta, d.m_dev, d.n_dev);
+    return hipGetLastError();
+  }
   const bool akc = (d.sak == 1);
   const bool bnc = (d.sbn == 1);
   const int nt = pick_nt(d.N);

@@ -129,7 +129,7 @@ struct Stage {
 // GEMM helper: C = A * B in the descriptor's layout, with split-K scratch.
 // ---------------------------------------------------------------------------
 void gemm(const Ctx& x, GemmDesc d, const char* stage = nullptr) {
-  d.splitk = gemm_pick_splitk(d.M, d.N, d.K, x.c->num_cus);
+  d.splitk = gemm_pick_splitk_desc(d, x.c->num_cus);
   void* part = x.ar->take(gemm_part_bytes(d));
   if (x.dry) return;
   hipEvent_t a = nullptr, b = nullptr;
@@ -340,6 +340,7 @@ SketchOut sketch(const Ctx& x, int dtype, const View& X, const idcur_opts& o, in
     g.A = X.A; g.sam = X.xc; g.sak = X.xr;
     g.B = Bm; g.sbk = ll; g.sbn = 1;
     g.C = Yt; g.ldc = ll;
+    g.b_rows_padded = true;   // Bm is mr x ll
     g.in_type = dtype; g.acc_type = dtype == IDCUR_F32 ? 1 : 0; g.out_type = dtype;
     g.alpha = 1.0; g.beta = 0.0;
     gemm(x, g, "sketch_gemm");
@@ -383,6 +384,7 @@ SketchOut sketch(const Ctx& x, int dtype, const View& X, const idcur_opts& o, in
       g.A = X.A; g.sam = X.xr; g.sak = X.xc;
       g.B = Qyt; g.sbk = ll; g.sbn = 1;
       g.C = Zt; g.ldc = ll;
+      g.b_rows_padded = true;   // Qyt is nc x ll
       g.in_type = dtype; g.acc_type = dtype == IDCUR_F32 ? 1 : 0; g.out_type = dtype;
       g.alpha = 1.0; g.beta = 0.0;
       gemm(x, g, "sketch_gemm");

@@ -85,9 +85,16 @@ struct GemmDesc {
   const int* m_dev; // optional device bound on M (rows >= *m_dev are skipped)
   const int* n_dev; // optional device bound on N
   const int* k_dev; // optional device bound on K
+  bool b_rows_padded = false;   // every row of B is allocated up to round_up(N, 4)
 };
 size_t gemm_part_bytes(const GemmDesc& d);
 int gemm_pick_splitk(int64_t M, int64_t N, int64_t K, int num_cus);
+// Split count for this descriptor (the FP32 thin kernel has its own choice).
+int gemm_pick_splitk_desc(const GemmDesc& d, int num_cus);
+// FP32 thin-output kernel (gemm_thin.hip), used by gemm_launch when eligible.
+bool thin_f32_eligible(const GemmDesc& d);
+int thin_f32_pick_splitk(int64_t M, int64_t N, int64_t K, int num_cus);
+hipError_t thin_f32_launch(const GemmDesc& d, int splitk, void* part, hipStream_t stream);
 // ev0/ev1 (optional) bracket the GEMM kernel itself, not the split-K reduction.
 hipError_t gemm_launch(const GemmDesc& d, void* part, hipStream_t stream, hipEvent_t ev0 = nullptr,
                        hipEvent_t ev1 = nullptr);
