@@ -76,6 +76,33 @@ def read_traffic(which="fp32"):
     return int(float(kv["traffic_bytes_per_launch"]))
 
 
+def library_gemm(torch, A, l, reps=5):
+    """Context for the roofline: torch's FP32 GEMM (the vendor BLAS, TF32 off) on
+    the sketch's shape, A^T (n x m) times an m x l operand, timed with events.
+    Not part of the product path."""
+    prev = torch.backends.cuda.matmul.allow_tf32
+    torch.backends.cuda.matmul.allow_tf32 = False
+    try:
+        m, n = A.shape
+        B = torch.randn(m, l, device=A.device, dtype=torch.float32)
+        At = A.t()
+        for _ in range(2):
+            At @ B
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            At @ B
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        del B
+        return {"what": "torch.matmul FP32 (TF32 off), A^T times an m x l matrix", "ms": round(ms, 4),
+                "TFLOPs": round(2.0 * m * n * l / (ms * 1e-3) / 1e12, 2)}
+    finally:
+        torch.backends.cuda.matmul.allow_tf32 = prev
+
+
 def bench_batched(args, P, synth, torch, dev, nblk=4096, tol=1e-6, kmax=24, p=8):
     """4096 blocks K_ij = 1/|x_i - y_j| (sizes uniform in 64..512), FP32, tolerance
     tol: launch time from graph replays, throughput, the HBM roofline of the
@@ -205,6 +232,8 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the BF16 / FP16 sketch measurements")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched kernel-block measurement")
+    ap.add_argument("--no-library-gemm", action="store_true",
+                    help="skip timing torch's FP32 GEMM on the sketch shape (context for the roofline)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched kernel-block measurement (one JSON object, for profiling)")
     ap.add_argument("--seed", type=int, default=20260)
@@ -309,6 +338,8 @@ def main():
                 "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": traffic,
                 "kernel": "sketch_gemm (FP32 MFMA 16x16x4)", "avg_launch_ms": round(g_avg, 4),
                 "launches": g_cnt, "flops_per_launch": g_flops}
+    if not args.no_library_gemm:
+        roofline["library_gemm"] = library_gemm(torch, A, l)
 
     result = {
         "metric": "ID/CUR GFLOP/s + matrices/sec vs plain FP32 GPU CPQR at equal rel. Frobenius error",
