@@ -1,0 +1,8 @@
+// double instantiations of the register-slab CPQR kernel.
+#include "cpqr_reg_kernel.hpp"
+
+namespace idcur {
+const void* cpqr_reg_fn_f64(int cfg) {
+  return cr::reg_kernel_lookup<double>(cfg, std::make_integer_sequence<int, cr::kNumRegCfgs>{});
+}
+}  // namespace idcur

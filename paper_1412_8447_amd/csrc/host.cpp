@@ -427,6 +427,9 @@ ColId column_id(const Ctx& x, int dtype, const View& X, const idcur_opts& o, int
   if (!x.dry) {
     Stage st(x, "cpqr");
     x.check(zero_launch(rec, pl.rec_bytes + pl.fin_bytes, x.s), "zero");
+    // column words carry only the publish index as their stamp: words left by an
+    // earlier call in the same memory must not match, so they start at zero
+    x.check(zero_launch(cvals, pl.cvals_bytes, x.s), "zero");
     CpqrArgs a{};
     a.Y = Ymat; a.rs = yrs; a.cs = ycs;
     a.l_host = l; a.l_dev = nullptr; a.n = (int)nc;
@@ -458,6 +461,9 @@ void row_id_of_c(const Ctx& x, int dtype, const void* C, int64_t m, int kcap, co
   if (!x.dry) {
     Stage st(x, "row_id");
     x.check(zero_launch(rec, pl.rec_bytes + pl.fin_bytes, x.s), "zero");
+    // column words carry only the publish index as their stamp: words left by an
+    // earlier call in the same memory must not match, so they start at zero
+    x.check(zero_launch(cvals, pl.cvals_bytes, x.s), "zero");
     CpqrArgs a{};
     a.Y = C; a.rs = 1; a.cs = kcap;
     a.l_host = kcap; a.l_dev = k_dev; a.n = (int)m;
