@@ -119,42 +119,47 @@ __device__ __forceinline__ void group_bcast(const T (&x)[NC], T (&r)[NC], int jr
   }
 }
 
-// candidate: value, column, payload (owner: group or workgroup index)
+// candidate: value and column (the owning group or workgroup follows from the
+// column: workgroups own contiguous column ranges, groups interleave in them)
 struct Cand {
   double v;
   int i;
-  int o;
 };
 __device__ __forceinline__ void cand_merge(Cand& a, const Cand& b) {
   if (better(b.v, b.i, a.v, a.i)) a = b;
 }
 template <int CTRL>
 __device__ __forceinline__ Cand cand_dpp(const Cand& a) {
-  return Cand{dpp_d<CTRL>(a.v), dpp_i<CTRL>(a.i), dpp_i<CTRL>(a.o)};
+  return Cand{dpp_d<CTRL>(a.v), dpp_i<CTRL>(a.i)};
 }
 __device__ __forceinline__ Cand cand_readlane(const Cand& a, int l) {
-  return Cand{readlane_d(a.v, l), __builtin_amdgcn_readlane(a.i, l), __builtin_amdgcn_readlane(a.o, l)};
+  return Cand{readlane_d(a.v, l), __builtin_amdgcn_readlane(a.i, l)};
 }
-// argmax (and a plain sum riding along) over each row of 16 lanes; the merge is
-// a total order, so every lane of the row ends with the same candidate
-__device__ __forceinline__ void cand_row16(Cand& c, double& s) {
+// argmax over each row of 16 lanes; the merge is a total order, so every lane
+// of the row ends with the same candidate
+__device__ __forceinline__ void cand_row16(Cand& c) {
   cand_merge(c, cand_dpp<kRor8>(c));
-  s += dpp_d<kRor8>(s);
   cand_merge(c, cand_dpp<kRor4>(c));
-  s += dpp_d<kRor4>(s);
   cand_merge(c, cand_dpp<kQuadX2>(c));
-  s += dpp_d<kQuadX2>(s);
   cand_merge(c, cand_dpp<kQuadX1>(c));
+}
+// plain sum over each row of 16 lanes (tolerance mode only)
+__device__ __forceinline__ void sum_row16(double& s) {
+  s += dpp_d<kRor8>(s);
+  s += dpp_d<kRor4>(s);
+  s += dpp_d<kQuadX2>(s);
   s += dpp_d<kQuadX1>(s);
 }
 // combine the four rows of the wave in a fixed order (uniform result)
-__device__ __forceinline__ void cand_rows(Cand& c, double& s) {
+__device__ __forceinline__ void cand_rows(Cand& c) {
   Cand b = cand_readlane(c, 0);
-  const double s0 = readlane_d(s, 0), s1 = readlane_d(s, 16), s2 = readlane_d(s, 32), s3 = readlane_d(s, 48);
   cand_merge(b, cand_readlane(c, 16));
   cand_merge(b, cand_readlane(c, 32));
   cand_merge(b, cand_readlane(c, 48));
   c = b;
+}
+__device__ __forceinline__ void sum_rows(double& s) {
+  const double s0 = readlane_d(s, 0), s1 = readlane_d(s, 16), s2 = readlane_d(s, 32), s3 = readlane_d(s, 48);
   s = (s0 + s1) + (s2 + s3);
 }
 
@@ -205,7 +210,7 @@ __global__ __launch_bounds__(kRT) void cpqr_reg_kernel(CpqrArgs a) {
   // so that a wave entering the next phase cannot overwrite entries another
   // wave is still reading
   __shared__ double p_v[kRW], p_s[kRW], x_v[kRW], x_s[kRW];
-  __shared__ int p_i[kRW], p_o[kRW], x_i[kRW], x_o[kRW], x_t[kRW];
+  __shared__ int p_i[kRW], x_i[kRW], x_t[kRW];
   __shared__ int s_vfail;   // a thread gave up waiting for the winning column
   __shared__ double s_xnorm;   // the winning column's exact trailing norm
   int* win = reinterpret_cast<int*>(rsm);   // kmax_host pivots
@@ -278,7 +283,7 @@ __global__ __launch_bounds__(kRT) void cpqr_reg_kernel(CpqrArgs a) {
   auto publish = [&](int e) {
     const uint32_t st = (uint32_t)(e + 1);
     // the group's best active column and the group's sum of squared norms
-    Cand c{-1.0, 0x7fffffff, grp};
+    Cand c{-1.0, 0x7fffffff};
     double ssq = 0.0;
     int bu = -1;
 #pragma unroll
@@ -300,20 +305,22 @@ __global__ __launch_bounds__(kRT) void cpqr_reg_kernel(CpqrArgs a) {
       for (int u = 0; u < NC; ++u) yb[t] = (bu == u) ? y[u][t] : yb[t];
     }
     // across the groups of the wave, then across the waves
-    if constexpr (GPW > 1) cand_rows(c, ssq);
+    if constexpr (GPW > 1) {
+      cand_rows(c);
+      if (tolmode) sum_rows(ssq);
+    }
     if (lane == 0) {
       p_v[wv] = c.v;
       p_i[wv] = c.i;
-      p_o[wv] = c.o;
       p_s[wv] = ssq;
     }
     __syncthreads();
     if (tid == 0) s_vfail = 0;   // read by every thread before this barrier, set only after the next one
-    Cand b{p_v[0], p_i[0], p_o[0]};
+    Cand b{p_v[0], p_i[0]};
     double tot = p_s[0];
 #pragma unroll
     for (int w = 1; w < kRW; ++w) {
-      cand_merge(b, Cand{p_v[w], p_i[w], p_o[w]});
+      cand_merge(b, Cand{p_v[w], p_i[w]});
       tot += p_s[w];
     }
     const int par = e & 1;
@@ -328,7 +335,7 @@ __global__ __launch_bounds__(kRT) void cpqr_reg_kernel(CpqrArgs a) {
         cstore(r + 4, stamp32(st, (uint32_t)__double2loint(tot)));
       }
     }
-    if (b.i != 0x7fffffff && grp == b.o) {
+    if (b.i != 0x7fffffff && grp == (b.i - c0) % NGR) {
       // every slot, by row: readers take rows [e, l) only
 #pragma unroll
       for (int t = 0; t < RPL; ++t) Words<T>::put(dst + (size_t)(rgi + R * t) * WN, st, yb[t]);
@@ -354,7 +361,7 @@ __global__ __launch_bounds__(kRT) void cpqr_reg_kernel(CpqrArgs a) {
     // ---- exchange: every workgroup's record of publish index j -------------------
     const int par = j & 1;
     const uint32_t st = (uint32_t)(j + 1);
-    Cand c{-2.0, 0x7fffffff, 0};
+    Cand c{-2.0, 0x7fffffff};
     double ssq = 0.0;
     int tmo = 0;
     if (tid < G) {
@@ -371,7 +378,6 @@ __global__ __launch_bounds__(kRT) void cpqr_reg_kernel(CpqrArgs a) {
           c.v = __hiloint2double((int)(uint32_t)w[0], (int)(uint32_t)w[1]);
           c.i = (int)(uint32_t)w[2];
           ssq = tolmode ? __hiloint2double((int)(uint32_t)w[3], (int)(uint32_t)w[4]) : 0.0;
-          c.o = tid;
           break;
         }
         __builtin_amdgcn_s_sleep(1);
@@ -381,23 +387,26 @@ __global__ __launch_bounds__(kRT) void cpqr_reg_kernel(CpqrArgs a) {
         }
       }
     }
-    cand_row16(c, ssq);
-    cand_rows(c, ssq);
+    cand_row16(c);
+    cand_rows(c);
+    if (tolmode) {
+      sum_row16(ssq);
+      sum_rows(ssq);
+    }
     const int tmo_w = __any(tmo) ? 1 : 0;
     if (lane == 0) {
       x_v[wv] = c.v;
       x_i[wv] = c.i;
-      x_o[wv] = c.o;
       x_s[wv] = ssq;
       x_t[wv] = tmo_w;
     }
     __syncthreads();
-    Cand w{x_v[0], x_i[0], x_o[0]};
+    Cand w{x_v[0], x_i[0]};
     double tot = x_s[0];
     int timed_out = x_t[0];
 #pragma unroll
     for (int q = 1; q < kRW; ++q) {
-      cand_merge(w, Cand{x_v[q], x_i[q], x_o[q]});
+      cand_merge(w, Cand{x_v[q], x_i[q]});
       tot += x_s[q];
       timed_out |= x_t[q];
     }
@@ -416,7 +425,7 @@ __global__ __launch_bounds__(kRT) void cpqr_reg_kernel(CpqrArgs a) {
     T v[RPL];
     double x0 = 0.0, xnorm = 0.0;
     if (stop == 0) {
-      const uint64_t* src = cvals + ((size_t)par * G + w.o) * CW;
+      const uint64_t* src = cvals + ((size_t)par * G + w.i / cpw) * CW;   // the owner's slot
       bool ok = true;
       if (tid == kRT - 1) {
         long spins = 0;
@@ -535,7 +544,11 @@ __global__ __launch_bounds__(kRT) void cpqr_reg_kernel(CpqrArgs a) {
       } else {
 #pragma unroll
         for (int t = 0; t < RPL; ++t) {
-          const double qq = (double)y[u][t];
+          // the empty asm keeps the compiler from computing these squares
+          // ahead of the (rarely taken) recompute branch on every step
+          T yt = y[u][t];
+          asm volatile("" : "+v"(yt));
+          const double qq = (double)yt;
           r += (t > jt) ? qq * qq : 0.0;
         }
       }
@@ -551,7 +564,6 @@ __global__ __launch_bounds__(kRT) void cpqr_reg_kernel(CpqrArgs a) {
       // downdate nu^2 -= s^2 with s the new row-j entry; recompute from the
       // column when the downdate has cancelled below tol3z of the norm^2 at
       // the last recompute
-      bool need_any = false;
       bool need[NC];
       // the new row-j entry of every column, from lane jr of the group (the
       // value a group sum of it and zeros would give, up to the sign of zero)
@@ -566,11 +578,11 @@ __global__ __launch_bounds__(kRT) void cpqr_reg_kernel(CpqrArgs a) {
           need[u] = nn <= lim[u];
           nu2[u] = nn;
         }
-        need_any = need_any || need[u];
       }
-      if (__any(need_any)) {
+      // one wave vote per column slot: only the slots some group needs
 #pragma unroll
-        for (int u = 0; u < NC; ++u) {
+      for (int u = 0; u < NC; ++u) {
+        if (__any(need[u])) {
           const double rs = below(u);
           if (need[u]) {
             nu2[u] = rs;
