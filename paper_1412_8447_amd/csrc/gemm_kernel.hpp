@@ -178,16 +178,27 @@ __global__ __launch_bounds__(256) void gemm_kernel(KArgs p) {
     for (int64_t it = 0; it < ntile; ++it) {
       const int buf = (int)(it & 1);
       if (it + 1 < ntile) gload(kb + (it + 1) * BK);
-      const TAcc* as = As[buf];
-      const TAcc* bs = Bs[buf];
+      // operands of the next 4-deep k step are read before this step's MFMAs
+      // issue (a scheduling barrier keeps them apart), so LDS latency overlaps
+      // the matrix cores instead of stalling every pair of MFMAs
+      const TAcc* as = As[buf] + (lane >> 4) * SA + wv * 16 + (lane & 15);
+      const TAcc* bs = Bs[buf] + (lane >> 4) * SB + (lane & 15);
+      TAcc av[2];
+      TAcc bv[2][NT];
+      av[0] = as[0];
 #pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
-        const TAcc a = as[(kk + (lane >> 4)) * SA + wv * 16 + (lane & 15)];
+      for (int t = 0; t < NT; ++t) bv[0][t] = bs[t * 16];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          const TAcc b = bs[(kk + (lane >> 4)) * SB + t * 16 + (lane & 15)];
-          acc[t] = mfma(a, b, acc[t]);
+      for (int kq = 0; kq < BK / 4; ++kq) {
+        const int cur = kq & 1, nxt = cur ^ 1;
+        if (kq + 1 < BK / 4) {
+          av[nxt] = as[(kq + 1) * 4 * SA];
+#pragma unroll
+          for (int t = 0; t < NT; ++t) bv[nxt][t] = bs[(kq + 1) * 4 * SB + t * 16];
         }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = mfma(av[cur], bv[cur][t], acc[t]);
       }
       if (it + 1 < ntile) sstore(buf ^ 1);
       __syncthreads();

@@ -88,7 +88,7 @@ struct GemmDesc {
   bool b_rows_padded = false;   // every row of B is allocated up to round_up(N, 4)
 };
 size_t gemm_part_bytes(const GemmDesc& d);
-int gemm_pick_splitk(int64_t M, int64_t N, int64_t K, int num_cus);
+int gemm_pick_splitk(int64_t M, int64_t N, int64_t K, int num_cus, bool acc64);
 // Split count for this descriptor (the FP32 thin kernel has its own choice).
 int gemm_pick_splitk_desc(const GemmDesc& d, int num_cus);
 // FP32 thin-output kernel (gemm_thin.hip), used by gemm_launch when eligible.
