@@ -44,7 +44,7 @@ namespace cr {
 
 constexpr int kRT = 256;
 constexpr int kRW = kRT / 64;
-constexpr int kRecWords = 8;   // words per record (3 used, 5 in tolerance mode)
+constexpr int kRecWords = 8;   // words per record (2 used, 4 in tolerance mode)
 
 __device__ __forceinline__ uint64_t stamp32(uint32_t s, uint32_t payload) { return ((uint64_t)s << 32) | payload; }
 
@@ -191,6 +191,31 @@ struct Words<double> {
   }
 };
 
+// 16 bytes (two stamped words) read coherently across XCDs: a buffer load with
+// the sc1 policy, marked volatile so that it is never hoisted out of a polling
+// loop. One wide load per record (and per pair of column rows) instead of one
+// per word: every workgroup reads every record, and the hot lines serve fewer
+// requests.
+typedef unsigned cr_u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void cload16(__amdgpu_buffer_rsrc_t rs, uint32_t byte_off, uint64_t& w0, uint64_t& w1) {
+  const cr_u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)byte_off, 0, (int)(16u | 0x80000000u));
+  w0 = ((uint64_t)v[1] << 32) | v[0];
+  w1 = ((uint64_t)v[3] << 32) | v[2];
+}
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, 0x7fffffff, 0x00020000);
+}
+// Records: two (tolerance mode: four) words, each with the publish index in its
+// top 16 bits: [s | v >> 16], [s | v & 0xffff | column], [s | tot >> 16],
+// [s | tot & 0xffff].
+__device__ __forceinline__ uint64_t rec_hi(uint32_t s16, uint64_t bits) { return ((uint64_t)s16 << 48) | (bits >> 16); }
+__device__ __forceinline__ uint64_t rec_lo(uint32_t s16, uint64_t bits, uint32_t low) {
+  return ((uint64_t)s16 << 48) | ((bits & 0xffffull) << 32) | low;
+}
+__device__ __forceinline__ uint64_t rec_bits(uint64_t hi, uint64_t lo) {
+  return ((hi & 0xffffffffffffull) << 16) | ((lo >> 32) & 0xffffull);
+}
+
 // x where keep, else +0, without a branch (the compiler may otherwise move a
 // load feeding a select into a conditional block with its own wait)
 __device__ __forceinline__ float keep_or_zero(float x, bool keep) {
@@ -233,6 +258,7 @@ __global__ __launch_bounds__(kRT) void cpqr_reg_kernel(CpqrArgs a) {
   // norm of its rows at or below the publish index (2 words)
   uint64_t* cvals = static_cast<uint64_t*>(a.cvals);
   constexpr int CW = R * RPL * WN + 2;
+  const __amdgpu_buffer_rsrc_t rs_rec = buf_rsrc(a.rec), rs_cv = buf_rsrc(a.cvals);
   static_assert(R * RPL > 0, "");
   const bool exact = a.norms_exact != 0;
   const bool tolmode = a.tol > 0.0;
@@ -327,12 +353,14 @@ __global__ __launch_bounds__(kRT) void cpqr_reg_kernel(CpqrArgs a) {
     uint64_t* dst = cvals + ((size_t)par * G + g) * CW;
     if (tid == 0) {
       uint64_t* r = recs + ((size_t)par * G + g) * kRecWords;
-      cstore(r + 0, stamp32(st, (uint32_t)__double2hiint(b.v)));
-      cstore(r + 1, stamp32(st, (uint32_t)__double2loint(b.v)));
-      cstore(r + 2, stamp32(st, (uint32_t)b.i));
+      const uint32_t s16 = st & 0xffffu;
+      const uint64_t vb = (uint64_t)__double_as_longlong(b.v);
+      cstore(r + 0, rec_hi(s16, vb));
+      cstore(r + 1, rec_lo(s16, vb, (uint32_t)b.i));
       if (tolmode) {
-        cstore(r + 3, stamp32(st, (uint32_t)__double2hiint(tot)));
-        cstore(r + 4, stamp32(st, (uint32_t)__double2loint(tot)));
+        const uint64_t tb = (uint64_t)__double_as_longlong(tot);
+        cstore(r + 2, rec_hi(s16, tb));
+        cstore(r + 3, rec_lo(s16, tb, 0u));
       }
     }
     if (b.i != 0x7fffffff && grp == (b.i - c0) % NGR) {
@@ -365,19 +393,17 @@ __global__ __launch_bounds__(kRT) void cpqr_reg_kernel(CpqrArgs a) {
     double ssq = 0.0;
     int tmo = 0;
     if (tid < G) {
-      const uint64_t* r = recs + ((size_t)par * G + tid) * kRecWords;
+      const uint32_t off = (uint32_t)(((size_t)par * G + tid) * kRecWords * sizeof(uint64_t));
+      const uint64_t s16 = st & 0xffffu;
       long spins = 0;
       while (true) {
-        uint64_t w[5];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) w[q] = q < nwords ? cload(r + q) : stamp32(st, 0);
-        bool ok = true;
-#pragma unroll
-        for (int q = 0; q < 5; ++q) ok = ok && (uint32_t)(w[q] >> 32) == st;
-        if (ok) {
-          c.v = __hiloint2double((int)(uint32_t)w[0], (int)(uint32_t)w[1]);
-          c.i = (int)(uint32_t)w[2];
-          ssq = tolmode ? __hiloint2double((int)(uint32_t)w[3], (int)(uint32_t)w[4]) : 0.0;
+        uint64_t w0, w1, w2 = s16 << 48, w3 = s16 << 48;
+        cload16(rs_rec, off, w0, w1);
+        if (tolmode) cload16(rs_rec, off + 16, w2, w3);
+        if ((w0 >> 48) == s16 && (w1 >> 48) == s16 && (w2 >> 48) == s16 && (w3 >> 48) == s16) {
+          c.v = __longlong_as_double((long long)rec_bits(w0, w1));
+          c.i = (int)(uint32_t)w1;
+          ssq = tolmode ? __longlong_as_double((long long)rec_bits(w2, w3)) : 0.0;
           break;
         }
         __builtin_amdgcn_s_sleep(1);
@@ -425,31 +451,40 @@ __global__ __launch_bounds__(kRT) void cpqr_reg_kernel(CpqrArgs a) {
     T v[RPL];
     double x0 = 0.0, xnorm = 0.0;
     if (stop == 0) {
-      const uint64_t* src = cvals + ((size_t)par * G + w.i / cpw) * CW;   // the owner's slot
+      // the owner's slot, 16 bytes per load: two rows of a float column, one row
+      // of a double column; the thread with the last index takes the norm
+      const uint32_t slot = (uint32_t)(((size_t)par * G + w.i / cpw) * CW * sizeof(uint64_t));
       bool ok = true;
+      auto fetch = [&](uint32_t byte_off, uint64_t& a0, uint64_t& a1) {
+        long spins = 0;
+        while (true) {
+          cload16(rs_cv, byte_off, a0, a1);
+          if ((uint32_t)(a0 >> 32) == st && (uint32_t)(a1 >> 32) == st) return;
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins > kSpinLimit) {
+            ok = false;
+            return;
+          }
+        }
+      };
       if (tid == kRT - 1) {
-        long spins = 0;
-        double xn = 0.0;
-        while (!Words<double>::get(src + (size_t)R * RPL * WN, st, xn)) {
-          __builtin_amdgcn_s_sleep(1);
-          if (++spins > kSpinLimit) {
-            ok = false;
-            break;
-          }
-        }
-        s_xnorm = xn;
+        uint64_t a0, a1;
+        fetch(slot + (uint32_t)(R * RPL * WN) * 8u, a0, a1);
+        s_xnorm = __hiloint2double((int)(uint32_t)a0, (int)(uint32_t)a1);
       }
-      for (int i = j + tid; i < l; i += kRT) {
-        long spins = 0;
-        T val;
-        while (!Words<T>::get(src + (size_t)i * WN, st, val)) {
-          __builtin_amdgcn_s_sleep(1);
-          if (++spins > kSpinLimit) {
-            ok = false;
-            break;
-          }
+      if constexpr (WN == 1) {
+        for (int q = (j >> 1) + tid; 2 * q < l; q += kRT) {
+          uint64_t a0, a1;
+          fetch(slot + (uint32_t)(2 * q) * 8u, a0, a1);
+          vbuf[2 * q] = __uint_as_float((uint32_t)a0);
+          vbuf[2 * q + 1] = __uint_as_float((uint32_t)a1);
         }
-        vbuf[i] = val;
+      } else {
+        for (int i = j + tid; i < l; i += kRT) {
+          uint64_t a0, a1;
+          fetch(slot + (uint32_t)(2 * i) * 8u, a0, a1);
+          vbuf[i] = (T)__hiloint2double((int)(uint32_t)a0, (int)(uint32_t)a1);
+        }
       }
       // every thread either has its words or has given up; agree on the outcome
       if (!ok) s_vfail = 1;
