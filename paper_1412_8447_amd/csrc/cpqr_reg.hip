@@ -28,7 +28,7 @@ size_t cpqr_reg_lds_bytes(int cfg, int kmax_host, int cols_per_wg, int dtype_siz
   return ((size_t)kmax_host + (size_t)cols_per_wg) * sizeof(int) / 16 * 16 + 16 + (size_t)c.R * c.RPL * dtype_size;
 }
 
-size_t cpqr_reg_rec_bytes(int G) { return 2 * (size_t)G * kRecWords * sizeof(uint64_t); }
+size_t cpqr_reg_rec_bytes(int G) { return 2 * (size_t)kRep * G * kRecWords * sizeof(uint64_t); }
 size_t cpqr_reg_cvals_bytes(int cfg, int G, int dtype_size) {
   const RegCfg c = kRegCfgs[cfg];
   return 2 * (size_t)G * ((size_t)c.R * c.RPL * (dtype_size / 4) + 2) * sizeof(uint64_t);

@@ -45,6 +45,11 @@ namespace cr {
 constexpr int kRT = 256;
 constexpr int kRW = kRT / 64;
 constexpr int kRecWords = 8;   // words per record (2 used, 4 in tolerance mode)
+// Every record is written in kRep copies; workgroup g reads copy g % kRep (its
+// XCD, with round-robin placement), so each hot line serves about G / kRep
+// readers instead of G. (Copies of the candidate columns cost more to write than
+// they saved.)
+constexpr int kRep = 8;
 
 __device__ __forceinline__ uint64_t stamp32(uint32_t s, uint32_t payload) { return ((uint64_t)s << 32) | payload; }
 
@@ -350,10 +355,9 @@ __global__ __launch_bounds__(kRT) void cpqr_reg_kernel(CpqrArgs a) {
       tot += p_s[w];
     }
     const int par = e & 1;
-    uint64_t* dst = cvals + ((size_t)par * G + g) * CW;
-    if (tid == 0) {
-      uint64_t* r = recs + ((size_t)par * G + g) * kRecWords;
-      const uint32_t s16 = st & 0xffffu;
+    const uint32_t s16 = st & 0xffffu;
+    if (tid < kRep) {
+      uint64_t* r = recs + (((size_t)par * kRep + tid) * G + g) * kRecWords;
       const uint64_t vb = (uint64_t)__double_as_longlong(b.v);
       cstore(r + 0, rec_hi(s16, vb));
       cstore(r + 1, rec_lo(s16, vb, (uint32_t)b.i));
@@ -364,6 +368,7 @@ __global__ __launch_bounds__(kRT) void cpqr_reg_kernel(CpqrArgs a) {
       }
     }
     if (b.i != 0x7fffffff && grp == (b.i - c0) % NGR) {
+      uint64_t* dst = cvals + ((size_t)par * G + g) * CW;
       // every slot, by row: readers take rows [e, l) only
 #pragma unroll
       for (int t = 0; t < RPL; ++t) Words<T>::put(dst + (size_t)(rgi + R * t) * WN, st, yb[t]);
@@ -393,7 +398,7 @@ __global__ __launch_bounds__(kRT) void cpqr_reg_kernel(CpqrArgs a) {
     double ssq = 0.0;
     int tmo = 0;
     if (tid < G) {
-      const uint32_t off = (uint32_t)(((size_t)par * G + tid) * kRecWords * sizeof(uint64_t));
+      const uint32_t off = (uint32_t)((((size_t)par * kRep + g % kRep) * G + tid) * kRecWords * sizeof(uint64_t));
       const uint64_t s16 = st & 0xffffu;
       long spins = 0;
       while (true) {
