@@ -51,6 +51,7 @@ struct CArgs {
   double* X; int64_t ldx;             // inverse (lower, zeros above)
   double shift_rel;
   int mode;
+  int keep_l;   // mode 0: store the factor to L (else L is only the working matrix)
   int* status;
 };
 
@@ -179,7 +180,7 @@ __device__ __forceinline__ double readlane_d(double x, int l) {
 // compiler keeps none of it alive across the panel loop) ----------------------
 
 // phase 2, mode 0: L(r, p) = A(r, p) D_p^T into LDS and L; mode 1: L(r, p) into LDS
-__device__ __noinline__ void item_panel(View A, double* L, int64_t ldl, int r, int p, int D, bool m0) {
+__device__ __noinline__ void item_panel(View A, double* L, int64_t ldl, int r, int p, int D, bool m0, bool keep_l) {
   const int P = kPan + (r - 1) * kTile;
   tile_from_view(P, A, r * kTS, p * kTS);
   if (m0) {
@@ -187,7 +188,7 @@ __device__ __noinline__ void item_panel(View A, double* L, int64_t ldl, int r, i
     acc_zero(acc);
     tile_mma<true>(acc, P, D, 1.0);
     acc_to_lds(acc, P);
-    acc_store(acc, L, ldl, r * kTS, p * kTS, A.c, false);
+    if (keep_l) acc_store(acc, L, ldl, r * kTS, p * kTS, A.c, false);
   }
 }
 
@@ -275,16 +276,61 @@ __device__ __noinline__ void phase3_items(View A, double* L, int64_t ldl, View X
   }
 }
 
+// ---- the diagonal tile, as a 2 x 2 block recursion on 16 x 16 blocks ---------
+// Cholesky of a 16 x 16 block in registers: lane i (< 16) holds row i, pivot
+// columns are broadcast with v_readlane (lanes 16..63 repeat lanes 0..15).
+__device__ __forceinline__ void chol16(double (&r)[16], bool& bad) {
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    double akk = readlane_d(r[k], k);
+    bad = bad || !(akk > 0.0);
+    akk = (akk > 0.0) ? akk : 1e-300;
+    const double inv = rsqrt_nr(akk);
+    // row k's own entry becomes akk / sqrt(akk), the pivot; rows above k only
+    // ever change entries above their diagonal
+    const double lk = r[k] * inv;
+    r[k] = lk;
+#pragma unroll
+    for (int j = k + 1; j < 16; ++j) r[j] = fma(-lk, readlane_d(r[k], j), r[j]);
+  }
+}
+
+// X = L^{-1} for the lower-triangular 16 x 16 block of the tile at (o, o) of
+// kDg, into the block (o, o) of out: lane i (< 16) forms column i by forward
+// substitution from the unit vector (zeros above the diagonal), column-oriented:
+// once x[t] is final it is subtracted from all later rows, so the dependent
+// chain is two operations per row.
+__device__ __forceinline__ void inv16(int o, int out) {
+  const int lane = threadIdx.x & 63, i = lane & 15;
+  if (lane < 16) sm[kRinv + o + i] = 1.0 / sm[kDg + (o + i) * kTL + o + i];
+  double x[16];
+#pragma unroll
+  for (int ii = 0; ii < 16; ++ii) x[ii] = sm[kOnehot + 32 + i - ii];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    x[t] *= sm[kRinv + o + t];
+#pragma unroll
+    for (int ii = t + 1; ii < 16; ++ii) x[ii] = fma(-sm[kDg + (o + ii) * kTL + o + t], x[t], x[ii]);
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int ii = 0; ii < 16; ++ii) sm[out + (o + ii) * kTL + o + i] = x[ii];
+  }
+}
+
 // One wave: diagonal tile q (after the update by panel q-1, whose L(q, q-1)
-// sits in the panel buffer when upd is set). mode 0: Cholesky of the tile in
-// registers (one row per lane, pivot columns broadcast with v_readlane), rows
-// stored to L; mode 1: the tile of the given factor. Then dout <- L_qq^{-1},
-// a column per lane starting from the unit vector (zeros above the diagonal).
-// No step depends on a lane predicate, so the unrolled code keeps no per-lane
-// masks alive.
+// sits in the panel buffer when upd is set). With the tile [A11 .; A21 A22] in
+// 16 x 16 blocks:
+//   mode 0:  L11 = chol(A11), X11 = L11^{-1}, L21 = A21 X11^T,
+//            L22 = chol(A22 - L21 L21^T), X22 = L22^{-1};
+//   mode 1:  the blocks of the given factor, X11 and X22 the same way;
+//   both:    X21 = -X22 (L21 X11), so dout <- L_qq^{-1} = [X11 0; X21 X22].
+// The 16 x 16 products run on the FP64 matrix cores (v_mfma_f64_16x16x4f64,
+// 4 k steps each); the serial chains are two 16-column eliminations and two
+// 16-row substitutions instead of 32 + 32. L_qq goes to L (mode 0).
 __device__ __noinline__ void item_diag(View A, double* L, int64_t ldl, int q, bool upd, int dout, bool m0,
-                                       int* status) {
-  const int lane = threadIdx.x & 63, i = lane & 31;
+                                       bool keep_l, int* status) {
+  const int lane = threadIdx.x & 63, i = lane & 15, g = lane >> 4;
   const int q0 = q * kTS;
   if (m0) {
     Acc acc;
@@ -294,50 +340,69 @@ __device__ __noinline__ void item_diag(View A, double* L, int64_t ldl, int q, bo
   } else {
     tile_from_view(kDg, A, q0, q0);
   }
+  bool bad = false;
   if (m0) {
-    double r[kTS];   // row i (entries above the diagonal are scratch)
+    double r[16];
 #pragma unroll
-    for (int j = 0; j < kTS; ++j) r[j] = sm[kDg + i * kTL + j];
-    bool bad = false;
+    for (int j = 0; j < 16; ++j) r[j] = sm[kDg + i * kTL + j];
+    chol16(r, bad);
+    if (lane < 16) {
 #pragma unroll
-    for (int k = 0; k < kTS; ++k) {
-      double akk = readlane_d(r[k], k);
-      bad = bad || !(akk > 0.0);
-      akk = (akk > 0.0) ? akk : 1e-300;
-      const double inv = rsqrt_nr(akk);
-      // row k's own entry becomes akk / sqrt(akk), the pivot; rows above k
-      // (i < k) only ever change entries above their diagonal
-      const double lk = r[k] * inv;
-      r[k] = lk;
-#pragma unroll
-      for (int j = k + 1; j < kTS; ++j) r[j] = fma(-lk, readlane_d(r[k], j), r[j]);
-    }
-    if (bad && lane == 0) set_status(status, ST_NONFINITE);
-    if (lane < kTS) {
-#pragma unroll
-      for (int j = 0; j < kTS; ++j) sm[kDg + i * kTL + j] = r[j];
-      if (q0 + i < A.c) {
-#pragma unroll
-        for (int j = 0; j < kTS; ++j)
-          if (j <= i) L[(int64_t)(q0 + i) * ldl + q0 + j] = r[j];
-      }
+      for (int j = 0; j < 16; ++j) sm[kDg + i * kTL + j] = r[j];
     }
   }
-  if (lane < kTS) sm[kRinv + i] = 1.0 / sm[kDg + i * kTL + i];
-  double x[kTS];
+  inv16(0, dout);
+  if (lane < 16) {
 #pragma unroll
-  for (int ii = 0; ii < kTS; ++ii) x[ii] = sm[kOnehot + 32 + i - ii];
-#pragma unroll
-  for (int ii = 0; ii < kTS; ++ii) {
-    // four interleaved partial sums keep the dependent chain short
-    double s[4] = {x[ii], 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int t = 0; t < ii; ++t) s[t & 3] = fma(-sm[kDg + ii * kTL + t], x[t], s[t & 3]);
-    x[ii] = ((s[0] + s[1]) + (s[2] + s[3])) * sm[kRinv + ii];
+    for (int ii = 0; ii < 16; ++ii) sm[dout + ii * kTL + 16 + i] = 0.0;   // X12 = 0
   }
-  if (lane < kTS) {
+  // f64 16x16x4 operands: lane L holds A(L%16, 4kk + L/16) and B(4kk + L/16, L%16);
+  // result register t of lane L is C(L/16 + 4t, L%16)
+  if (m0) {
+    d4 c = d4{0.0, 0.0, 0.0, 0.0};   // L21 = A21 X11^T
 #pragma unroll
-    for (int ii = 0; ii < kTS; ++ii) sm[dout + ii * kTL + i] = x[ii];
+    for (int kk = 0; kk < 4; ++kk)
+      c = __builtin_amdgcn_mfma_f64_16x16x4f64(sm[kDg + (16 + i) * kTL + 4 * kk + g], sm[dout + i * kTL + 4 * kk + g], c, 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) sm[kDg + (16 + g + 4 * t) * kTL + i] = c[t];
+    d4 s22;   // A22 - L21 L21^T
+#pragma unroll
+    for (int t = 0; t < 4; ++t) s22[t] = sm[kDg + (16 + g + 4 * t) * kTL + 16 + i];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const double l = sm[kDg + (16 + i) * kTL + 4 * kk + g];
+      s22 = __builtin_amdgcn_mfma_f64_16x16x4f64(-l, l, s22, 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) sm[kDg + (16 + g + 4 * t) * kTL + 16 + i] = s22[t];
+    double r[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) r[j] = sm[kDg + (16 + i) * kTL + 16 + j];
+    chol16(r, bad);
+    if (lane < 16) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) sm[kDg + (16 + i) * kTL + 16 + j] = r[j];
+    }
+  }
+  inv16(16, dout);
+  {
+    d4 pm = d4{0.0, 0.0, 0.0, 0.0};   // P = L21 X11
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+      pm = __builtin_amdgcn_mfma_f64_16x16x4f64(sm[kDg + (16 + i) * kTL + 4 * kk + g], sm[dout + (4 * kk + g) * kTL + i], pm, 0, 0, 0);
+    // X21 = -X22 P: the B operand P(4kk + L/16, L%16) is result register kk of lane L
+    d4 x21 = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+      x21 = __builtin_amdgcn_mfma_f64_16x16x4f64(-sm[dout + (16 + i) * kTL + 16 + 4 * kk + g], pm[kk], x21, 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) sm[dout + (16 + g + 4 * t) * kTL + i] = x21[t];
+  }
+  if (bad && lane == 0) set_status(status, ST_NONFINITE);
+  if (m0 && keep_l && lane < kTS && q0 + lane < A.c) {
+#pragma unroll
+    for (int j = 0; j < kTS; ++j)
+      if (j <= lane) L[(int64_t)(q0 + lane) * ldl + q0 + j] = sm[kDg + lane * kTL + j];
   }
 }
 
@@ -396,7 +461,7 @@ __global__ __launch_bounds__(kCT) void chol_inv_kernel(CArgs a) {
     if (p >= 0) {
       // ---- phase 2 --------------------------------------------------------------
       for (int it = wv; it < T; it += kWaves) {
-        if (it < m) item_panel(A, L, a.ldl, p + 1 + it, p, D, m0);
+        if (it < m) item_panel(A, L, a.ldl, p + 1 + it, p, D, m0, a.keep_l != 0);
         else if (it == m) item_store_d(X, a.ldx, p, D, c);
         else item_xrow(XV, X, a.ldx, p, it - m - 1, D);
       }
@@ -405,7 +470,7 @@ __global__ __launch_bounds__(kCT) void chol_inv_kernel(CArgs a) {
     }
     // ---- phase 3 ----------------------------------------------------------------
     if (wv == 0) {
-      item_diag(A, L, a.ldl, p + 1, p >= 0, kDbuf + ((p + 1) & 1) * kTile, m0, a.status);
+      item_diag(A, L, a.ldl, p + 1, p >= 0, kDbuf + ((p + 1) & 1) * kTile, m0, a.keep_l != 0, a.status);
     } else if (p >= 0) {
       phase3_items(A, L, a.ldl, XV, X, a.ldx, p, m, m0, D, wv - 1);
     }
@@ -421,13 +486,15 @@ size_t chol_inv_lds_bytes(int c_host) {
 }
 
 hipError_t chol_inv_launch(int mode, const double* G, int64_t gr, int64_t gc, int c_host, const int* c_dev, double* L,
-                           int64_t ldl, double* X, int64_t ldx, double shift_rel, int* status, hipStream_t stream) {
+                           int64_t ldl, double* X, int64_t ldx, double shift_rel, int* status, hipStream_t stream,
+                           int keep_l) {
   if (c_host <= 0) return hipSuccess;
   if (c_host > kMaxC) return hipErrorInvalidValue;
   if (mode == 0 && !L) return hipErrorInvalidValue;
   CArgs a{};
   a.G = G; a.gr = gr; a.gc = gc; a.c_host = c_host; a.c_dev = c_dev;
   a.L = L; a.ldl = ldl; a.X = X; a.ldx = ldx; a.shift_rel = shift_rel; a.mode = mode; a.status = status;
+  a.keep_l = keep_l;
   const size_t lds = chol_inv_lds_bytes(c_host);
   hipError_t e = hipFuncSetAttribute((const void*)chol_inv_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;

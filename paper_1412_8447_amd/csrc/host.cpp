@@ -154,9 +154,9 @@ void gemm(const Ctx& x, GemmDesc d, const char* stage = nullptr) {
 constexpr int kCholDirect = 256;
 
 void chol_inv(const Ctx& x, int mode, const double* G, int64_t gr, int64_t gc, int c, const int* c_dev, double* L,
-              int64_t ldl, double* X, int64_t ldx, double shift_rel, const char* what) {
+              int64_t ldl, double* X, int64_t ldx, double shift_rel, const char* what, bool keep_l = true) {
   if (c <= kCholDirect) {
-    if (!x.dry) x.check(chol_inv_launch(mode, G, gr, gc, c, c_dev, L, ldl, X, ldx, shift_rel, x.c->dstatus, x.s), what);
+    if (!x.dry) x.check(chol_inv_launch(mode, G, gr, gc, c, c_dev, L, ldl, X, ldx, shift_rel, x.c->dstatus, x.s, keep_l), what);
     return;
   }
   const int nb = (int)ceil_div(c, kCholDirect);
@@ -222,7 +222,7 @@ void orth_rows(const Ctx& x, int dtype, const void* Vt, void* Qt, int64_t N, int
   g.in_type = dtype; g.acc_type = 0; g.out_type = 0;
   g.alpha = 1.0; g.beta = 0.0;
   gemm(x, g);
-  chol_inv(x, 0, G, l, 1, l, nullptr, L, l, Li, l, 1e-14, "chol");
+  chol_inv(x, 0, G, l, 1, l, nullptr, L, l, Li, l, 1e-14, "chol", false);   // only L^{-1} is used
   GemmDesc q{};   // Q^T = V^T L^{-T}
   q.M = N; q.N = l; q.K = l;
   q.A = Vt; q.sam = ld; q.sak = 1;
@@ -512,12 +512,12 @@ void solve_u(const Ctx& x, int dtype, const void* R, int64_t ldr, int64_t n, int
   };
   // G1 = R R^T, L1 L1^T = G1
   prod(kcap, kcap, n, R, ldr, 1, dtype, R, 1, ldr, dtype, G, kcap, 0, kr_dev, kr_dev, nullptr);
-  chol_inv(x, 0, G, kcap, 1, kcap, kr_dev, L1, kcap, L1i, kcap, 1e-15, "chol(R)");
+  chol_inv(x, 0, G, kcap, 1, kcap, kr_dev, L1, kcap, L1i, kcap, 1e-15, "chol(R)", false);
   // Q1^T = L1^{-1} R
   prod(kcap, n, kcap, L1i, kcap, 1, 0, R, ldr, 1, dtype, Q1t, n, 0, kr_dev, nullptr, kr_dev);
   // G2 = Q1^T Q1, L2 L2^T = G2, Q^T = L2^{-1} Q1^T
   prod(kcap, kcap, n, Q1t, n, 1, 0, Q1t, 1, n, 0, G, kcap, 0, kr_dev, kr_dev, nullptr);
-  chol_inv(x, 0, G, kcap, 1, kcap, kr_dev, L2, kcap, L2i, kcap, 0.0, "chol(Q1)");
+  chol_inv(x, 0, G, kcap, 1, kcap, kr_dev, L2, kcap, L2i, kcap, 0.0, "chol(Q1)", false);
   prod(kcap, n, kcap, L2i, kcap, 1, 0, Q1t, n, 1, 0, Qt, n, 0, kr_dev, nullptr, kr_dev);
   // Bls = Q^T V (kr x k)
   if (!x.dry) x.check(build_v_launch(dtype, T, ldt, J, n, kcap, k_dev, V, kcap, x.s), "build V");
@@ -779,7 +779,7 @@ void id_col_backward(const Ctx& x, int dtype, int64_t m, int64_t n, const void* 
   } else {
     mm(k, k, m, Aj, 1, n, dtype, Aj, n, 1, dtype, Gr, k, F64, 1.0, 0.0, 0);
   }
-  chol_inv(x, 0, Gr, k, 1, k, nullptr, Lf, k, Li, k, 0.0, "chol(Y1^T Y1)");
+  chol_inv(x, 0, Gr, k, 1, k, nullptr, Lf, k, Li, k, 0.0, "chol(Y1^T Y1)", false);
   // M = Li^T (Li Tbar) = (Y1^T Y1)^{-1} Tbar;  TMt = T M^T
   mm(k, n2, k, Li, k, 1, F64, Tb, n2, 1, F64, W, n2, F64, 1.0, 0.0, 0);
   mm(k, n2, k, Li, 1, k, F64, W, n2, 1, F64, M, n2, F64, 1.0, 0.0, 0);

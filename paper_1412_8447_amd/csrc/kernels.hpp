@@ -173,8 +173,11 @@ hipError_t batched_launch(const BatchedArgs& a, int variant, int num_cus, hipStr
 // A non-positive pivot is clamped and reported through `status`.
 // ---------------------------------------------------------------------------
 size_t chol_inv_lds_bytes(int c_host);
+// keep_l = 0: mode 0 leaves L as the working matrix only (the factor is not
+// stored; callers that need just the inverse save the stores).
 hipError_t chol_inv_launch(int mode, const double* G, int64_t gr, int64_t gc, int c_host, const int* c_dev, double* L,
-                           int64_t ldl, double* X, int64_t ldx, double shift_rel, int* status, hipStream_t stream);
+                           int64_t ldl, double* X, int64_t ldx, double shift_rel, int* status, hipStream_t stream,
+                           int keep_l = 1);
 
 // S11 = S(0:c, J(0:c)) into a dense c x c double matrix (row-major, ld c_host).
 hipError_t gather_s11_launch(int dtype, const void* S, int64_t ldS, const int* J, int c_host,
