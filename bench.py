@@ -222,6 +222,101 @@ def bench_batched(args, P, synth, torch, dev, nblk=4096, tol=1e-6, kmax=24, p=8)
     return out
 
 
+def bench_adjoint(args, P, synth, torch, dev, reps=10):
+    """The differentiable-ID workload: gradient of the column-ID reconstruction
+    loss with the skeleton frozen, (a) one FP32 8192 x 4096 matrix, k = 128,
+    p = 10 (forward ID, then the backward call timed alone), and (b) 256 blocks
+    of 256 x 256, k = 32, p = 10, in one persistent launch (the backward launch
+    timed alone, replayed from a captured graph). Both are checked against the
+    FP64 oracle gradient (all of (a), a sample of the blocks of (b))."""
+    import numpy as np
+    from oracle import adjoint
+    from paper_1412_8447_amd.flops import adjoint_flops
+    out = {}
+    cfg = synth.CONFIGS["diff_fp32_8192x4096_k128"]
+    m, n, k, p = cfg.m, cfg.n, cfg.k, cfg.p
+    l = k + p
+    A = synth.noisy_lowrank_torch(m, n, cfg.spectrum(), 1e-3, seed=args.seed + 5, device=dev).to(torch.float32)
+    A = A.contiguous()
+    om = P.gaussian(l, m, seed=args.seed + 6, dtype=torch.float32)
+    r = P.id_col(A, k, p=p, q=0, omega=om)
+    dA = torch.empty_like(A)
+    ws = None
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    nb = P.backward_workspace_bytes(A, k, l, True)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    for _ in range(2):
+        P.id_col_backward(A, r.J, r.T, k, omega=om, out=dA, workspace=ws)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(reps):
+        P.id_col_backward(A, r.J, r.T, k, omega=om, out=dA, workspace=ws)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    fl = adjoint_flops(m, n, k, l)
+    J = r.J.cpu().numpy().astype(np.int64)
+    tc = time.time()
+    want = adjoint.recon_grad(A.double().cpu().numpy(), J, k, om.double().cpu().numpy())
+    t_orc = time.time() - tc
+    e = float(np.linalg.norm(dA.double().cpu().numpy() - want) / np.linalg.norm(want))
+    out["single"] = {"workload": f"FP32 {m}x{n}, sigma_j=(j+1)^-1.5 + N(0,1e-3^2), k={k}, p={p}, q=0",
+                     "ms": round(ms, 4), "gflops": round(fl / (ms * 1e-3) / 1e9, 2), "flops": fl,
+                     "oracle_rel_err": e, "oracle_seconds": round(t_orc, 2)}
+    log("adjoint single", out["single"])
+    del A, dA, ws, want
+    # (b) 256 blocks of 256 x 256
+    nblk, mb, nbk, kb, pb = 256, 256, 256, 32, 10
+    Ab = synth.noisy_lowrank_blocks_torch(nblk, mb, nbk, 1.5, 1e-3, seed=args.seed + 7, device=dev).to(torch.float32)
+    blocks = [Ab[i] for i in range(nblk)]
+    plan = P.BatchedID(blocks, k=kb, p=pb, seed=args.seed + 8)
+    plan.run()
+    plan.backward()
+    plan.grads()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.backward()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.backward()
+    g.replay()
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(reps):
+        g.replay()
+    ev1.record()
+    torch.cuda.synchronize()
+    msb = ev0.elapsed_time(ev1) / reps
+    P.sync_status(dev)
+    ks = plan.kout.cpu().tolist()
+    flb = sum(adjoint_flops(mb, nbk, kk, kb + pb) for kk in ks)
+    tfl = flb / (msb * 1e-3) / 1e12
+    bytes_b = nblk * (2.0 * 4 * mb * nbk + 4.0 * kb * (nbk - kb) + 4.0 * nbk)
+    grads = plan.grads()
+    res = plan.results()
+    omb = P.gaussian(kb + pb, mb, seed=args.seed + 8, dtype=torch.float32).double().cpu().numpy()
+    errs = []
+    for b in range(0, nblk, nblk // 8):
+        Jb = res[b].J.cpu().numpy().astype(np.int64)
+        wb = adjoint.recon_grad(Ab[b].double().cpu().numpy(), Jb, res[b].k, omb)
+        errs.append(float(np.linalg.norm(grads[b].double().cpu().numpy() - wb) / np.linalg.norm(wb)))
+    out["batched"] = {"workload": f"{nblk} blocks {mb}x{nbk}, sigma_j=(j+1)^-1.5 + N(0,1e-3^2), k={kb}, p={pb}",
+                      "launch": "one persistent launch replayed from a captured graph",
+                      "ms_per_batch": round(msb, 4), "blocks_per_s": round(nblk / (msb * 1e-3), 1),
+                      "gflops": round(flb / (msb * 1e-3) / 1e9, 2),
+                      "roofline": {"bound": "mfma", "achieved": round(tfl, 3), "peak": PEAK_FP32_MFMA_TFLOPS,
+                                   "unit": "TFLOP/s", "frac": round(tfl / PEAK_FP32_MFMA_TFLOPS, 4),
+                                   "flops_per_launch": flb,
+                                   "hbm_GBps": round(bytes_b / (msb * 1e-3) / 1e9, 1),
+                                   "bytes_per_launch": bytes_b},
+                      "oracle_sample": {"blocks": len(errs), "rel_err_max": max(errs)}}
+    log("adjoint batched", out["batched"])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,6 +327,8 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the BF16 / FP16 sketch measurements")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched kernel-block measurement")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable-ID (adjoint) measurements")
+    ap.add_argument("--adjoint-only", action="store_true", help="only run the adjoint measurements")
     ap.add_argument("--no-library-gemm", action="store_true",
                     help="skip timing torch's FP32 GEMM on the sketch shape (context for the roofline)")
     ap.add_argument("--batched-only", action="store_true",
@@ -265,6 +362,9 @@ def main():
         return
     if args.batched_only:
         print(json.dumps({"batched": bench_batched(args, P, synth, torch, dev)}), flush=True)
+        return
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": bench_adjoint(args, P, synth, torch, dev)}), flush=True)
         return
     cfg = synth.CONFIGS["rand_fp32_20000x10000_k200"]
     m, n, k, p, q = cfg.m, cfg.n, cfg.k, cfg.p, cfg.q
@@ -401,6 +501,10 @@ def main():
     # replayed from a captured graph)
     if not args.no_batched:
         result["batched"] = bench_batched(args, P, synth, torch, dev)
+
+    # gradient of the ID reconstruction loss (single matrix and 256 blocks)
+    if not args.no_adjoint:
+        result["adjoint"] = bench_adjoint(args, P, synth, torch, dev)
 
     # plain FP32 GPU CPQR comparator (no sketch) and the equal-error sweep
     if not args.no_comparator:

@@ -280,6 +280,41 @@ idcur_status idcur_id_col_batched_autotune(idcur_ctx* ctx, int32_t dtype, int32_
                                            const int64_t* lda, const idcur_opts* opts, void* ws, size_t ws_bytes,
                                            int32_t* k_out, int32_t* const* J, void* const* T, const int64_t* ldt,
                                            int32_t* variant /* host out */);
+/* Batched gradient of the reconstruction loss of fixed-rank column IDs, each
+ * block's skeleton frozen: the adjoint of idcur_id_col_batched with opts->k > 0,
+ * block by block the derivative that idcur_id_col_backward computes for one
+ * matrix, in one persistent launch. For block b (m[b] x n[b] FP32, row-major at
+ * A[b], ld lda[b]):
+ *   Y_b = Omega(:l, :m_b) A_b,  l = opts->k + opts->p, Omega the l x mmax matrix
+ *         the batched ID draws (from opts->seed, or opts->omega: l x mmax
+ *         row-major FP32, ld mmax),
+ *   T_b = argmin_X |Y_b(:,J1) X - Y_b(:,J2)|_F (Section 2.3 on the sketch of
+ *         Section 5.1), J1 = J_b[0..k_b-1], J2 = the rest,
+ *   L_b = |A_b(:,J2) - A_b(:,J1) T_b|_F^2,
+ *   dA_b = scale * dL_b / dA_b with J_b and Omega held fixed (written to dA[b],
+ *          m_b x n_b row-major, ld ldd[b] >= n_b; overwritten).
+ * k (device int32[nblk]) holds each block's rank k_b, 0 <= k_b <= opts->k (the
+ * forward call's k_out); J (pointers to int32[n_b], permutations) and T
+ * (pointers to FP32 k_b x (n_b - k_b), ld ldt[b]) as idcur_id_col_batched writes
+ * them. m, n, A, lda, mmax, nmax as there. Limits: n_b <= nmax <= 512,
+ * m_b <= mmax, opts->k + opts->p <= 64, p >= 1, q = 0, NATIVE precision, dtype
+ * IDCUR_F32, lda[b] >= n_b, ldt[b] >= n_b - k_b. The m x n products run on the
+ * FP32 matrix cores (FP32 sums); Y1^T Y1, its Cholesky factor and inverse are
+ * FP64. A block outside the limits,
+ * or a J_b that is not a permutation of 0..n_b-1, is reported as IDCUR_EINVAL by
+ * idcur_sync_status (that block's dA_b is then left unwritten or undefined); a
+ * singular Y1^T Y1 as IDCUR_ENONFINITE. The call only enqueues kernels on the
+ * context's stream (no allocation, no host synchronisation, no memset node).
+ * Workspace from idcur_id_col_batched_backward_workspace_bytes. */
+idcur_status idcur_id_col_batched_backward_workspace_bytes(idcur_ctx* ctx, int32_t dtype, int32_t nblk,
+                                                           int32_t mmax, int32_t nmax, const idcur_opts* opts,
+                                                           size_t* bytes /* host out */);
+idcur_status idcur_id_col_batched_backward(idcur_ctx* ctx, int32_t dtype, int32_t nblk, int32_t mmax, int32_t nmax,
+                                           const int32_t* m, const int32_t* n, const void* const* A,
+                                           const int64_t* lda, const idcur_opts* opts, const int32_t* k,
+                                           const int32_t* const* J, const void* const* T, const int64_t* ldt,
+                                           double scale, void* const* dA, const int64_t* ldd, void* ws,
+                                           size_t ws_bytes);
 /* Force a launch variant (0 .. 7) for every later batched call on this context;
  * -1 returns to the tuned or default choice. */
 idcur_status idcur_id_col_batched_set_variant(idcur_ctx* ctx, int32_t variant);

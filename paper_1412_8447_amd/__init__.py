@@ -101,10 +101,14 @@ _lib.idcur_cur_error.argtypes = [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _v
 _lib.idcur_id_col_backward_workspace_bytes.argtypes = [_vp, _i32, _i64, _i64, _i32, _i32, _i32, ctypes.POINTER(_sz)]
 _lib.idcur_id_col_backward.argtypes = [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _i32, _vp, _i32, _vp, _i64,
                                        ctypes.c_double, _vp, _i64, _vp, _sz]
+_lib.idcur_id_col_batched_backward_workspace_bytes.argtypes = [_vp, _i32, _i32, _i32, _i32, ctypes.POINTER(Opts),
+                                                                ctypes.POINTER(_sz)]
+_lib.idcur_id_col_batched_backward.argtypes = [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, ctypes.POINTER(Opts),
+                                               _vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _sz]
 _lib.idcur_timing_enable.argtypes = [_vp, _i32]
 _lib.idcur_timing_read.argtypes = [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32)]
 for _f in ("idcur_error_workspace_bytes", "idcur_id_error", "idcur_cur_error", "idcur_id_col_backward_workspace_bytes",
-           "idcur_id_col_backward",
+           "idcur_id_col_backward", "idcur_id_col_batched_backward_workspace_bytes", "idcur_id_col_batched_backward",
            "idcur_timing_enable", "idcur_timing_read", "idcur_create", "idcur_set_stream", "idcur_destroy", "idcur_sync_status", "idcur_workspace_bytes",
            "idcur_id_col", "idcur_id_row", "idcur_id_two_sided", "idcur_cur", "idcur_gaussian", "idcur_sketch",
            "idcur_id_col_batched_workspace_bytes", "idcur_id_col_batched", "idcur_id_col_batched_autotune",
@@ -116,7 +120,8 @@ EXPORTED = ("idcur_opts_default", "idcur_create", "idcur_set_stream", "idcur_des
             "idcur_cur", "idcur_gaussian", "idcur_timing_enable", "idcur_timing_read", "idcur_error_workspace_bytes",
             "idcur_id_error", "idcur_cur_error", "idcur_id_col_backward_workspace_bytes", "idcur_id_col_backward",
             "idcur_sketch", "idcur_id_col_batched_workspace_bytes", "idcur_id_col_batched",
-            "idcur_id_col_batched_autotune", "idcur_id_col_batched_set_variant")
+            "idcur_id_col_batched_autotune", "idcur_id_col_batched_set_variant",
+            "idcur_id_col_batched_backward_workspace_bytes", "idcur_id_col_batched_backward")
 
 STAGES = ("omega", "pack", "sketch_gemm", "orth", "cpqr", "trsm", "gather", "row_id", "u_solve", "error", "backward",
           "batched")
@@ -433,6 +438,17 @@ def cur_error(A: torch.Tensor, C: torch.Tensor, U: torch.Tensor, R: torch.Tensor
 # ---------------------------------------------------------------------------
 # Gradient of the column-ID reconstruction loss (skeleton frozen)
 # ---------------------------------------------------------------------------
+def backward_workspace_bytes(A: torch.Tensor, k: int, l: int = 0, sketched: bool = False) -> int:
+    """Workspace bytes of :func:`id_col_backward` for A's shape and dtype, rank k
+    and (when sketched) l sketch rows."""
+    h = _prep(A, None)
+    m, n = A.shape
+    nb = ctypes.c_size_t(0)
+    _check(h, _lib.idcur_id_col_backward_workspace_bytes(h, _dtype_code(A), m, n, int(k), int(l) if sketched else 0,
+                                                         1 if sketched else 0, ctypes.byref(nb)))
+    return int(nb.value)
+
+
 def id_col_backward(A: torch.Tensor, J: torch.Tensor, T: torch.Tensor, k: int, *, omega: Optional[torch.Tensor] = None,
                     scale: float = 1.0, out: Optional[torch.Tensor] = None, workspace=None) -> torch.Tensor:
     """scale * dL/dA for L = |A(:,J2) - A(:,J1) T|_F^2 with J and Omega fixed and T
@@ -550,6 +566,7 @@ class BatchedID:
         _check(self.h, _lib.idcur_id_col_batched_workspace_bytes(self.h, F32, self.nblk, self.mmax, self.nmax,
                                                                  ctypes.byref(self.opts), ctypes.byref(nbytes)))
         self.ws = torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device=dev)
+        self._dbuf = None
 
     def _args(self):
         return (self.h, F32, self.nblk, self.mmax, self.nmax, self.m.data_ptr(), self.n.data_ptr(),
@@ -568,6 +585,45 @@ class BatchedID:
         v = _i32(-1)
         _check(self.h, _lib.idcur_id_col_batched_autotune(*self._args(), ctypes.byref(v)))
         return int(v.value)
+
+    def backward(self, scale: float = 1.0) -> None:
+        """Enqueue the gradient of every block's reconstruction loss
+        |A_b(:,J2) - A_b(:,J1) T_b|_F^2 with the skeleton of the last :meth:`run`
+        frozen (idcur_id_col_batched_backward; fixed-rank plans only), times
+        ``scale``, into the plan's gradient buffers (see :meth:`grads`). Only
+        enqueues kernels on the current stream, so it can be captured in a graph."""
+        if self.kcap <= 0 or self.opts.k <= 0:
+            raise IDCurError(EINVAL, "the batched backward differentiates fixed-rank plans (k > 0)")
+        if self._dbuf is None:
+            dev, i64 = self.device, torch.int64
+            offd, o = [], 0
+            for mb, nb in zip(self.ms, self.ns):
+                offd.append(o)
+                o += mb * nb
+            self._offd = offd
+            self._dbuf = torch.empty(max(o, 1), dtype=torch.float32, device=dev)
+            self._dp = torch.tensor([self._dbuf.data_ptr() + 4 * x for x in offd], dtype=i64, device=dev)
+            self._ldd = torch.tensor(self.ns, dtype=i64, device=dev)
+            nbytes = ctypes.c_size_t(0)
+            _check(self.h, _lib.idcur_id_col_batched_backward_workspace_bytes(
+                self.h, F32, self.nblk, self.mmax, self.nmax, ctypes.byref(self.opts), ctypes.byref(nbytes)))
+            self._wsb = torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device=dev)
+        _lib.idcur_set_stream(self.h, _vp(torch.cuda.current_stream(self.device).cuda_stream))
+        _check(self.h, _lib.idcur_id_col_batched_backward(
+            self.h, F32, self.nblk, self.mmax, self.nmax, self.m.data_ptr(), self.n.data_ptr(), self.A.data_ptr(),
+            self.lda.data_ptr(), ctypes.byref(self.opts), self.kout.data_ptr(), self.Jp.data_ptr(), self.Tp.data_ptr(),
+            self.ldt.data_ptr(), float(scale), self._dp.data_ptr(), self._ldd.data_ptr(), self._wsb.data_ptr(),
+            self._wsb.numel()))
+
+    def grads(self) -> list:
+        """Synchronise and return the gradients of the last :meth:`backward`, one
+        m_b x n_b view per block (copy them before the next call)."""
+        if self._dbuf is None:
+            raise IDCurError(EINVAL, "backward() has not been called")
+        st = _lib.idcur_sync_status(self.h)
+        if st != OK:
+            raise IDCurError(st, _lib.idcur_last_error(self.h).decode())
+        return [self._dbuf[o: o + mb * nb].view(mb, nb) for o, mb, nb in zip(self._offd, self.ms, self.ns)]
 
     def results(self) -> list:
         """Synchronise and return one BlockID per block (views into the plan's

@@ -972,6 +972,84 @@ idcur_status run_batched(idcur_ctx* ctx, int dtype, const BatchedCall& c, const 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Batched gradient of the fixed-rank column IDs' reconstruction losses (one
+// persistent launch, batched_bwd.hip)
+// ---------------------------------------------------------------------------
+struct BatchedBwdCall {
+  int nblk, mmax, nmax;
+  const int32_t* m; const int32_t* n; const void* const* A; const int64_t* lda;
+  const int32_t* k; const int32_t* const* J; const void* const* T; const int64_t* ldt;
+  double scale;
+  void* const* dA; const int64_t* ldd;
+};
+
+void batched_bwd_run(const Ctx& x, const BatchedBwdCall& c, const idcur_opts& o) {
+  const int l = o.k + o.p;
+  const int ldom = batched_ldom(l);
+  const int64_t mrows = round_up(std::max(c.mmax, 1), 16);
+  const int grid = batched_bwd_grid(c.nblk, x.c->num_cus);
+  float* omt = static_cast<float*>(x.ar->take((size_t)mrows * ldom * sizeof(float)));
+  float* slot = static_cast<float*>(x.ar->take((size_t)grid * batched_bwd_slot_floats(o.k, l, c.nmax) * sizeof(float)));
+  int* queue = static_cast<int*>(x.ar->take(256));
+  if (x.dry || c.nblk == 0) return;
+  Stage st(x, "backward");
+  x.check(zero_launch(omt, (size_t)mrows * ldom * sizeof(float), x.s), "zero Omega");
+  if (o.omega)
+    x.check(copy2d_launch(IDCUR_F32, l, c.mmax, o.omega, c.mmax, 1, omt, 1, ldom, x.s), "Omega copy");
+  else
+    x.check(gaussian_launch(IDCUR_F32, l, c.mmax, o.seed, 0, omt, 1, ldom, x.s), "Omega");
+  BatchedBwdArgs a{};
+  a.nblk = c.nblk;
+  a.m = c.m; a.n = c.n; a.k = c.k;
+  a.A = reinterpret_cast<const float* const*>(c.A); a.lda = c.lda;
+  a.J = c.J; a.T = reinterpret_cast<const float* const*>(c.T); a.ldt = c.ldt;
+  a.dA = reinterpret_cast<float* const*>(c.dA); a.ldd = c.ldd;
+  a.omt = omt; a.ldom = ldom;
+  a.mmax = c.mmax; a.nmax = c.nmax; a.l = l; a.kcap = o.k;
+  a.scale = c.scale;
+  a.slot = slot; a.queue = queue; a.status = x.c->dstatus;
+  x.check(batched_bwd_launch(a, grid, x.s), "batched backward launch");
+}
+
+idcur_status run_batched_bwd(idcur_ctx* ctx, int dtype, const BatchedBwdCall& c, const idcur_opts* o, void* ws,
+                             size_t ws_bytes, size_t* bytes_only) {
+  try {
+    if (!ctx) return IDCUR_EINVAL;
+    if (!o) fail(ctx, IDCUR_EINVAL, "opts is NULL");
+    if (dtype != IDCUR_F32) fail(ctx, IDCUR_EDTYPE, "the batched backward takes FP32 blocks");
+    if (o->prec != IDCUR_PREC_NATIVE) fail(ctx, IDCUR_EDTYPE, "the batched backward sketches in FP32");
+    if (c.nblk < 0 || c.nblk > (1 << 20)) fail(ctx, IDCUR_EINVAL, "nblk must be in [0, 2^20]");
+    if (c.mmax < 1 || c.mmax > (1 << 24)) fail(ctx, IDCUR_EINVAL, "mmax must be in [1, 2^24]");
+    if (c.nmax < 1 || c.nmax > batched_bwd_max_width()) fail(ctx, IDCUR_EINVAL, "nmax must be in [1, 512]");
+    if (o->k < 1) fail(ctx, IDCUR_EINVAL, "the batched backward differentiates fixed-rank IDs (k >= 1)");
+    if (o->p < 1) fail(ctx, IDCUR_EINVAL, "the batched backward needs oversampling p >= 1");
+    if (o->q != 0) fail(ctx, IDCUR_EINVAL, "the batched backward takes no power steps (q = 0)");
+    if ((int64_t)o->k + o->p > batched_bwd_max_sketch()) fail(ctx, IDCUR_EINVAL, "k + p must be <= 64");
+    if (!std::isfinite(c.scale)) fail(ctx, IDCUR_EINVAL, "scale must be finite");
+    Arena dry;
+    Ctx xd{ctx, ctx->stream, true, &dry};
+    batched_bwd_run(xd, c, *o);
+    if (bytes_only) {
+      *bytes_only = dry.off + 256;
+      return IDCUR_OK;
+    }
+    if (c.nblk > 0 && (!c.m || !c.n || !c.A || !c.lda || !c.k || !c.J || !c.T || !c.ldt || !c.dA || !c.ldd))
+      fail(ctx, IDCUR_EINVAL, "null array");
+    if (!ws || ws_bytes < dry.off) fail(ctx, IDCUR_EWORKSPACE, "workspace missing or too small");
+    hipcheck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    Arena ar;
+    ar.dry = false;
+    ar.base = static_cast<char*>(ws);
+    ar.cap = ws_bytes;
+    Ctx x{ctx, ctx->stream, false, &ar};
+    batched_bwd_run(x, c, *o);
+    return IDCUR_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  }
+}
+
 idcur_status run(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const void* A, int64_t lda,
                  const idcur_opts* opts, void* ws, size_t ws_bytes, const Outs& out) {
   try {
@@ -1243,6 +1321,28 @@ idcur_status idcur_id_col_batched_autotune(idcur_ctx* ctx, int32_t dtype, int32_
                                              opts, ws, ws_bytes, nullptr, 1, &v);
   if (variant) *variant = v;
   return st;
+}
+
+idcur_status idcur_id_col_batched_backward_workspace_bytes(idcur_ctx* ctx, int32_t dtype, int32_t nblk,
+                                                           int32_t mmax, int32_t nmax, const idcur_opts* opts,
+                                                           size_t* bytes) {
+  if (!bytes) return IDCUR_EINVAL;
+  idcur::BatchedBwdCall c{};
+  c.nblk = nblk; c.mmax = mmax; c.nmax = nmax; c.scale = 1.0;
+  return idcur::run_batched_bwd(ctx, dtype, c, opts, nullptr, 0, bytes);
+}
+
+idcur_status idcur_id_col_batched_backward(idcur_ctx* ctx, int32_t dtype, int32_t nblk, int32_t mmax, int32_t nmax,
+                                           const int32_t* m, const int32_t* n, const void* const* A,
+                                           const int64_t* lda, const idcur_opts* opts, const int32_t* k,
+                                           const int32_t* const* J, const void* const* T, const int64_t* ldt,
+                                           double scale, void* const* dA, const int64_t* ldd, void* ws,
+                                           size_t ws_bytes) {
+  idcur::BatchedBwdCall c{};
+  c.nblk = nblk; c.mmax = mmax; c.nmax = nmax;
+  c.m = m; c.n = n; c.A = A; c.lda = lda; c.k = k; c.J = J; c.T = T; c.ldt = ldt;
+  c.scale = scale; c.dA = dA; c.ldd = ldd;
+  return idcur::run_batched_bwd(ctx, dtype, c, opts, ws, ws_bytes, nullptr);
 }
 
 idcur_status idcur_id_col_batched_set_variant(idcur_ctx* ctx, int32_t variant) {

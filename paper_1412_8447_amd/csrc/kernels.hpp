@@ -164,6 +164,29 @@ size_t batched_lds_bytes(int lcap, int nmax);
 int batched_num_variants();
 hipError_t batched_launch(const BatchedArgs& a, int variant, int num_cus, hipStream_t stream);
 
+// Batched gradient of the column-ID reconstruction loss (batched_bwd.hip): one
+// persistent launch, one workgroup per block, each workgroup with a slot of
+// batched_bwd_slot_floats floats of scratch (slot = grid slots).
+struct BatchedBwdArgs {
+  int nblk;
+  const int* m; const int* n; const int* k;
+  const float* const* A; const int64_t* lda;
+  const int* const* J; const float* const* T; const int64_t* ldt;
+  float* const* dA; const int64_t* ldd;
+  const float* omt; int ldom;   // Omega^T: round_up(mmax, 16) x ldom, zero past column l
+  int mmax, nmax, l, kcap;
+  double scale;
+  float* slot;                  // grid * batched_bwd_slot_floats(kcap, l, nmax) floats
+  int* queue;                   // one int of scratch (zeroed by the launch)
+  int* status;
+};
+size_t batched_bwd_lds_bytes();
+int batched_bwd_max_width();
+int batched_bwd_max_sketch();
+int64_t batched_bwd_slot_floats(int kcap, int l, int nmax);
+int batched_bwd_grid(int nblk, int num_cus);
+hipError_t batched_bwd_launch(const BatchedBwdArgs& a, int grid, hipStream_t stream);
+
 // ---------------------------------------------------------------------------
 // Cholesky factor and triangular inverse (chol.hip), FP64, c <= 256, one workgroup
 // (larger c: the blocked driver in host.cpp).

@@ -53,3 +53,21 @@ def batched_flops(ms, ns, ks, l: int) -> float:
         k = max(int(k), 0)
         tot += 2.0 * l * m * n + cpqr_flops(l, n, k) + float(k) * k * (n - k)
     return tot
+
+
+def adjoint_flops(m: int, n: int, k: int, l: int = 0) -> float:
+    """Gradient of the column-ID reconstruction loss (skeleton frozen), sketched
+    with l rows (l = 0: Y = A): E = A(:,J2) - C T, Tbar = -2 C^T E and -2 E T^T
+    (2 m (n-k) k each), Y = Omega A(:,J) and Omega^T Ybar (2 l m n each), the Gram
+    matrix (2 k^2 l, or 2 k^2 m), its Cholesky factor (k^3 / 3), M (2 k^2 (n-k)),
+    T M^T (2 k^2 (n-k)), Y2 - Y1 T, Y1 M and (Y2 - Y1 T) M^T (2 l k (n-k) each),
+    Y1 (T M^T) (2 l k^2); without a sketch the last group works on m rows and
+    Y2 - Y1 T is E itself."""
+    n2 = n - k
+    rows = l if l > 0 else m
+    f = 3 * 2.0 * m * n2 * k
+    if l > 0:
+        f += 2 * 2.0 * l * m * n
+    f += 2.0 * k * k * rows + k ** 3 / 3.0 + 2 * 2.0 * k * k * n2
+    f += (3 if l > 0 else 2) * 2.0 * rows * k * n2 + 2.0 * rows * k * k
+    return f

@@ -27,6 +27,8 @@ __all__ = [
     "haar_orthonormal",
     "lowrank",
     "lowrank_torch",
+    "noisy_lowrank_torch",
+    "noisy_lowrank_blocks_torch",
     "gaussian",
     "sigma_exp",
     "sigma_pow",
@@ -109,6 +111,41 @@ def lowrank_torch(m: int, n: int, sigma: np.ndarray, seed: int, device, rank: in
     u = _haar(m, r)
     v = _haar(n, r)
     return (u * sig) @ v.T
+
+
+def noisy_lowrank_torch(m: int, n: int, sigma: np.ndarray, noise: float, seed: int, device):
+    """:func:`lowrank_torch` plus i.i.d. N(0, noise^2) entries (the differentiable-ID
+    workload: a decaying spectrum under a noise floor). Returns float64."""
+    import torch
+
+    a = lowrank_torch(m, n, sigma, seed, device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed) + 104729)
+    return a + noise * torch.randn(m, n, generator=gen, device=device, dtype=torch.float64)
+
+
+def noisy_lowrank_blocks_torch(nblk: int, m: int, n: int, power: float, noise: float, seed: int, device):
+    """nblk blocks A_b = U_b diag((j+1)^-power) V_b^T + N(0, noise^2) (m x n each,
+    Haar U_b, V_b from batched QRs of N(0,1) draws), as one float64 tensor of
+    shape (nblk, m, n)."""
+    import torch
+
+    r = min(m, n)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    sig = torch.as_tensor(sigma_pow(r, power), device=device)
+
+    def _haar(rows):
+        g = torch.randn(nblk, rows, r, generator=gen, device=device, dtype=torch.float64)
+        q, rr = torch.linalg.qr(g, mode="reduced")
+        s = torch.sign(torch.diagonal(rr, dim1=1, dim2=2))
+        s[s == 0] = 1.0
+        return q * s[:, None, :]
+
+    u = _haar(m)
+    v = _haar(n)
+    a = (u * sig) @ v.transpose(1, 2)
+    return a + noise * torch.randn(nblk, m, n, generator=gen, device=device, dtype=torch.float64)
 
 
 def gaussian(rows: int, cols: int, seed: int, dtype=np.float64) -> np.ndarray:

@@ -114,3 +114,23 @@ def test_out_of_range_index_is_reported():
     with pytest.raises(P.IDCurError):
         P.id_col_backward(dA, Jbad, r.T, k)
         P.sync_status(dA.device)
+
+
+def test_full_size_differentiable_id_workload():
+    # the differentiable-ID workload at its full size: FP32 8192 x 4096, spectrum
+    # (j+1)^-1.5 under N(0, 1e-3^2) noise, k = 128, p = 10, q = 0
+    cfg = synth.CONFIGS["diff_fp32_8192x4096_k128"]
+    m, n, k, p = cfg.m, cfg.n, cfg.k, cfg.p
+    say(f"adjoint full size {m}x{n} k={k} p={p}")
+    dev = torch.device("cuda")
+    A = synth.noisy_lowrank_torch(m, n, cfg.spectrum(), 1e-3, seed=2024, device=dev).to(torch.float32).contiguous()
+    om = P.gaussian(k + p, m, seed=11, dtype=torch.float32)
+    r = P.id_col(A, k, p=p, q=0, omega=om)
+    assert r.k == k
+    J = r.J.cpu().numpy().astype(np.int64)
+    check_perm(J, n)
+    g = P.id_col_backward(A, r.J, r.T, k, omega=om).cpu().numpy().astype(np.float64)
+    want = adjoint.recon_grad(A.double().cpu().numpy(), J, k, om.double().cpu().numpy())
+    e = _relnorm(g, want)
+    say(f"  |dA - oracle| / |oracle| = {e:.3e}")
+    assert e <= 2e-4

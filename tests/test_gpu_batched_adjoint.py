@@ -1,0 +1,147 @@
+"""GPU parity of the batched reconstruction-loss gradient (one persistent launch
+over many blocks, idcur_id_col_batched_backward) against the FP64 oracle
+gradient (oracle/adjoint.py), block by block.
+
+The skeleton J_b and the rank k_b come from the GPU's fixed-rank batched ID,
+Omega is the matrix that call draws (idcur_gaussian with the same seed), and
+both are handed to the oracle, so both sides differentiate the same function.
+Tolerance: normwise 2e-4 per block, as for the single-matrix FP32 adjoint (FP32
+storage of A and T, FP32 matrix-core sums over at most m, n or k + p terms,
+FP64 for Y1^T Y1 and its inverse).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import adjoint
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1412_8447_amd as P  # noqa: E402
+from gpu_helpers import say, to_dev, check_perm  # noqa: E402
+
+TOL = 2e-4
+
+
+def _relnorm(x, y):
+    return float(np.linalg.norm(x - y) / np.linalg.norm(y))
+
+
+def _block(m, n, seed, noise=1e-3, rank=None):
+    A = synth.lowrank(m, n, synth.sigma_pow(min(m, n), 1.5), seed=seed, rank=rank)
+    if noise:
+        A = A + noise * synth.rng(seed + 7).standard_normal((m, n))
+    return A
+
+
+def _check_blocks(plan, blocks64, grads, k, p, seed, which, scale=1.0):
+    l = k + p
+    om = P.gaussian(l, plan.mmax, seed=seed, dtype=torch.float32).double().cpu().numpy()
+    res = plan.results()
+    worst = 0.0
+    for b in which:
+        A = blocks64[b]
+        r = res[b]
+        J = r.J.cpu().numpy().astype(np.int64)
+        check_perm(J, A.shape[1])
+        want = scale * adjoint.recon_grad(A, J, r.k, om[:, : A.shape[0]])
+        got = grads[b].cpu().numpy().astype(np.float64)
+        e = _relnorm(got, want)
+        worst = max(worst, e)
+        assert e <= TOL, f"block {b} ({A.shape[0]}x{A.shape[1]}, k={r.k}): {e:.3e}"
+    return worst
+
+
+def test_ragged_blocks_match_oracle():
+    # widths 13 (one partial tile), 100, 300 and 512 (four column groups), heights
+    # from 40 to 700 (ragged last stripe), one block wider than tall
+    k, p, seed = 12, 8, 4242
+    shapes = [(40, 13), (57, 100), (300, 300), (64, 512), (700, 96), (129, 250), (33, 200), (256, 256)]
+    say(f"batched adjoint ragged: {shapes} k={k} p={p}")
+    A64 = [_block(m, n, seed=10 + i) for i, (m, n) in enumerate(shapes)]
+    blocks = [to_dev(a, torch.float32) for a in A64]
+    A64 = [b.double().cpu().numpy() for b in blocks]   # what the device holds
+    plan = P.BatchedID(blocks, k=k, p=p, seed=seed)
+    plan.run()
+    assert plan.kout.cpu().tolist() == [min(k, n) for (_, n) in shapes]
+    plan.backward(scale=0.5)
+    g = [x.clone() for x in plan.grads()]
+    worst = _check_blocks(plan, A64, g, k, p, seed, range(len(shapes)), scale=0.5)
+    say(f"  worst |dA - oracle| / |oracle| = {worst:.3e}")
+
+
+def test_rank_deficient_block_and_small_rank():
+    # block 0 has exact rank 5 < k: the forward stops at k_b = 5 and the loss is
+    # at rounding level, so its gradient must be tiny; block 1 is generic
+    k, p, seed = 10, 6, 77
+    A0 = _block(120, 90, seed=3, noise=0.0, rank=5)
+    A1 = _block(150, 110, seed=4)
+    blocks = [to_dev(A0, torch.float32), to_dev(A1, torch.float32)]
+    plan = P.BatchedID(blocks, k=k, p=p, seed=seed)
+    plan.run()
+    ks = plan.kout.cpu().tolist()
+    say(f"batched adjoint rank-deficient: k_out = {ks}")
+    assert ks[0] == 5 and ks[1] == k
+    plan.backward()
+    g = [x.clone().cpu().numpy() for x in plan.grads()]
+    assert np.linalg.norm(g[0]) <= 1e-3 * np.linalg.norm(A0)
+    A64 = [b.double().cpu().numpy() for b in blocks]
+    _check_blocks(plan, A64, [torch.as_tensor(x) for x in g], k, p, seed, [1])
+
+
+def test_256_blocks_of_256_sampled_deterministic_and_graph():
+    # the batched differentiable-ID workload: 256 blocks of 256 x 256, decaying
+    # spectrum (j+1)^-1.5 under N(0, 1e-3^2) noise, k = 32, p = 10
+    nblk, m, n, k, p, seed = 256, 256, 256, 32, 10, 9
+    say(f"batched adjoint {nblk} blocks {m}x{n} k={k} p={p}")
+    dev = torch.device("cuda")
+    Ab = synth.noisy_lowrank_blocks_torch(nblk, m, n, 1.5, 1e-3, seed=seed, device=dev).to(torch.float32)
+    blocks = [Ab[i] for i in range(nblk)]
+    plan = P.BatchedID(blocks, k=k, p=p, seed=seed + 1)
+    plan.run()
+    plan.backward()
+    g1 = [x.clone() for x in plan.grads()]
+    # the same call again: bitwise identical (fixed reduction order)
+    plan.backward()
+    g2 = plan.grads()
+    assert all(torch.equal(a, b) for a, b in zip(g1, g2))
+    # captured in a graph with the forward, replayed with eager work in between
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.run()
+        plan.backward()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.run()
+        plan.backward()
+    for rep in range(3):
+        plan._dbuf.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        g3 = plan.grads()
+        assert all(torch.equal(a, b) for a, b in zip(g1, g3)), f"graph replay {rep}"
+    sample = list(range(0, nblk, nblk // 12))
+    A64 = Ab.double().cpu().numpy()
+    worst = _check_blocks(plan, [A64[i] for i in range(nblk)], g1, k, p, seed + 1, sample)
+    say(f"  sampled {len(sample)} blocks: worst rel. error {worst:.3e}")
+
+
+def test_repeated_column_is_reported():
+    # a J that repeats a column is clamped on the device and reported
+    k, p = 6, 4
+    blocks = [to_dev(_block(80, 60, seed=5), torch.float32)]
+    plan = P.BatchedID(blocks, k=k, p=p, seed=1)
+    plan.run()
+    plan.results()
+    plan.Jbuf[3] = plan.Jbuf[4]
+    plan.backward()
+    with pytest.raises(P.IDCurError):
+        plan.grads()
