@@ -180,7 +180,6 @@ struct BatchedBwdArgs {
   int* queue;                   // one int of scratch (zeroed by the launch)
   int* status;
 };
-size_t batched_bwd_lds_bytes();
 int batched_bwd_max_width();
 int batched_bwd_max_sketch();
 int64_t batched_bwd_slot_floats(int kcap, int l, int nmax);

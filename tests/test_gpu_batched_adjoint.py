@@ -56,11 +56,16 @@ def _check_blocks(plan, blocks64, grads, k, p, seed, which, scale=1.0):
     return worst
 
 
-def test_ragged_blocks_match_oracle():
+@pytest.mark.parametrize("k,p", [(12, 8), (40, 8), (50, 10)])
+def test_ragged_blocks_match_oracle(k, p):
     # widths 13 (one partial tile), 100, 300 and 512 (four column groups), heights
-    # from 40 to 700 (ragged last stripe), one block wider than tall
-    k, p, seed = 12, 8, 4242
-    shapes = [(40, 13), (57, 100), (300, 300), (64, 512), (700, 96), (129, 250), (33, 200), (256, 256)]
+    # from 40 to 700 (ragged last stripe), one block wider than tall; ranks whose
+    # padded sizes (16, 48, 64) select every form of the factorisation step
+    seed = 4242
+    if k < 20:
+        shapes = [(40, 13), (57, 100), (300, 300), (64, 512), (700, 96), (129, 250), (33, 200), (256, 256)]
+    else:
+        shapes = [(90, 70), (300, 300), (128, 512), (700, 96), (129, 250), (256, 256)]
     say(f"batched adjoint ragged: {shapes} k={k} p={p}")
     A64 = [_block(m, n, seed=10 + i) for i, (m, n) in enumerate(shapes)]
     blocks = [to_dev(a, torch.float32) for a in A64]
