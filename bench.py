@@ -588,6 +588,24 @@ def main():
                                   "leading_pivots_identical": int(np.array_equal(Jg[:lead], ref.ts.col.J[:lead])),
                                   "clear_pivots": lead}
         log(f"oracle {tcpu:.1f}s e={e_orc:.4e}")
+        # the same oracle run on one host thread, and the host CPU model
+        try:
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1):
+                tc1 = time.time()
+                oracle.cur(A_h, k, omega=om, q=q)
+                t1 = time.time() - tc1
+            result["cpu_baseline"]["single_core"] = {"value": round(flops["total"] / t1 / 1e9, 3), "unit": "GFLOP/s",
+                                                     "cores": 1, "seconds": round(t1, 2)}
+            log(f"oracle on one thread {t1:.1f}s")
+        except Exception as ex:  # pragma: no cover
+            log(f"single-thread oracle timing skipped: {ex}")
+        try:
+            with open("/proc/cpuinfo") as f:
+                models = [ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")]
+            result["cpu_baseline"]["cpu_model"] = models[0] if models else None
+        except OSError:  # pragma: no cover
+            result["cpu_baseline"]["cpu_model"] = None
         for prec, r in result.get("mixed_precision", {}).items():
             r["error_ratio_vs_fp64_oracle"] = round(r["rel_fro_error"] / e_orc, 4)
 
