@@ -18,6 +18,8 @@ Layout of the oracle:
 * ``errors``   -- the reported error measures (Frobenius; spectral at small sizes).
 * ``philox``   -- Philox4x32-10 (Salmon et al., SC'11) and a Box-Muller transform,
                   the counter-based generator used for the sketch matrix.
+* ``srht``     -- the subsampled randomized Hadamard sketch (the real counterpart
+                  of the structured sketch of Section 5.2).
 
 Every function here is pinned by a ``-m "not gpu"`` test against something other
 than itself (brute force, closed forms, library routines, identities from the

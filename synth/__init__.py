@@ -29,6 +29,7 @@ __all__ = [
     "lowrank_torch",
     "noisy_lowrank_torch",
     "noisy_lowrank_blocks_torch",
+    "srht_draws",
     "gaussian",
     "sigma_exp",
     "sigma_pow",
@@ -146,6 +147,21 @@ def noisy_lowrank_blocks_torch(nblk: int, m: int, n: int, power: float, noise: f
     v = _haar(n)
     a = (u * sig) @ v.transpose(1, 2)
     return a + noise * torch.randn(nblk, m, n, generator=gen, device=device, dtype=torch.float64)
+
+
+def srht_draws(m: int, l: int, seed: int):
+    """The random inputs of a subsampled randomized Hadamard sketch of an m-row
+    matrix: ``rows`` (int32[l], distinct, uniform in [0, m') with m' the smallest
+    power of two >= m) and ``signs`` (int8[m], +1 or -1 with equal probability)."""
+    mp = 1
+    while mp < m:
+        mp *= 2
+    if l > mp:
+        raise ValueError("l exceeds the padded order")
+    g = rng(seed)
+    rows = g.choice(mp, size=l, replace=False).astype(np.int32)
+    signs = (2 * g.integers(0, 2, size=m) - 1).astype(np.int8)
+    return rows, signs
 
 
 def gaussian(rows: int, cols: int, seed: int, dtype=np.float64) -> np.ndarray:
