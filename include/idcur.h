@@ -77,6 +77,21 @@ typedef enum {
   IDCUR_OP_SKETCH_ROW = 5   /* idcur_sketch of A^T (the sketch an ID_ROW call takes) */
 } idcur_op;
 
+/* Kind of sketch matrix (Section 5): i.i.d. Gaussian (Section 5.1), or the
+ * subsampled randomized Hadamard transform, the real counterpart of the
+ * structured sketch of Section 5.2 (eq. (def_srft)): the unitary DFT replaced by
+ * the orthonormal Walsh-Hadamard matrix of order m' (the smallest power of two
+ * >= the sketched dimension M, the matrix extended by zero rows), the random
+ * unit-modulus diagonal by random signs, so that
+ *   Omega(r, i) = l^(-1/2) (-1)^popcount(rows[r] & i) sign_i,  r < l, i < M.
+ * The structured sketch needs q = 0, NATIVE precision, no omega, l <= 256, and
+ * its random inputs from the caller: srht_rows (device int32[l], distinct values
+ * in [0, m'); values out of range are reported as IDCUR_EINVAL by
+ * idcur_sync_status) and srht_signs (device int8[M]: -1 where negative, else
+ * +1). M is m for the column ID, two-sided ID, CUR and IDCUR_OP_SKETCH, and n for
+ * the row ID and IDCUR_OP_SKETCH_ROW. */
+typedef enum { IDCUR_SKETCH_GAUSSIAN = 0, IDCUR_SKETCH_SRHT = 1 } idcur_sketch_kind;
+
 typedef struct {
   int32_t k;          /* > 0: fixed rank, k < min(m, n), k <= 4096. 0: tolerance mode. */
   int32_t kmax;       /* rank cap in tolerance mode (ignored when k > 0), <= 4096; the
@@ -94,10 +109,14 @@ typedef struct {
                          leading dimension m, same dtype as A; NULL: generated.        */
   int32_t prec;       /* idcur_prec of the sketch GEMMs.                                 */
   int32_t norms;      /* idcur_norms.                                                    */
+  int32_t sketch;     /* idcur_sketch_kind (default Gaussian).                           */
+  const int8_t* srht_signs;   /* structured sketch: device int8[M] signs (see above).     */
+  const int32_t* srht_rows;   /* structured sketch: device int32[l] sampled rows.         */
 } idcur_opts;
 
 /* Fill *opts with defaults: k = 0, kmax = 0, tol = 0, rank_tol = 0, p = -1
- * (deterministic), q = 0, seed = 0, omega = NULL, NATIVE precision, downdated norms. */
+ * (deterministic), q = 0, seed = 0, omega = NULL, NATIVE precision, downdated norms,
+ * Gaussian sketch (srht_signs = srht_rows = NULL). */
 void idcur_opts_default(idcur_opts* opts /* host */);
 
 /* Create a context bound to `stream` (a hipStream_t, borrowed, may be NULL for the
@@ -119,7 +138,8 @@ idcur_status idcur_sync_status(idcur_ctx* ctx);
  * this context records a pair of HIP events on the context's stream around each
  * stage: "omega", "pack", "sketch_gemm" (the sketch / power-step GEMM kernels
  * alone, without their split-K reduction), "orth", "cpqr", "trsm", "gather",
- * "row_id", "u_solve", "error", "backward", "batched". Enabling (or disabling)
+ * "row_id", "u_solve", "error", "backward", "batched", "srht" (the structured
+ * sketch kernels). Enabling (or disabling)
  * synchronises the stream and clears the accumulated marks. idcur_timing_read
  * synchronises and returns the summed elapsed milliseconds and the number of
  * marks of one stage (host outputs). */

@@ -52,6 +52,7 @@ F64, F32 = 0, 1
 PREC_NATIVE, PREC_BF16, PREC_FP16 = 0, 1, 2
 NORMS_DOWNDATE, NORMS_EXACT = 0, 1
 OP_ID_COL, OP_ID_ROW, OP_TWO_SIDED, OP_CUR, OP_SKETCH, OP_SKETCH_ROW = 0, 1, 2, 3, 4, 5
+SKETCH_GAUSSIAN, SKETCH_SRHT = 0, 1
 
 STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", EDTYPE: "EDTYPE", EWORKSPACE: "EWORKSPACE", EHIP: "EHIP",
                 ERANKCAP: "ERANKCAP", ENONFINITE: "ENONFINITE", ETIMEOUT: "ETIMEOUT"}
@@ -69,6 +70,9 @@ class Opts(ctypes.Structure):
         ("omega", ctypes.c_void_p),
         ("prec", ctypes.c_int32),
         ("norms", ctypes.c_int32),
+        ("sketch", ctypes.c_int32),
+        ("srht_signs", ctypes.c_void_p),
+        ("srht_rows", ctypes.c_void_p),
     ]
 
 
@@ -124,7 +128,7 @@ EXPORTED = ("idcur_opts_default", "idcur_create", "idcur_set_stream", "idcur_des
             "idcur_id_col_batched_backward_workspace_bytes", "idcur_id_col_batched_backward")
 
 STAGES = ("omega", "pack", "sketch_gemm", "orth", "cpqr", "trsm", "gather", "row_id", "u_solve", "error", "backward",
-          "batched")
+          "batched", "srht")
 
 
 class IDCurError(RuntimeError):
@@ -179,7 +183,11 @@ def _dtype_code(t: torch.Tensor) -> int:
 
 def make_opts(k: int = 0, *, tol: float = 0.0, kmax: int = 0, p: int = -1, q: int = 0, seed: int = 0,
               omega: Optional[torch.Tensor] = None, rank_tol: float = 0.0, norms: str = "downdate",
-              prec: str = "native") -> Opts:
+              prec: str = "native", srht: Optional[tuple] = None) -> Opts:
+    """Options of a decomposition call. ``srht = (rows, signs)`` selects the
+    subsampled randomized Hadamard sketch with the given device tensors (rows:
+    int32[l], distinct, below the padded order; signs: int8, one per sketched
+    row), instead of the Gaussian one."""
     o = Opts()
     _lib.idcur_opts_default(ctypes.byref(o))
     o.k, o.kmax, o.tol, o.rank_tol = int(k), int(kmax), float(tol), float(rank_tol)
@@ -187,6 +195,13 @@ def make_opts(k: int = 0, *, tol: float = 0.0, kmax: int = 0, p: int = -1, q: in
     o.omega = omega.data_ptr() if omega is not None else None
     o.norms = {"downdate": NORMS_DOWNDATE, "exact": NORMS_EXACT}[norms]
     o.prec = {"native": PREC_NATIVE, "bf16": PREC_BF16, "fp16": PREC_FP16}[prec]
+    if srht is not None:
+        rows, signs = srht
+        for t, name, dt in ((rows, "srht rows", torch.int32), (signs, "srht signs", torch.int8)):
+            if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+                raise IDCurError(EINVAL, f"{name} must be a contiguous device tensor of {dt}")
+        o.sketch = SKETCH_SRHT
+        o.srht_rows, o.srht_signs = rows.data_ptr(), signs.data_ptr()
     return o
 
 

@@ -290,6 +290,25 @@ SketchOut sketch(const Ctx& x, int dtype, const View& X, const idcur_opts& o, in
   // multiple of 4 elements, so that every row starts 16-byte aligned and the
   // GEMMs read them with vector loads
   const int64_t ll = round_up(l, 4);
+  if (o.sketch == IDCUR_SKETCH_SRHT) {
+    // the subsampled randomized Hadamard sketch (Section 5.2's structured
+    // sketch, real form): one pass over X, no power steps
+    void* Yt = x.ar->take((size_t)nc * ll * esz(dtype));
+    SrhtDesc d{};
+    d.X = X.A; d.xr = X.xr; d.xc = X.xc; d.mr = mr; d.nc = nc;
+    d.signs = static_cast<const int8_t*>(o.srht_signs);
+    d.rows = o.srht_rows; d.l = l;
+    d.Yt = Yt; d.ldo = ll;
+    d.splits = srht_pick_splits(mr, nc, x.c->num_cus);
+    d.status = x.c->dstatus;
+    void* part = x.ar->take(srht_part_bytes(d, (int)esz(dtype)));
+    if (!x.dry) {
+      Stage st(x, "srht");
+      x.check(srht_launch(dtype, d, part, x.s), "structured sketch");
+    }
+    r.Y = Yt; r.rs = 1; r.cs = ll; r.l = l; r.sketched = true;
+    return r;
+  }
   const bool lowp = o.prec == IDCUR_PREC_BF16 || o.prec == IDCUR_PREC_FP16;
   const int fp16 = o.prec == IDCUR_PREC_FP16;
   void* Omt = (lowp && o.omega) ? nullptr : x.ar->take((size_t)mr * ll * esz(dtype));   // Omega^T, mr x l
@@ -572,6 +591,15 @@ void validate(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const voi
     fail(ctx, IDCUR_EINVAL, "a sketch needs p >= 0 and k + p below the sketched dimension");
   if (opts->rank_tol < 0 || !std::isfinite(opts->rank_tol)) fail(ctx, IDCUR_EINVAL, "rank_tol must be >= 0");
   if (opts->norms != IDCUR_NORMS_DOWNDATE && opts->norms != IDCUR_NORMS_EXACT) fail(ctx, IDCUR_EINVAL, "bad norms");
+  if (opts->sketch != IDCUR_SKETCH_GAUSSIAN && opts->sketch != IDCUR_SKETCH_SRHT)
+    fail(ctx, IDCUR_EINVAL, "unknown sketch kind");
+  if (opts->sketch == IDCUR_SKETCH_SRHT && opts->p >= 0 && (int64_t)kcap + opts->p < mr) {
+    if (opts->q != 0) fail(ctx, IDCUR_EINVAL, "the structured sketch takes no power steps (q = 0)");
+    if (opts->prec != IDCUR_PREC_NATIVE) fail(ctx, IDCUR_EDTYPE, "the structured sketch runs in the native precision");
+    if (opts->omega) fail(ctx, IDCUR_EINVAL, "omega and the structured sketch exclude each other");
+    if (!opts->srht_rows || !opts->srht_signs) fail(ctx, IDCUR_EINVAL, "srht_rows and srht_signs are required");
+    if ((int64_t)kcap + opts->p > kSrhtMaxRows) fail(ctx, IDCUR_EINVAL, "k (kmax) + p must be <= 256 for the structured sketch");
+  }
   (void)nc;
 }
 

@@ -164,6 +164,24 @@ size_t batched_lds_bytes(int lcap, int nmax);
 int batched_num_variants();
 hipError_t batched_launch(const BatchedArgs& a, int variant, int num_cus, hipStream_t stream);
 
+// Subsampled randomized Hadamard sketch (srht.hip): Y^T (nc x l, ld ldo) of the
+// mr x nc view X, X(i, c) = X[i*xr + c*xc] with xr == 1 or xc == 1;
+// Y(r, c) = l^(-1/2) sum_i (-1)^popcount(rows[r] & i) s_i X(i, c), s_i = -1 where
+// signs[i] < 0, else +1. Out-of-range rows flag ST_BADINDEX (row 0 is used).
+constexpr int kSrhtMaxRows = 256;
+struct SrhtDesc {
+  const void* X; int64_t xr, xc;
+  int64_t mr, nc;
+  const int8_t* signs;
+  const int* rows; int l;
+  void* Yt; int64_t ldo;
+  int splits;
+  int* status;
+};
+int srht_pick_splits(int64_t mr, int64_t nc, int num_cus);
+size_t srht_part_bytes(const SrhtDesc& d, int esize);
+hipError_t srht_launch(int dtype, const SrhtDesc& d, void* part, hipStream_t stream);
+
 // Batched gradient of the column-ID reconstruction loss (batched_bwd.hip): one
 // persistent launch, one workgroup per block, each workgroup with a slot of
 // batched_bwd_slot_floats floats of scratch (slot = grid slots).

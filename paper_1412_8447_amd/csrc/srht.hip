@@ -1,0 +1,222 @@
+// Subsampled randomized Hadamard sketch: the real counterpart of the structured
+// sketch of Section 5.2, eq. (def_srft) (unitary DFT -> orthonormal
+// Walsh-Hadamard of order m', random unit-modulus diagonal -> random signs).
+// For the mr x nc view X it writes Y^T (nc x l) with
+//   Y(r, c) = l^(-1/2) sum_{i < mr} (-1)^popcount(s_r & i) d_i X(i, c),
+// s_r the sampled rows (distinct, < m' = the smallest power of two >= mr),
+// d_i = +-1. With i = 128 i1 + i2 and s = 128 s1 + s2 the sign factors into
+// (-1)^popcount(s1 & i1) (-1)^popcount(s2 & i2): each 128-row block of X is
+// transformed by the length-128 Walsh-Hadamard transform (seven butterfly
+// stages: four on a thread's 16 rows in registers, three more after one
+// exchange through LDS), and every sampled row takes entry s2 of the
+// transformed block with sign (-1)^popcount(s1 & i1). X is read once, with 7
+// additions and l / 128 multiply-adds per element, so the kernel is bound by
+// HBM. Row blocks are split over the grid; the split partial sums are added in
+// split order by a second kernel.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace idcur {
+namespace {
+
+constexpr int kSB = 128;                      // rows per block
+constexpr int kSC = 32;                       // columns per workgroup
+constexpr int kST = 256;                      // threads
+constexpr int kSG = kST / kSC;                // row groups (8)
+constexpr int kSJ = kSrhtMaxRows / kSG;       // sampled rows per thread
+
+template <typename T>
+struct SArgs {
+  const T* X; int64_t xr, xc;
+  int64_t mr, nc;
+  const int8_t* signs;
+  const int* rows; int l;
+  T* out; int64_t ldo;     // split s writes rows s*nc .. (s+1)*nc - 1 (ld ldo)
+  int64_t nblk, bps;       // row blocks, blocks per split
+  int64_t mp;              // padded order
+  double scale;            // l^(-1/2)
+  int* status;
+};
+
+template <typename T>
+__device__ __forceinline__ T signed_load(const T* X, int64_t off, bool ok, const int8_t* signs, int64_t i) {
+  const T v = X[ok ? off : 0];
+  const int8_t d = signs[ok ? i : 0];
+  return ok ? (d < 0 ? -v : v) : T(0);
+}
+
+// XC1: X(i, c) = X[i*xr + c] (rows along memory); else X(i, c) = X[i + c*xc].
+template <typename T, bool XC1>
+__global__ __launch_bounds__(kST) void srht_kernel(SArgs<T> a) {
+  __shared__ T buf[kSB][kSC + 1];
+  const int tid = threadIdx.x, c = tid % kSC, g = tid / kSC;
+  const int64_t c0 = (int64_t)blockIdx.x * kSC;
+  const int64_t b0 = (int64_t)blockIdx.y * a.bps;
+  const int64_t b1 = min(a.nblk, b0 + a.bps);
+
+  // sampled rows r = g + kSG j of this thread
+  int srow[kSJ];
+  T acc[kSJ];
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < kSJ; ++j) {
+    const int r = g + kSG * j;
+    int s = r < a.l ? a.rows[r] : 0;
+    if (s < 0 || s >= a.mp) {
+      bad = true;
+      s = 0;
+    }
+    srow[j] = s;
+    acc[j] = T(0);
+  }
+  if (bad) set_status(a.status, ST_BADINDEX);
+
+  // coalesced loads of one 128 x 32 block: XC1 -> thread (g, c) takes rows
+  // 16 g .. 16 g + 15 of column c; else thread t takes row t % 128 of columns
+  // t / 128 + 2 q
+  T ld[16];
+  auto load_block = [&](int64_t i1) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      if (XC1) {
+        const int64_t i = i1 * kSB + 16 * g + q, cc = c0 + c;
+        const bool ok = i < a.mr && cc < a.nc;
+        ld[q] = signed_load(a.X, i * a.xr + cc, ok, a.signs, i);
+      } else {
+        const int64_t i = i1 * kSB + tid % kSB, cc = c0 + tid / kSB + 2 * q;
+        const bool ok = i < a.mr && cc < a.nc;
+        ld[q] = signed_load(a.X, i + cc * a.xc, ok, a.signs, i);
+      }
+    }
+  };
+  auto store_block = [&]() {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      if (XC1) buf[16 * g + q][c] = ld[q];
+      else buf[tid % kSB][tid / kSB + 2 * q] = ld[q];
+    }
+  };
+
+  if (b0 < b1) load_block(b0);
+  for (int64_t i1 = b0; i1 < b1; ++i1) {
+    store_block();
+    __syncthreads();
+    if (i1 + 1 < b1) load_block(i1 + 1);   // in flight during this block
+    // stages 1, 2, 4, 8: a thread's 16 consecutive rows of column c
+    T v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = buf[16 * g + q][c];
+#pragma unroll
+    for (int h = 1; h < 16; h *= 2)
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if ((q & h) == 0) {
+          const T x0 = v[q], x1 = v[q + h];
+          v[q] = x0 + x1;
+          v[q + h] = x0 - x1;
+        }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) buf[16 * g + q][c] = v[q];
+    __syncthreads();
+    // stages 16, 32, 64: rows lo + 16 u (u < 8) for lo = 2 g and 2 g + 1
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+      const int lo = 2 * g + hh;
+      T u[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) u[q] = buf[lo + 16 * q][c];
+#pragma unroll
+      for (int h = 1; h < 8; h *= 2)
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if ((q & h) == 0) {
+            const T x0 = u[q], x1 = u[q + h];
+            u[q] = x0 + x1;
+            u[q + h] = x0 - x1;
+          }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) buf[lo + 16 * q][c] = u[q];
+    }
+    __syncthreads();
+    // each sampled row takes its entry of the transformed block
+    const unsigned i1u = (unsigned)i1;
+#pragma unroll
+    for (int j = 0; j < kSJ; ++j) {
+      if (g + kSG * j < a.l) {
+        const int s = srow[j];
+        const T z = buf[s & (kSB - 1)][c];
+        acc[j] += (__builtin_popcount(((unsigned)s >> 7) & i1u) & 1) ? -z : z;
+      }
+    }
+    __syncthreads();
+  }
+  const int64_t cc = c0 + c;
+  if (cc < a.nc) {
+    T* o = a.out + ((int64_t)blockIdx.y * a.nc + cc) * a.ldo;
+#pragma unroll
+    for (int j = 0; j < kSJ; ++j) {
+      const int r = g + kSG * j;
+      if (r < a.l) o[r] = (T)(a.scale * (double)acc[j]);
+    }
+  }
+}
+
+// Y^T(c, r) = sum over splits s (in order) of part[s](c, r).
+template <typename T>
+__global__ void srht_reduce_kernel(const T* part, int splits, int64_t nc, int l, int64_t ldo, T* Yt) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nc * l) return;
+  const int64_t c = e / l, r = e % l;
+  double s = 0.0;
+  for (int q = 0; q < splits; ++q) s += (double)part[((int64_t)q * nc + c) * ldo + r];
+  Yt[c * ldo + r] = (T)s;
+}
+
+template <typename T>
+hipError_t launch_t(const SrhtDesc& d, void* part, hipStream_t stream) {
+  SArgs<T> a{};
+  a.X = static_cast<const T*>(d.X); a.xr = d.xr; a.xc = d.xc;
+  a.mr = d.mr; a.nc = d.nc;
+  a.signs = d.signs; a.rows = d.rows; a.l = d.l;
+  a.ldo = d.ldo;
+  a.nblk = ceil_div(d.mr, kSB);
+  a.bps = ceil_div(a.nblk, d.splits);
+  int64_t mp = 1;
+  while (mp < d.mr) mp *= 2;
+  a.mp = mp;
+  a.scale = 1.0 / std::sqrt((double)std::max(d.l, 1));
+  a.status = d.status;
+  a.out = d.splits > 1 ? static_cast<T*>(part) : static_cast<T*>(d.Yt);
+  const dim3 grid((unsigned)ceil_div(d.nc, kSC), (unsigned)d.splits);
+  if (d.xc == 1) hipLaunchKernelGGL((srht_kernel<T, true>), grid, dim3(kST), 0, stream, a);
+  else hipLaunchKernelGGL((srht_kernel<T, false>), grid, dim3(kST), 0, stream, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || d.splits == 1) return e;
+  const int64_t tot = d.nc * d.l;
+  hipLaunchKernelGGL((srht_reduce_kernel<T>), dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, stream,
+                     static_cast<const T*>(part), d.splits, d.nc, d.l, d.ldo, static_cast<T*>(d.Yt));
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// Splits of the row blocks: about four workgroups per CU over the column
+// blocks, each split at least 8 blocks (1024 rows) deep.
+int srht_pick_splits(int64_t mr, int64_t nc, int num_cus) {
+  const int64_t cb = ceil_div(nc, kSC), nblk = ceil_div(mr, kSB);
+  int64_t s = ceil_div(4LL * std::max(num_cus, 1), cb);
+  s = std::min<int64_t>(s, std::max<int64_t>(1, nblk / 8));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(s, 64));
+}
+
+size_t srht_part_bytes(const SrhtDesc& d, int esize) {
+  return d.splits > 1 ? (size_t)d.splits * d.nc * d.ldo * esize : 0;
+}
+
+hipError_t srht_launch(int dtype, const SrhtDesc& d, void* part, hipStream_t stream) {
+  if (d.l < 1 || d.l > kSrhtMaxRows || d.splits < 1 || (d.xc != 1 && d.xr != 1)) return hipErrorInvalidValue;
+  if (d.mr <= 0 || d.nc <= 0) return hipSuccess;
+  return dtype == 0 ? launch_t<double>(d, part, stream) : launch_t<float>(d, part, stream);
+}
+
+}  // namespace idcur
