@@ -317,6 +317,74 @@ def bench_adjoint(args, P, synth, torch, dev, reps=10):
     return out
 
 
+def bench_structured(args, P, synth, torch, dev, A, k):
+    """The structured sketch (subsampled randomized Hadamard, the real form of
+    Section 5.2's) on the bench matrix with l = 2k and q = 0: the sketch
+    kernel's time against the HBM roofline (A read once), the CUR step on it,
+    the same step with a Gaussian sketch of the same l, and both errors against
+    the FP64 oracle with the same sketch matrix."""
+    import numpy as np
+    import oracle
+    from oracle import srht
+    m, n = A.shape
+    l = 2 * k
+    rows, signs = synth.srht_draws(m, l, seed=args.seed + 9)
+    rows_d = torch.as_tensor(rows, device=dev).contiguous()
+    signs_d = torch.as_tensor(signs, device=dev).contiguous()
+    kw = dict(p=l - k, q=0, srht=(rows_d, signs_d))
+    reps = max(5, args.steps)
+    out = {"workload": f"FP32 {m}x{n}, k={k}, l=2k={l}, q=0"}
+    for _ in range(2):
+        P.cur(A, k, sync=False, **kw)
+    P.sync_status(dev)
+    P.timing_enable(True, dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        r = P.cur(A, k, sync=False, **kw)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    st = P.timing_read(dev)
+    P.timing_enable(False, dev)
+    P.sync_status(dev)
+    sk_ms, sk_n = st["srht"]
+    sk_avg = sk_ms / max(sk_n, 1)
+    abytes = 4.0 * m * n + 4.0 * n * l + m + 4.0 * l
+    gbs = abytes / (sk_avg * 1e-3) / 1e9
+    er = P.cur_error(A, r.C, r.U, r.R, r.kout, k).tolist()
+    e_s = float(np.sqrt(er[0] / er[1]))
+    out["cur_ms"] = round(ms, 4)
+    out["rel_fro_error"] = e_s
+    out["stages_ms_per_step"] = {s: round(v[0] / reps, 4) for s, v in st.items() if v[1]}
+    out["sketch_kernel"] = {"avg_launch_ms": round(sk_avg, 4), "launches": sk_n,
+                            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                         "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_launch": abytes,
+                                         "note": "algorithmic bytes: A read once, Y^T written, signs and rows read"}}
+    # the same step with a Gaussian sketch of the same width
+    g_kw = dict(p=l - k, q=0, seed=args.seed + 1)
+    for _ in range(2):
+        P.cur(A, k, sync=False, **g_kw)
+    P.sync_status(dev)
+    e0.record()
+    for _ in range(reps):
+        rg = P.cur(A, k, sync=False, **g_kw)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_g = e0.elapsed_time(e1) / reps
+    P.sync_status(dev)
+    er = P.cur_error(A, rg.C, rg.U, rg.R, rg.kout, k).tolist()
+    out["gaussian_same_l"] = {"cur_ms": round(ms_g, 4), "rel_fro_error": float(np.sqrt(er[0] / er[1]))}
+    # oracle with the same structured sketch matrix
+    A_h = A.cpu().numpy().astype(np.float64)
+    ref = oracle.cur(A_h, k, omega=srht.srht_omega(m, rows, signs))
+    e_o = oracle.e_cur(A_h, ref.C, ref.U, ref.R)
+    out["oracle_rel_fro_error"] = e_o
+    out["error_ratio_vs_oracle"] = round(e_s / e_o, 4)
+    log("structured", out)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -329,6 +397,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched kernel-block measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable-ID (adjoint) measurements")
     ap.add_argument("--adjoint-only", action="store_true", help="only run the adjoint measurements")
+    ap.add_argument("--no-structured", action="store_true", help="skip the structured (Hadamard) sketch measurements")
     ap.add_argument("--no-library-gemm", action="store_true",
                     help="skip timing torch's FP32 GEMM on the sketch shape (context for the roofline)")
     ap.add_argument("--batched-only", action="store_true",
@@ -501,6 +570,10 @@ def main():
     # replayed from a captured graph)
     if not args.no_batched:
         result["batched"] = bench_batched(args, P, synth, torch, dev)
+
+    # the structured sketch (subsampled randomized Hadamard), l = 2k, q = 0
+    if not args.no_structured:
+        result["structured_sketch"] = bench_structured(args, P, synth, torch, dev, A, k)
 
     # gradient of the ID reconstruction loss (single matrix and 256 blocks)
     if not args.no_adjoint:

@@ -84,7 +84,7 @@ typedef enum {
  * >= the sketched dimension M, the matrix extended by zero rows), the random
  * unit-modulus diagonal by random signs, so that
  *   Omega(r, i) = l^(-1/2) (-1)^popcount(rows[r] & i) sign_i,  r < l, i < M.
- * The structured sketch needs q = 0, NATIVE precision, no omega, l <= 256, and
+ * The structured sketch needs q = 0, NATIVE precision, no omega, l <= 512, and
  * its random inputs from the caller: srht_rows (device int32[l], distinct values
  * in [0, m'); values out of range are reported as IDCUR_EINVAL by
  * idcur_sync_status) and srht_signs (device int8[M]: -1 where negative, else

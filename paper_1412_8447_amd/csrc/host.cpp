@@ -598,7 +598,7 @@ void validate(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const voi
     if (opts->prec != IDCUR_PREC_NATIVE) fail(ctx, IDCUR_EDTYPE, "the structured sketch runs in the native precision");
     if (opts->omega) fail(ctx, IDCUR_EINVAL, "omega and the structured sketch exclude each other");
     if (!opts->srht_rows || !opts->srht_signs) fail(ctx, IDCUR_EINVAL, "srht_rows and srht_signs are required");
-    if ((int64_t)kcap + opts->p > kSrhtMaxRows) fail(ctx, IDCUR_EINVAL, "k (kmax) + p must be <= 256 for the structured sketch");
+    if ((int64_t)kcap + opts->p > kSrhtMaxRows) fail(ctx, IDCUR_EINVAL, "k (kmax) + p must be <= 512 for the structured sketch");
   }
   (void)nc;
 }

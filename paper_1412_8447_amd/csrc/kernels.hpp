@@ -168,7 +168,7 @@ hipError_t batched_launch(const BatchedArgs& a, int variant, int num_cus, hipStr
 // mr x nc view X, X(i, c) = X[i*xr + c*xc] with xr == 1 or xc == 1;
 // Y(r, c) = l^(-1/2) sum_i (-1)^popcount(rows[r] & i) s_i X(i, c), s_i = -1 where
 // signs[i] < 0, else +1. Out-of-range rows flag ST_BADINDEX (row 0 is used).
-constexpr int kSrhtMaxRows = 256;
+constexpr int kSrhtMaxRows = 512;
 struct SrhtDesc {
   const void* X; int64_t xr, xc;
   int64_t mr, nc;

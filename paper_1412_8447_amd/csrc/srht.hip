@@ -23,7 +23,6 @@ constexpr int kSB = 128;                      // rows per block
 constexpr int kSC = 32;                       // columns per workgroup
 constexpr int kST = 256;                      // threads
 constexpr int kSG = kST / kSC;                // row groups (8)
-constexpr int kSJ = kSrhtMaxRows / kSG;       // sampled rows per thread
 
 template <typename T>
 struct SArgs {
@@ -39,73 +38,78 @@ struct SArgs {
 };
 
 template <typename T>
-__device__ __forceinline__ T signed_load(const T* X, int64_t off, bool ok, const int8_t* signs, int64_t i) {
+__device__ __forceinline__ T load_or_zero(const T* X, int64_t off, bool ok) {
   const T v = X[ok ? off : 0];
-  const int8_t d = signs[ok ? i : 0];
-  return ok ? (d < 0 ? -v : v) : T(0);
+  return ok ? v : T(0);
 }
 
 // XC1: X(i, c) = X[i*xr + c] (rows along memory); else X(i, c) = X[i + c*xc].
-template <typename T, bool XC1>
+// kSJ: sampled rows per thread (l <= 8 kSJ).
+template <typename T, bool XC1, int kSJ>
 __global__ __launch_bounds__(kST) void srht_kernel(SArgs<T> a) {
   __shared__ T buf[kSB][kSC + 1];
+  __shared__ int srow_s[kSG * kSJ];   // the sampled rows
+  __shared__ float sgn_s[2][kSB];     // the signs of a block's rows (two blocks in flight)
   const int tid = threadIdx.x, c = tid % kSC, g = tid / kSC;
   const int64_t c0 = (int64_t)blockIdx.x * kSC;
   const int64_t b0 = (int64_t)blockIdx.y * a.bps;
   const int64_t b1 = min(a.nblk, b0 + a.bps);
 
-  // sampled rows r = g + kSG j of this thread
-  int srow[kSJ];
-  T acc[kSJ];
+  // the sampled rows, to LDS (thread g, c accumulates rows r = g + kSG j)
   bool bad = false;
-#pragma unroll
-  for (int j = 0; j < kSJ; ++j) {
-    const int r = g + kSG * j;
+  for (int r = tid; r < kSG * kSJ; r += kST) {
     int s = r < a.l ? a.rows[r] : 0;
     if (s < 0 || s >= a.mp) {
       bad = true;
       s = 0;
     }
-    srow[j] = s;
-    acc[j] = T(0);
+    srow_s[r] = s;
   }
   if (bad) set_status(a.status, ST_BADINDEX);
+  T acc[kSJ];
+#pragma unroll
+  for (int j = 0; j < kSJ; ++j) acc[j] = T(0);
 
   // coalesced loads of one 128 x 32 block: XC1 -> thread (g, c) takes rows
   // 16 g .. 16 g + 15 of column c; else thread t takes row t % 128 of columns
   // t / 128 + 2 q
   T ld[16];
+  int8_t sg = 0;
   auto load_block = [&](int64_t i1) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       if (XC1) {
         const int64_t i = i1 * kSB + 16 * g + q, cc = c0 + c;
-        const bool ok = i < a.mr && cc < a.nc;
-        ld[q] = signed_load(a.X, i * a.xr + cc, ok, a.signs, i);
+        ld[q] = load_or_zero(a.X, i * a.xr + cc, i < a.mr && cc < a.nc);
       } else {
         const int64_t i = i1 * kSB + tid % kSB, cc = c0 + tid / kSB + 2 * q;
-        const bool ok = i < a.mr && cc < a.nc;
-        ld[q] = signed_load(a.X, i + cc * a.xc, ok, a.signs, i);
+        ld[q] = load_or_zero(a.X, i + cc * a.xc, i < a.mr && cc < a.nc);
       }
     }
+    if (tid < kSB) {
+      const int64_t i = i1 * kSB + tid;
+      sg = a.signs[i < a.mr ? i : 0];
+    }
   };
-  auto store_block = [&]() {
+  auto store_block = [&](int sb) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       if (XC1) buf[16 * g + q][c] = ld[q];
       else buf[tid % kSB][tid / kSB + 2 * q] = ld[q];
     }
+    if (tid < kSB) sgn_s[sb][tid] = sg < 0 ? -1.0f : 1.0f;
   };
 
   if (b0 < b1) load_block(b0);
-  for (int64_t i1 = b0; i1 < b1; ++i1) {
-    store_block();
+  int sb = 0;
+  for (int64_t i1 = b0; i1 < b1; ++i1, sb ^= 1) {
+    store_block(sb);
     __syncthreads();
     if (i1 + 1 < b1) load_block(i1 + 1);   // in flight during this block
-    // stages 1, 2, 4, 8: a thread's 16 consecutive rows of column c
+    // stages 1, 2, 4, 8: a thread's 16 consecutive rows of column c, signed
     T v[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = buf[16 * g + q][c];
+    for (int q = 0; q < 16; ++q) v[q] = sgn_s[sb][16 * g + q] < 0.0f ? -buf[16 * g + q][c] : buf[16 * g + q][c];
 #pragma unroll
     for (int h = 1; h < 16; h *= 2)
 #pragma unroll
@@ -138,15 +142,15 @@ __global__ __launch_bounds__(kST) void srht_kernel(SArgs<T> a) {
       for (int q = 0; q < 8; ++q) buf[lo + 16 * q][c] = u[q];
     }
     __syncthreads();
-    // each sampled row takes its entry of the transformed block
+    // each sampled row takes its entry of the transformed block (rows past l
+    // read row 0 into accumulators that are never stored: no branches, so the
+    // LDS reads issue together)
     const unsigned i1u = (unsigned)i1;
 #pragma unroll
     for (int j = 0; j < kSJ; ++j) {
-      if (g + kSG * j < a.l) {
-        const int s = srow[j];
-        const T z = buf[s & (kSB - 1)][c];
-        acc[j] += (__builtin_popcount(((unsigned)s >> 7) & i1u) & 1) ? -z : z;
-      }
+      const int s = srow_s[g + kSG * j];
+      const T z = buf[s & (kSB - 1)][c];
+      acc[j] += (__builtin_popcount(((unsigned)s >> 7) & i1u) & 1) ? -z : z;
     }
     __syncthreads();
   }
@@ -188,8 +192,14 @@ hipError_t launch_t(const SrhtDesc& d, void* part, hipStream_t stream) {
   a.status = d.status;
   a.out = d.splits > 1 ? static_cast<T*>(part) : static_cast<T*>(d.Yt);
   const dim3 grid((unsigned)ceil_div(d.nc, kSC), (unsigned)d.splits);
-  if (d.xc == 1) hipLaunchKernelGGL((srht_kernel<T, true>), grid, dim3(kST), 0, stream, a);
-  else hipLaunchKernelGGL((srht_kernel<T, false>), grid, dim3(kST), 0, stream, a);
+  const bool wide = d.l > kSG * 32;
+  if (d.xc == 1) {
+    if (wide) hipLaunchKernelGGL((srht_kernel<T, true, 64>), grid, dim3(kST), 0, stream, a);
+    else hipLaunchKernelGGL((srht_kernel<T, true, 32>), grid, dim3(kST), 0, stream, a);
+  } else {
+    if (wide) hipLaunchKernelGGL((srht_kernel<T, false, 64>), grid, dim3(kST), 0, stream, a);
+    else hipLaunchKernelGGL((srht_kernel<T, false, 32>), grid, dim3(kST), 0, stream, a);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || d.splits == 1) return e;
   const int64_t tot = d.nc * d.l;

@@ -38,7 +38,7 @@ def _draws(M, l, seed):
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 @pytest.mark.parametrize("row", [False, True])
 @pytest.mark.parametrize("m,n,l", [(1000, 300, 40), (130, 50, 16), (4096, 257, 100), (20000, 1000, 210),
-                                   (777, 2049, 255)])
+                                   (777, 2049, 255), (3000, 700, 257), (20000, 600, 400), (1100, 1300, 512)])
 def test_structured_sketch_within_summation_bound(dtype, row, m, n, l):
     say(f"srht sketch {dtype} row={row} {m}x{n} l={l}")
     M = n if row else m
