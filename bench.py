@@ -47,6 +47,7 @@ TRAFFIC = {
     "g16": ("sketch_gemm16_20000x10000_l210_traffic.md", ("gemm16_kernel.hpp", "gemm16.hip", "gemm16_f16.hip"),
             "gemm16_sources_sha"),
     "batched": ("batched_id_4096_kernel_blocks_traffic.md", ("batched.hip",), "batched_sources_sha"),
+    "srht": ("structured_sketch_srht_20000x10000_l400.md", ("srht.hip",), "srht_sources_sha"),
 }
 
 
@@ -359,7 +360,8 @@ def bench_structured(args, P, synth, torch, dev, A, k):
     out["stages_ms_per_step"] = {s: round(v[0] / reps, 4) for s, v in st.items() if v[1]}
     out["sketch_kernel"] = {"avg_launch_ms": round(sk_avg, 4), "launches": sk_n,
                             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                                         "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_launch": abytes,
+                                         "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": read_traffic("srht"),
+                                         "bytes_per_launch": abytes,
                                          "note": "algorithmic bytes: A read once, Y^T written, signs and rows read"}}
     # the same step with a Gaussian sketch of the same width
     g_kw = dict(p=l - k, q=0, seed=args.seed + 1)

@@ -51,7 +51,13 @@ __global__ __launch_bounds__(kST) void srht_kernel(SArgs<T> a) {
   __shared__ int srow_s[kSG * kSJ];   // the sampled rows
   __shared__ float sgn_s[2][kSB];     // the signs of a block's rows (two blocks in flight)
   const int tid = threadIdx.x, c = tid % kSC, g = tid / kSC;
-  const int64_t c0 = (int64_t)blockIdx.x * kSC;
+  // XCD-aware order: the 8 XCDs take workgroups round-robin, so XCD x gets the
+  // contiguous column-block range x*per .. (x+1)*per - 1 and neighbouring blocks
+  // (which share the 128-byte lines a row straddles) meet in the same L2
+  const int64_t per = gridDim.x / 8;   // gridDim.x is a multiple of 8
+  const int64_t cb = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (cb >= ceil_div(a.nc, kSC)) return;   // whole workgroup, before any barrier
+  const int64_t c0 = cb * kSC;
   const int64_t b0 = (int64_t)blockIdx.y * a.bps;
   const int64_t b1 = min(a.nblk, b0 + a.bps);
 
@@ -191,7 +197,9 @@ hipError_t launch_t(const SrhtDesc& d, void* part, hipStream_t stream) {
   a.scale = 1.0 / std::sqrt((double)std::max(d.l, 1));
   a.status = d.status;
   a.out = d.splits > 1 ? static_cast<T*>(part) : static_cast<T*>(d.Yt);
-  const dim3 grid((unsigned)ceil_div(d.nc, kSC), (unsigned)d.splits);
+  // x: column blocks rounded up to a multiple of 8 (the XCD-aware order skips
+  // the indices past the last block)
+  const dim3 grid((unsigned)round_up(ceil_div(d.nc, kSC), 8), (unsigned)d.splits);
   const bool wide = d.l > kSG * 32;
   if (d.xc == 1) {
     if (wide) hipLaunchKernelGGL((srht_kernel<T, true, 64>), grid, dim3(kST), 0, stream, a);
