@@ -133,10 +133,21 @@ def cur_u(R: np.ndarray, Vstar: np.ndarray) -> np.ndarray:
     return back_substitute(S, Q.T @ np.asarray(Vstar, dtype=np.float64).T).T
 
 
+def corrected_rhs(A: np.ndarray, C: np.ndarray, Vstar: np.ndarray) -> np.ndarray:
+    """The right-hand side of the error-corrected system for U (Section 4.3,
+    eq. (cur_ur_sys2)): V* + C^+ E with E = A - C V* the column-ID error
+    (eq. (id_error)); C^+ E is the least-squares solution of C X = E."""
+    A = np.asarray(A, dtype=np.float64)
+    C = np.asarray(C, dtype=np.float64)
+    E = A - C @ Vstar
+    return Vstar + np.linalg.lstsq(C, E, rcond=None)[0]
+
+
 def cur(A: np.ndarray, k: int, omega: np.ndarray | None = None, q: int = 0,
         tol: float | None = None, rank_tol: float | None = None,
-        row_rank_tol: float | None = None) -> CURResult:
-    """Algorithm 3 (CUR-ID): C = A(:, J(1:k)), R = A(I(1:k), :), U = V* R^+."""
+        row_rank_tol: float | None = None, u_correct: bool = False) -> CURResult:
+    """Algorithm 3 (CUR-ID): C = A(:, J(1:k)), R = A(I(1:k), :), U = V* R^+;
+    with ``u_correct`` U solves U R = V* + C^+ E instead (Section 4.3)."""
     A = np.asarray(A, dtype=np.float64)
     ts = two_sided(A, k, omega=omega, q=q, tol=tol, rank_tol=rank_tol,
                    row_rank_tol=row_rank_tol)
@@ -144,5 +155,6 @@ def cur(A: np.ndarray, k: int, omega: np.ndarray | None = None, q: int = 0,
     kr = ts.row.k
     R = A[ts.row.J[:kr], :]
     Vs = vstar_from(ts.col.J, ts.col.T, n)
-    U = cur_u(R, Vs)
+    rhs = corrected_rhs(A, ts.C, Vs) if u_correct else Vs
+    U = cur_u(R, rhs)
     return CURResult(ts=ts, C=ts.C, U=U, R=R)

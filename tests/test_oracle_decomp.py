@@ -199,3 +199,36 @@ def test_row_id_is_column_id_of_transpose():
     assert np.array_equal(r.J, c.J) and np.array_equal(r.T, c.T)
     W = w_from(r.J, r.T, 25)
     assert np.array_equal(W[r.J[:6]], np.eye(6))
+
+
+# ---------------------------------------------------------------------------
+# Error-corrected U (Section 4.3, eq. (cur_ur_sys2))
+# ---------------------------------------------------------------------------
+def test_corrected_u_is_the_frobenius_optimal_u_by_brute_force():
+    # tiny case: min_U |A - C U R|_F over all k x k U, solved as one least-squares
+    # problem in vec(U) (vec(C U R) = (R^T kron C) vec(U)); the corrected system
+    # must reach that optimum, the plain one not below it
+    import oracle.decomp as D
+    m, n, k = 14, 11, 3
+    A = synth.lowrank(m, n, synth.sigma_exp(min(m, n), 1.5), seed=4)
+    ref = D.cur(A, k, u_correct=True)
+    plain = D.cur(A, k)
+    K = np.kron(ref.R.T, ref.C)
+    u = np.linalg.lstsq(K, A.reshape(-1, order="F"), rcond=None)[0]
+    U_opt = u.reshape(k, k, order="F")
+    e_opt = np.linalg.norm(A - ref.C @ U_opt @ ref.R)
+    e_cor = np.linalg.norm(A - ref.C @ ref.U @ ref.R)
+    e_pl = np.linalg.norm(A - plain.C @ plain.U @ plain.R)
+    assert abs(e_cor - e_opt) <= 1e-10 * np.linalg.norm(A)
+    assert e_pl >= e_opt * (1 - 1e-12)
+
+
+def test_corrected_u_equals_c_pinv_a_r_pinv():
+    # closed form: V* + C^+ (A - C V*) = C^+ A when C has full column rank, so
+    # U = C^+ A R^+
+    import oracle.decomp as D
+    m, n, k = 60, 45, 7
+    A = synth.lowrank(m, n, synth.sigma_exp(min(m, n), 3.0), seed=12)
+    ref = D.cur(A, k, u_correct=True)
+    U_cf = np.linalg.pinv(ref.C) @ A @ np.linalg.pinv(ref.R)
+    assert np.abs(ref.U - U_cf).max() <= 1e-8 * np.abs(U_cf).max()
