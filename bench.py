@@ -400,6 +400,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable-ID (adjoint) measurements")
     ap.add_argument("--adjoint-only", action="store_true", help="only run the adjoint measurements")
     ap.add_argument("--no-structured", action="store_true", help="skip the structured (Hadamard) sketch measurements")
+    ap.add_argument("--no-ucorrect", action="store_true", help="skip the error-corrected U measurement")
     ap.add_argument("--no-library-gemm", action="store_true",
                     help="skip timing torch's FP32 GEMM on the sketch shape (context for the roofline)")
     ap.add_argument("--batched-only", action="store_true",
@@ -572,6 +573,30 @@ def main():
     # replayed from a captured graph)
     if not args.no_batched:
         result["batched"] = bench_batched(args, P, synth, torch, dev)
+
+    # the same step with the error-corrected U (U R = V* + C^+ E)
+    if not args.no_ucorrect:
+        outc = {kk: torch.empty_like(v) for kk, v in out.items()}
+        for _ in range(2):
+            P.cur(A, k, workspace=None, out=outc, sync=False, u_correct=True, **kw)
+        P.sync_status(dev)
+        P.timing_enable(True, dev)
+        reps = max(3, args.steps)
+        e0.record()
+        for _ in range(reps):
+            P.cur(A, k, out=outc, sync=False, u_correct=True, **kw)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_c = e0.elapsed_time(e1) / reps
+        st_c = P.timing_read(dev)
+        P.timing_enable(False, dev)
+        P.sync_status(dev)
+        er = P.cur_error(A, outc["C"], outc["U"], outc["R"], outc["kout"], k).tolist()
+        result["u_corrected"] = {"ms_per_step": round(ms_c, 4), "rel_fro_error": math.sqrt(er[0] / er[1]),
+                                 "error_ratio_vs_plain_u": round(math.sqrt(er[0] / er[1]) / e_cur, 4),
+                                 "u_solve_ms": round(st_c["u_solve"][0] / reps, 4)}
+        log("u_corrected", result["u_corrected"])
+        del outc
 
     # the structured sketch (subsampled randomized Hadamard), l = 2k, q = 0
     if not args.no_structured:

@@ -112,11 +112,15 @@ typedef struct {
   int32_t sketch;     /* idcur_sketch_kind (default Gaussian).                           */
   const int8_t* srht_signs;   /* structured sketch: device int8[M] signs (see above).     */
   const int32_t* srht_rows;   /* structured sketch: device int32[l] sampled rows.         */
+  int32_t u_correct;  /* idcur_cur only: 0 solves U R = V* (Section 4.3, eq. (cur_ur_sys));
+                         1 solves U R = V* + C^+ E, E = A - C V* the column-ID error
+                         (eq. (cur_ur_sys2)), which in exact arithmetic gives the
+                         U minimising |A - C U R|_F for the chosen C and R.        */
 } idcur_opts;
 
 /* Fill *opts with defaults: k = 0, kmax = 0, tol = 0, rank_tol = 0, p = -1
  * (deterministic), q = 0, seed = 0, omega = NULL, NATIVE precision, downdated norms,
- * Gaussian sketch (srht_signs = srht_rows = NULL). */
+ * Gaussian sketch (srht_signs = srht_rows = NULL), u_correct = 0. */
 void idcur_opts_default(idcur_opts* opts /* host */);
 
 /* Create a context bound to `stream` (a hipStream_t, borrowed, may be NULL for the

@@ -73,6 +73,7 @@ class Opts(ctypes.Structure):
         ("sketch", ctypes.c_int32),
         ("srht_signs", ctypes.c_void_p),
         ("srht_rows", ctypes.c_void_p),
+        ("u_correct", ctypes.c_int32),
     ]
 
 
@@ -183,11 +184,12 @@ def _dtype_code(t: torch.Tensor) -> int:
 
 def make_opts(k: int = 0, *, tol: float = 0.0, kmax: int = 0, p: int = -1, q: int = 0, seed: int = 0,
               omega: Optional[torch.Tensor] = None, rank_tol: float = 0.0, norms: str = "downdate",
-              prec: str = "native", srht: Optional[tuple] = None) -> Opts:
+              prec: str = "native", srht: Optional[tuple] = None, u_correct: bool = False) -> Opts:
     """Options of a decomposition call. ``srht = (rows, signs)`` selects the
     subsampled randomized Hadamard sketch with the given device tensors (rows:
     int32[l], distinct, below the padded order; signs: int8, one per sketched
-    row), instead of the Gaussian one."""
+    row), instead of the Gaussian one. ``u_correct`` makes a CUR call solve the
+    error-corrected system U R = V* + C^+ E for U."""
     o = Opts()
     _lib.idcur_opts_default(ctypes.byref(o))
     o.k, o.kmax, o.tol, o.rank_tol = int(k), int(kmax), float(tol), float(rank_tol)
@@ -202,6 +204,7 @@ def make_opts(k: int = 0, *, tol: float = 0.0, kmax: int = 0, p: int = -1, q: in
                 raise IDCurError(EINVAL, f"{name} must be a contiguous device tensor of {dt}")
         o.sketch = SKETCH_SRHT
         o.srht_rows, o.srht_signs = rows.data_ptr(), signs.data_ptr()
+    o.u_correct = 1 if u_correct else 0
     return o
 
 

@@ -503,8 +503,14 @@ void row_id_of_c(const Ctx& x, int dtype, const void* C, int64_t m, int kcap, co
 // R^T = Q S_R with S_R = L2^T L1^T, so U^T = S_R^{-1} Q^T V = L1^{-T} L2^{-T} Q^T V.
 // Every step is a matrix-core product with the explicit triangular inverses.
 // R: kr x n (row-major ldr), V* from (J, T); k = kout[0] columns, kr = kout[1].
+// With `corr` (A, lda, m and C = A(:, J(1:k)), m x kcap ld kcap given) the right
+// side is V* + C^+ E, E = A - C V* (the error-corrected system of Section 4.3,
+// eq. (cur_ur_sys2)): with Gc = C^T C = Lc Lc^T,
+//   (C^+ E)^T = (A^T C - V Gc) Gc^{-1} = (A^T C - V Gc) Lc^{-T} Lc^{-1},
+// A^T C accumulated in FP64, so the difference keeps its digits when E is small.
 void solve_u(const Ctx& x, int dtype, const void* R, int64_t ldr, int64_t n, int kcap, const int* kout, const int* J,
-             const void* T, int64_t ldt, void* U, int64_t ldu) {
+             const void* T, int64_t ldt, void* U, int64_t ldu, bool corr = false, const void* A = nullptr,
+             int64_t lda = 0, int64_t m = 0, const void* C = nullptr) {
   const int* k_dev = kout;
   const int* kr_dev = kout + 1;
   double* G = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
@@ -540,6 +546,36 @@ void solve_u(const Ctx& x, int dtype, const void* R, int64_t ldr, int64_t n, int
   prod(kcap, n, kcap, L2i, kcap, 1, 0, Q1t, n, 1, 0, Qt, n, 0, kr_dev, nullptr, kr_dev);
   // Bls = Q^T V (kr x k)
   if (!x.dry) x.check(build_v_launch(dtype, T, ldt, J, n, kcap, k_dev, V, kcap, x.s), "build V");
+  if (corr) {
+    double* Gc = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
+    double* Lc = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
+    double* Lci = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
+    double* Zt = static_cast<double*>(x.ar->take((size_t)n * kcap * 8));
+    double* W1 = static_cast<double*>(x.ar->take((size_t)n * kcap * 8));
+    // Gc = C^T C, its factor's inverse
+    prod(kcap, kcap, m, C, 1, kcap, dtype, C, kcap, 1, dtype, Gc, kcap, 0, k_dev, k_dev, nullptr);
+    chol_inv(x, 0, Gc, kcap, 1, kcap, k_dev, Lc, kcap, Lci, kcap, 0.0, "chol(C)", false);
+    // Zt = A^T C (n x k), then Zt -= V Gc
+    prod(n, kcap, m, A, 1, lda, dtype, C, kcap, 1, dtype, Zt, kcap, 0, nullptr, k_dev, nullptr);
+    GemmDesc g{};
+    g.M = n; g.N = kcap; g.K = kcap;
+    g.A = V; g.sam = kcap; g.sak = 1; g.a_type = 0;
+    g.B = Gc; g.sbk = kcap; g.sbn = 1; g.b_type = 0;
+    g.C = Zt; g.ldc = kcap; g.out_type = 0;
+    g.in_type = 0; g.acc_type = 0; g.alpha = -1.0; g.beta = 1.0;
+    g.n_dev = k_dev; g.k_dev = k_dev;
+    gemm(x, g);
+    // W1 = Zt Lc^{-T} (B(kk, j) = Lci[j][kk]), then V += W1 Lc^{-1}
+    prod(n, kcap, kcap, Zt, kcap, 1, 0, Lci, 1, kcap, 0, W1, kcap, 0, nullptr, k_dev, k_dev);
+    GemmDesc h{};
+    h.M = n; h.N = kcap; h.K = kcap;
+    h.A = W1; h.sam = kcap; h.sak = 1; h.a_type = 0;
+    h.B = Lci; h.sbk = kcap; h.sbn = 1; h.b_type = 0;
+    h.C = V; h.ldc = kcap; h.out_type = 0;
+    h.in_type = 0; h.acc_type = 0; h.alpha = 1.0; h.beta = 1.0;
+    h.n_dev = k_dev; h.k_dev = k_dev;
+    gemm(x, h);
+  }
   prod(kcap, kcap, n, Qt, n, 1, 0, V, kcap, 1, 0, Bls, kcap, 0, kr_dev, k_dev, nullptr);
   // Y1 = L2^{-T} Bls  (A(i, kk) = L2i[kk][i])
   prod(kcap, kcap, kcap, L2i, 1, kcap, 0, Bls, kcap, 1, 0, Y1, kcap, 0, kr_dev, k_dev, kr_dev);
@@ -593,6 +629,7 @@ void validate(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const voi
   if (opts->norms != IDCUR_NORMS_DOWNDATE && opts->norms != IDCUR_NORMS_EXACT) fail(ctx, IDCUR_EINVAL, "bad norms");
   if (opts->sketch != IDCUR_SKETCH_GAUSSIAN && opts->sketch != IDCUR_SKETCH_SRHT)
     fail(ctx, IDCUR_EINVAL, "unknown sketch kind");
+  if (opts->u_correct != 0 && opts->u_correct != 1) fail(ctx, IDCUR_EINVAL, "u_correct must be 0 or 1");
   if (opts->sketch == IDCUR_SKETCH_SRHT && opts->p >= 0 && (int64_t)kcap + opts->p < mr) {
     if (opts->q != 0) fail(ctx, IDCUR_EINVAL, "the structured sketch takes no power steps (q = 0)");
     if (opts->prec != IDCUR_PREC_NATIVE) fail(ctx, IDCUR_EDTYPE, "the structured sketch runs in the native precision");
@@ -657,7 +694,7 @@ void execute(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const void
     if (out.C) x.check(gather_cols_launch(dtype, m, A, lda, J, kcap, out.k_out, out.C, out.ldc, dtype, x.s), "C out");
   }
   Stage st(x, "u_solve");
-  solve_u(x, dtype, R, ldr, n, kcap, out.k_out, J, T, ldt, out.U, out.ldu);
+  solve_u(x, dtype, R, ldr, n, kcap, out.k_out, J, T, ldt, out.U, out.ldu, o.u_correct != 0, A, lda, m, C);
 }
 
 // Error measurement: out[0] = |A - C W|_F^2, out[1] = |A|_F^2 (device doubles).
