@@ -4,25 +4,27 @@
 // For the mr x nc view X it writes Y^T (nc x l) with
 //   Y(r, c) = l^(-1/2) sum_{i < mr} (-1)^popcount(s_r & i) d_i X(i, c),
 // s_r the sampled rows (distinct, < m' = the smallest power of two >= mr),
-// d_i = +-1. With i = 128 i1 + i2 and s = 128 s1 + s2 the sign factors into
-// (-1)^popcount(s1 & i1) (-1)^popcount(s2 & i2): each 128-row block of X is
-// transformed by the length-128 Walsh-Hadamard transform (seven butterfly
-// stages: four on a thread's 16 rows in registers, three more after one
+// d_i = +-1. With i = 256 i1 + i2 and s = 256 s1 + s2 the sign factors into
+// (-1)^popcount(s1 & i1) (-1)^popcount(s2 & i2): each 256-row block of X is
+// transformed by the length-256 Walsh-Hadamard transform (eight butterfly
+// stages: four on a thread's 16 rows in registers, four more after one
 // exchange through LDS), and every sampled row takes entry s2 of the
-// transformed block with sign (-1)^popcount(s1 & i1). X is read once, with 7
-// additions and l / 128 multiply-adds per element, so the kernel is bound by
-// HBM. Row blocks are split over the grid; the split partial sums are added in
-// split order by a second kernel.
+// transformed block with sign (-1)^popcount(s1 & i1). X is read once, with 8
+// additions and l / 256 signed additions per element. Row blocks are split
+// over the grid; the split partial sums are added in split order by a second
+// kernel.
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace idcur {
 namespace {
 
-constexpr int kSB = 128;                      // rows per block
-constexpr int kSC = 32;                       // columns per workgroup
+constexpr int kSB = 256;                      // rows per block
+constexpr int kSBL = 8;                       // log2(kSB)
+constexpr int kSC = 16;                       // columns per workgroup
 constexpr int kST = 256;                      // threads
-constexpr int kSG = kST / kSC;                // row groups (8)
+constexpr int kSG = kST / kSC;                // row groups (16)
+static_assert(kST == kSB, "a thread per block row");
 
 template <typename T>
 struct SArgs {
@@ -43,12 +45,35 @@ __device__ __forceinline__ T load_or_zero(const T* X, int64_t off, bool ok) {
   return ok ? v : T(0);
 }
 
-// XC1: X(i, c) = X[i*xr + c] (rows along memory); else X(i, c) = X[i + c*xc].
-// kSJ: sampled rows per thread (l <= 8 kSJ).
-template <typename T, bool XC1, int kSJ>
+// Column loads through a buffer descriptor per column: rows past mr (and every
+// row of a column past nc, whose descriptor has no records) read as zero
+// without per-element address arithmetic or selects.
+template <typename T>
+__device__ __forceinline__ T col_load(const T* col, int64_t nrec_bytes, uint32_t byte_off) {
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(col), (short)0, (int)nrec_bytes, 0x00020000);
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)byte_off, 0, 0));
+  } else {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)byte_off, 0, 0));
+  }
+}
+
+// LAY 0: X(i, c) = X[i*xr + c] (rows along memory); LAY 1: X(i, c) = X[i + c*xc]
+// with pointer loads; LAY 2: the same through column buffer descriptors (a
+// column's bytes, mr * sizeof(T) plus one block, below 2^31).
+// kSJ: sampled rows per thread (l <= kSG kSJ).
+template <typename T, int LAY, int kSJ>
 __global__ __launch_bounds__(kST) void srht_kernel(SArgs<T> a) {
+  constexpr bool XC1 = LAY == 0;
+  // one sampled row's term for the current block: the byte offset of its
+  // entry s2 in buf (column 0) and its sign (-1)^popcount(s1 & i1)
+  struct Tap {
+    int off;
+    float sgn;
+  };
   __shared__ T buf[kSB][kSC + 1];
-  __shared__ int srow_s[kSG * kSJ];   // the sampled rows
+  __shared__ Tap tap_s[kSG * kSJ];    // the sampled rows' terms, rebuilt per block
   __shared__ float sgn_s[2][kSB];     // the signs of a block's rows (two blocks in flight)
   const int tid = threadIdx.x, c = tid % kSC, g = tid / kSC;
   // XCD-aware order: the 8 XCDs take workgroups round-robin, so XCD x gets the
@@ -61,61 +86,87 @@ __global__ __launch_bounds__(kST) void srht_kernel(SArgs<T> a) {
   const int64_t b0 = (int64_t)blockIdx.y * a.bps;
   const int64_t b1 = min(a.nblk, b0 + a.bps);
 
-  // the sampled rows, to LDS (thread g, c accumulates rows r = g + kSG j)
+  // the sampled rows this thread keeps the terms of (r = tid + kST h; thread
+  // g, c accumulates rows r = g + kSG j); rows past l get sign 0
+  constexpr int kSH = (kSG * kSJ + kST - 1) / kST;
+  unsigned s_hi[kSH];
+  int s_off[kSH];
+  bool s_on[kSH];
   bool bad = false;
-  for (int r = tid; r < kSG * kSJ; r += kST) {
+#pragma unroll
+  for (int h = 0; h < kSH; ++h) {
+    const int r = tid + kST * h;
     int s = r < a.l ? a.rows[r] : 0;
     if (s < 0 || s >= a.mp) {
       bad = true;
       s = 0;
     }
-    srow_s[r] = s;
+    s_hi[h] = (unsigned)s >> kSBL;
+    s_off[h] = (s & (kSB - 1)) * (kSC + 1) * (int)sizeof(T);
+    s_on[h] = r < a.l;
   }
   if (bad) set_status(a.status, ST_BADINDEX);
+  const char* col_base = reinterpret_cast<const char*>(&buf[0][c]);
   T acc[kSJ];
 #pragma unroll
   for (int j = 0; j < kSJ; ++j) acc[j] = T(0);
 
-  // coalesced loads of one 128 x 32 block: XC1 -> thread (g, c) takes rows
-  // 16 g .. 16 g + 15 of column c; else thread t takes row t % 128 of columns
-  // t / 128 + 2 q
+  // coalesced loads of one 256 x 16 block: XC1 -> thread (g, c) takes rows
+  // 16 g .. 16 g + 15 of column c; else thread t takes row t of the 16 columns
   T ld[16];
   int8_t sg = 0;
   auto load_block = [&](int64_t i1) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      if (XC1) {
+      if constexpr (LAY == 0) {
         const int64_t i = i1 * kSB + 16 * g + q, cc = c0 + c;
         ld[q] = load_or_zero(a.X, i * a.xr + cc, i < a.mr && cc < a.nc);
-      } else {
-        const int64_t i = i1 * kSB + tid % kSB, cc = c0 + tid / kSB + 2 * q;
+      } else if constexpr (LAY == 1) {
+        const int64_t i = i1 * kSB + tid, cc = c0 + q;
         ld[q] = load_or_zero(a.X, i + cc * a.xc, i < a.mr && cc < a.nc);
+      } else {
+        const int64_t cc = c0 + q;
+        ld[q] = col_load(a.X + cc * a.xc, cc < a.nc ? a.mr * (int64_t)sizeof(T) : 0,
+                         (uint32_t)((i1 * kSB + tid) * (int64_t)sizeof(T)));
       }
     }
-    if (tid < kSB) {
-      const int64_t i = i1 * kSB + tid;
+    {
+      const int64_t i = i1 * kSB + tid;   // kST == kSB
       sg = a.signs[i < a.mr ? i : 0];
     }
   };
+  // the row signs: XC1 -> to LDS, for the thread that holds the row in stage 1;
+  // else thread t holds row t of every column and applies its sign here
   auto store_block = [&](int sb) {
+    const float sgf = sg < 0 ? -1.0f : 1.0f;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       if (XC1) buf[16 * g + q][c] = ld[q];
-      else buf[tid % kSB][tid / kSB + 2 * q] = ld[q];
+      else buf[tid][q] = (T)sgf * ld[q];   // exact, branch-free
     }
-    if (tid < kSB) sgn_s[sb][tid] = sg < 0 ? -1.0f : 1.0f;
+    if (XC1) sgn_s[sb][tid] = sgf;
   };
 
   if (b0 < b1) load_block(b0);
   int sb = 0;
   for (int64_t i1 = b0; i1 < b1; ++i1, sb ^= 1) {
     store_block(sb);
+    const unsigned i1u = (unsigned)i1;
+#pragma unroll
+    for (int h = 0; h < kSH; ++h) {
+      const int r = tid + kST * h;
+      if (r < kSG * kSJ) {
+        const float sg1 = (__builtin_popcount(s_hi[h] & i1u) & 1) ? -1.0f : 1.0f;
+        tap_s[r] = Tap{s_off[h], s_on[h] ? sg1 : 0.0f};
+      }
+    }
     __syncthreads();
     if (i1 + 1 < b1) load_block(i1 + 1);   // in flight during this block
     // stages 1, 2, 4, 8: a thread's 16 consecutive rows of column c, signed
     T v[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = sgn_s[sb][16 * g + q] < 0.0f ? -buf[16 * g + q][c] : buf[16 * g + q][c];
+    for (int q = 0; q < 16; ++q)
+      v[q] = XC1 ? (T)sgn_s[sb][16 * g + q] * buf[16 * g + q][c] : buf[16 * g + q][c];
 #pragma unroll
     for (int h = 1; h < 16; h *= 2)
 #pragma unroll
@@ -128,35 +179,31 @@ __global__ __launch_bounds__(kST) void srht_kernel(SArgs<T> a) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) buf[16 * g + q][c] = v[q];
     __syncthreads();
-    // stages 16, 32, 64: rows lo + 16 u (u < 8) for lo = 2 g and 2 g + 1
+    // stages 16, 32, 64, 128: rows g + 16 u (u < 16) of column c
+    {
+      T u[16];
 #pragma unroll
-    for (int hh = 0; hh < 2; ++hh) {
-      const int lo = 2 * g + hh;
-      T u[8];
+      for (int q = 0; q < 16; ++q) u[q] = buf[g + 16 * q][c];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) u[q] = buf[lo + 16 * q][c];
+      for (int h = 1; h < 16; h *= 2)
 #pragma unroll
-      for (int h = 1; h < 8; h *= 2)
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
+        for (int q = 0; q < 16; ++q)
           if ((q & h) == 0) {
             const T x0 = u[q], x1 = u[q + h];
             u[q] = x0 + x1;
             u[q + h] = x0 - x1;
           }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) buf[lo + 16 * q][c] = u[q];
+      for (int q = 0; q < 16; ++q) buf[g + 16 * q][c] = u[q];
     }
     __syncthreads();
-    // each sampled row takes its entry of the transformed block (rows past l
-    // read row 0 into accumulators that are never stored: no branches, so the
-    // LDS reads issue together)
-    const unsigned i1u = (unsigned)i1;
+    // each sampled row takes its signed entry of the transformed block (rows
+    // past l add zero times row 0: no branches, so the LDS reads issue together)
 #pragma unroll
     for (int j = 0; j < kSJ; ++j) {
-      const int s = srow_s[g + kSG * j];
-      const T z = buf[s & (kSB - 1)][c];
-      acc[j] += (__builtin_popcount(((unsigned)s >> 7) & i1u) & 1) ? -z : z;
+      const Tap e = tap_s[g + kSG * j];
+      const T z = *reinterpret_cast<const T*>(col_base + e.off);
+      acc[j] = fma((T)e.sgn, z, acc[j]);
     }
     __syncthreads();
   }
@@ -200,13 +247,19 @@ hipError_t launch_t(const SrhtDesc& d, void* part, hipStream_t stream) {
   // x: column blocks rounded up to a multiple of 8 (the XCD-aware order skips
   // the indices past the last block)
   const dim3 grid((unsigned)round_up(ceil_div(d.nc, kSC), 8), (unsigned)d.splits);
-  const bool wide = d.l > kSG * 32;
+  const bool wide = d.l > kSG * 16;
+  // column descriptors hold a column's bytes (plus a block of slack for the
+  // offsets past mr) in 31 bits
+  const bool bufok = (d.mr + kSB) * (int64_t)sizeof(T) < ((int64_t)1 << 31);
   if (d.xc == 1) {
-    if (wide) hipLaunchKernelGGL((srht_kernel<T, true, 64>), grid, dim3(kST), 0, stream, a);
-    else hipLaunchKernelGGL((srht_kernel<T, true, 32>), grid, dim3(kST), 0, stream, a);
+    if (wide) hipLaunchKernelGGL((srht_kernel<T, 0, 32>), grid, dim3(kST), 0, stream, a);
+    else hipLaunchKernelGGL((srht_kernel<T, 0, 16>), grid, dim3(kST), 0, stream, a);
+  } else if (bufok) {
+    if (wide) hipLaunchKernelGGL((srht_kernel<T, 2, 32>), grid, dim3(kST), 0, stream, a);
+    else hipLaunchKernelGGL((srht_kernel<T, 2, 16>), grid, dim3(kST), 0, stream, a);
   } else {
-    if (wide) hipLaunchKernelGGL((srht_kernel<T, false, 64>), grid, dim3(kST), 0, stream, a);
-    else hipLaunchKernelGGL((srht_kernel<T, false, 32>), grid, dim3(kST), 0, stream, a);
+    if (wide) hipLaunchKernelGGL((srht_kernel<T, 1, 32>), grid, dim3(kST), 0, stream, a);
+    else hipLaunchKernelGGL((srht_kernel<T, 1, 16>), grid, dim3(kST), 0, stream, a);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || d.splits == 1) return e;
@@ -219,7 +272,7 @@ hipError_t launch_t(const SrhtDesc& d, void* part, hipStream_t stream) {
 }  // namespace
 
 // Splits of the row blocks: about four workgroups per CU over the column
-// blocks, each split at least 8 blocks (1024 rows) deep.
+// blocks, each split at least 8 blocks (2048 rows) deep.
 int srht_pick_splits(int64_t mr, int64_t nc, int num_cus) {
   const int64_t cb = ceil_div(nc, kSC), nblk = ceil_div(mr, kSB);
   int64_t s = ceil_div(4LL * std::max(num_cus, 1), cb);
