@@ -45,13 +45,13 @@ __device__ __forceinline__ T load_or_zero(const T* X, int64_t off, bool ok) {
   return ok ? v : T(0);
 }
 
-// Column loads through a buffer descriptor per column: rows past mr (and every
-// row of a column past nc, whose descriptor has no records) read as zero
-// without per-element address arithmetic or selects.
+// Loads through a buffer descriptor: offsets at or past the descriptor's byte
+// count read as zero, which takes the place of per-element bounds selects and
+// 64-bit address arithmetic.
 template <typename T>
-__device__ __forceinline__ T col_load(const T* col, int64_t nrec_bytes, uint32_t byte_off) {
+__device__ __forceinline__ T rsrc_load(const T* base, int64_t nrec_bytes, uint32_t byte_off) {
   const __amdgpu_buffer_rsrc_t rs =
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(col), (short)0, (int)nrec_bytes, 0x00020000);
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, (int)nrec_bytes, 0x00020000);
   if constexpr (sizeof(T) == 4) {
     return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)byte_off, 0, 0));
   } else {
@@ -59,13 +59,15 @@ __device__ __forceinline__ T col_load(const T* col, int64_t nrec_bytes, uint32_t
   }
 }
 
-// LAY 0: X(i, c) = X[i*xr + c] (rows along memory); LAY 1: X(i, c) = X[i + c*xc]
-// with pointer loads; LAY 2: the same through column buffer descriptors (a
+// LAY 0: X(i, c) = X[i*xr + c] (rows along memory) with pointer loads; LAY 3:
+// the same through one descriptor per block (the block's rows below mr; a
+// block's bytes, 257 xr sizeof(T), below 2^31); LAY 1: X(i, c) = X[i + c*xc]
+// with pointer loads; LAY 2: the same through one descriptor per column (a
 // column's bytes, mr * sizeof(T) plus one block, below 2^31).
 // kSJ: sampled rows per thread (l <= kSG kSJ).
 template <typename T, int LAY, int kSJ>
 __global__ __launch_bounds__(kST) void srht_kernel(SArgs<T> a) {
-  constexpr bool XC1 = LAY == 0;
+  constexpr bool XC1 = LAY == 0 || LAY == 3;
   // one sampled row's term for the current block: the byte offset of its
   // entry s2 in buf (column 0) and its sign (-1)^popcount(s1 & i1)
   struct Tap {
@@ -115,10 +117,19 @@ __global__ __launch_bounds__(kST) void srht_kernel(SArgs<T> a) {
   // 16 g .. 16 g + 15 of column c; else thread t takes row t of the 16 columns
   T ld[16];
   int8_t sg = 0;
+  // LAY 3: load q of a block reads row 16 g + q through a descriptor based at
+  // block row q, at the lane's byte offset (16 g xr + c) sizeof(T), which is
+  // below the descriptor's count exactly when the row is below mr; columns past
+  // nc take an offset past every count, so they read zero
+  const uint32_t lane_off = c0 + c < a.nc ? (uint32_t)((16 * g * a.xr + c) * (int64_t)sizeof(T)) : 0x80000000u;
   auto load_block = [&](int64_t i1) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      if constexpr (LAY == 0) {
+      if constexpr (LAY == 3) {
+        const int64_t r0 = i1 * kSB + q;   // the descriptor's first row
+        const int64_t nrec = r0 < a.mr ? min(a.mr - r0, (int64_t)kSB) * a.xr * (int64_t)sizeof(T) : 0;
+        ld[q] = rsrc_load(a.X + r0 * a.xr + c0, nrec, lane_off);
+      } else if constexpr (LAY == 0) {
         const int64_t i = i1 * kSB + 16 * g + q, cc = c0 + c;
         ld[q] = load_or_zero(a.X, i * a.xr + cc, i < a.mr && cc < a.nc);
       } else if constexpr (LAY == 1) {
@@ -126,7 +137,7 @@ __global__ __launch_bounds__(kST) void srht_kernel(SArgs<T> a) {
         ld[q] = load_or_zero(a.X, i + cc * a.xc, i < a.mr && cc < a.nc);
       } else {
         const int64_t cc = c0 + q;
-        ld[q] = col_load(a.X + cc * a.xc, cc < a.nc ? a.mr * (int64_t)sizeof(T) : 0,
+        ld[q] = rsrc_load(a.X + cc * a.xc, cc < a.nc ? a.mr * (int64_t)sizeof(T) : 0,
                          (uint32_t)((i1 * kSB + tid) * (int64_t)sizeof(T)));
       }
     }
@@ -135,16 +146,17 @@ __global__ __launch_bounds__(kST) void srht_kernel(SArgs<T> a) {
       sg = a.signs[i < a.mr ? i : 0];
     }
   };
-  // the row signs: XC1 -> to LDS, for the thread that holds the row in stage 1;
-  // else thread t holds row t of every column and applies its sign here
+  // XC1: the loaded rows are the ones the thread transforms first, so they stay
+  // in registers, and the row signs go to LDS for them; else thread t holds
+  // row t of every column, applies its sign and stores the block to LDS
   auto store_block = [&](int sb) {
     const float sgf = sg < 0 ? -1.0f : 1.0f;
+    if constexpr (XC1) {
+      sgn_s[sb][tid] = sgf;
+    } else {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      if (XC1) buf[16 * g + q][c] = ld[q];
-      else buf[tid][q] = (T)sgf * ld[q];   // exact, branch-free
+      for (int q = 0; q < 16; ++q) buf[tid][q] = (T)sgf * ld[q];   // exact, branch-free
     }
-    if (XC1) sgn_s[sb][tid] = sgf;
   };
 
   if (b0 < b1) load_block(b0);
@@ -161,12 +173,17 @@ __global__ __launch_bounds__(kST) void srht_kernel(SArgs<T> a) {
       }
     }
     __syncthreads();
-    if (i1 + 1 < b1) load_block(i1 + 1);   // in flight during this block
     // stages 1, 2, 4, 8: a thread's 16 consecutive rows of column c, signed
     T v[16];
+    if constexpr (XC1) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q)
-      v[q] = XC1 ? (T)sgn_s[sb][16 * g + q] * buf[16 * g + q][c] : buf[16 * g + q][c];
+      for (int q = 0; q < 16; ++q) v[q] = (T)sgn_s[sb][16 * g + q] * ld[q];   // exact
+    }
+    if (i1 + 1 < b1) load_block(i1 + 1);   // in flight during this block
+    if constexpr (!XC1) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v[q] = buf[16 * g + q][c];
+    }
 #pragma unroll
     for (int h = 1; h < 16; h *= 2)
 #pragma unroll
@@ -251,7 +268,13 @@ hipError_t launch_t(const SrhtDesc& d, void* part, hipStream_t stream) {
   // column descriptors hold a column's bytes (plus a block of slack for the
   // offsets past mr) in 31 bits
   const bool bufok = (d.mr + kSB) * (int64_t)sizeof(T) < ((int64_t)1 << 31);
-  if (d.xc == 1) {
+  // row-major: a block's bytes (and the offsets of the columns past nc, from
+  // 2^31 up) in 32 bits
+  const bool rbufok = (kSB + 1) * d.xr * (int64_t)sizeof(T) < ((int64_t)1 << 31) && d.xr >= d.nc;
+  if (d.xc == 1 && rbufok) {
+    if (wide) hipLaunchKernelGGL((srht_kernel<T, 3, 32>), grid, dim3(kST), 0, stream, a);
+    else hipLaunchKernelGGL((srht_kernel<T, 3, 16>), grid, dim3(kST), 0, stream, a);
+  } else if (d.xc == 1) {
     if (wide) hipLaunchKernelGGL((srht_kernel<T, 0, 32>), grid, dim3(kST), 0, stream, a);
     else hipLaunchKernelGGL((srht_kernel<T, 0, 16>), grid, dim3(kST), 0, stream, a);
   } else if (bufok) {
