@@ -116,11 +116,22 @@ typedef struct {
                          1 solves U R = V* + C^+ E, E = A - C V* the column-ID error
                          (eq. (cur_ur_sys2)), which in exact arithmetic gives the
                          U minimising |A - C U R|_F for the chosen C and R.        */
+  double t_reg;       /* 0: T = S11^{-1} S12 (Section 2.3, eq. (S11T=S12)). In (0, 1): the
+                         stabilized T of Section 4.1 (eq. (lsqr_for_T) with a Tikhonov
+                         term), T = argmin |S11 U - S12|_F^2 + lam^2 |U|_F^2 with
+                         lam = t_reg max_j |S11(:, j)|_2 (= t_reg |S11(1, 1)| for the
+                         pivoted QR), for every interpolation matrix the call forms
+                         (column ID, row ID, both IDs of a two-sided ID or CUR).
+                         Solved as the least-squares problem [S11; lam I] U =
+                         [S12; 0] through an FP64 Cholesky QR taken twice, with an
+                         error of about u / t_reg relative to |T| (u = 2^-53), so
+                         t_reg should exceed about 1e-8. Other values:
+                         IDCUR_EINVAL.                                             */
 } idcur_opts;
 
 /* Fill *opts with defaults: k = 0, kmax = 0, tol = 0, rank_tol = 0, p = -1
  * (deterministic), q = 0, seed = 0, omega = NULL, NATIVE precision, downdated norms,
- * Gaussian sketch (srht_signs = srht_rows = NULL), u_correct = 0. */
+ * Gaussian sketch (srht_signs = srht_rows = NULL), u_correct = 0, t_reg = 0. */
 void idcur_opts_default(idcur_opts* opts /* host */);
 
 /* Create a context bound to `stream` (a hipStream_t, borrowed, may be NULL for the
@@ -276,7 +287,7 @@ idcur_status idcur_id_col_backward(idcur_ctx* ctx, int32_t dtype, int64_t m, int
  *   level, and 10 sqrt(l_cap) u32 with a fixed rank).
  *   T = S11^{-1} S12 by FP64 back-substitution.
  * Limits: 1 <= n_b <= nmax <= 512, 1 <= m_b <= mmax, (k or kmax) + p <= 64,
- * p >= 1, q = 0, NATIVE precision, dtype IDCUR_F32. A block outside its limits
+ * p >= 1, q = 0, t_reg = 0, NATIVE precision, dtype IDCUR_F32. A block outside its limits
  * gets k_out[b] = -1 and IDCUR_EINVAL from idcur_sync_status.
  * All arrays are DEVICE arrays of nblk entries: m, n (int32), A (pointers to
  * const float), lda (int64), and the outputs k_out (int32), J (pointers to

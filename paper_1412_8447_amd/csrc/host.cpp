@@ -237,7 +237,7 @@ void orth_rows(const Ctx& x, int dtype, const void* Vt, void* Qt, int64_t N, int
 // ld ldS): S11 gathered and inverted (as the lower factor S11^T), S12 gathered,
 // T = (S11^{-T})^T S12 as an FP64 matrix-core product written in T's dtype.
 void interp_matrix(const Ctx& x, int dtype, const void* S, int64_t ldS, const int* J, int64_t n, int kcap,
-                   const int* k_dev, void* T, int64_t ldt) {
+                   const int* k_dev, void* T, int64_t ldt, double t_reg = 0.0) {
   double* S11 = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
   double* S11it = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
   double* S12 = static_cast<double*>(x.ar->take((size_t)kcap * std::max<int64_t>(n - 1, 1) * 8));
@@ -248,16 +248,59 @@ void interp_matrix(const Ctx& x, int dtype, const void* S, int64_t ldS, const in
     x.check(gather_s12_launch(dtype, S, ldS, J, n, kcap, k_dev, S12, ldo, ncol, x.s), "gather S12");
     // view S11^T as lower: element (i, j) = S11[j][i]
   }
+  auto mm = [&](int64_t M, int64_t N, const double* Am, int64_t sam, int64_t sak, const double* Bm, int64_t sbk,
+                int64_t sbn, void* Cm, int64_t ldc, int ct, const int* nd, double beta = 0.0) {
+    GemmDesc g{};
+    g.M = M; g.N = N; g.K = kcap;
+    g.A = Am; g.sam = sam; g.sak = sak;
+    g.B = Bm; g.sbk = sbk; g.sbn = sbn;
+    g.C = Cm; g.ldc = ldc;
+    g.in_type = 0; g.acc_type = 0; g.out_type = ct;
+    g.alpha = 1.0; g.beta = beta;
+    g.m_dev = k_dev; g.k_dev = k_dev; g.n_dev = nd;
+    gemm(x, g);
+  };
+  if (t_reg > 0.0) {
+    // Tikhonov-stabilized T (Section 4.1, eq. (lsqr_for_T) with a regularization
+    // term): T = argmin |S11 U - S12|^2 + lam^2 |U|^2, lam = t_reg times the
+    // largest column norm of S11, the least-squares solution of M U = [S12; 0]
+    // with M = [S11; lam I]. M = Q R by Cholesky QR twice (FP64), which keeps
+    // the error at about u cond(M) <= u / t_reg instead of the normal
+    // equations' u / t_reg^2:
+    //   L1 L1^T = M^T M = S11^T S11 + lam^2 I,  Q1 = M L1^{-T}
+    //   L2 L2^T = Q1^T Q1 = Qt^T Qt + lam^2 L1^{-1} L1^{-T},  Qt = S11 L1^{-T}
+    //   Q = Q1 L2^{-T}, R = L2^T L1^T, T = R^{-1} Q^T [S12; 0]
+    //     = L1^{-T} L2^{-T} (Qt L2^{-T})^T S12.
+    double* G = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
+    double* L = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
+    double* L1i = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
+    double* L2i = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
+    double* Qt = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
+    double* Q = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
+    double* P = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
+    double* lam2 = static_cast<double*>(x.ar->take(256));
+    double* W = static_cast<double*>(x.ar->take((size_t)kcap * ldo * 8));
+    double* Z = static_cast<double*>(x.ar->take((size_t)kcap * ldo * 8));
+    // G = S11^T S11 (A(i, kk) = S11[kk][i]); lam^2 = t_reg^2 max diag(G)
+    mm(kcap, kcap, S11, 1, kcap, S11, kcap, 1, G, kcap, 0, k_dev);
+    if (!x.dry) x.check(diag_shift_launch(G, kcap, 1, kcap, k_dev, t_reg * t_reg, lam2, x.s), "lam^2");
+    chol_inv(x, 0, G, kcap, 1, kcap, k_dev, L, kcap, L1i, kcap, t_reg * t_reg, "chol(S11^T S11 + lam^2 I)", false);
+    // Qt = S11 L1^{-T} (B(kk, j) = L1i[j][kk]); G = Qt^T Qt + lam^2 L1^{-1} L1^{-T}
+    mm(kcap, kcap, S11, kcap, 1, L1i, 1, kcap, Qt, kcap, 0, k_dev);
+    mm(kcap, kcap, Qt, 1, kcap, Qt, kcap, 1, G, kcap, 0, k_dev);
+    mm(kcap, kcap, L1i, kcap, 1, L1i, 1, kcap, P, kcap, 0, k_dev);
+    if (!x.dry) x.check(axpy_dev_launch(lam2, P, kcap, G, kcap, kcap, kcap, x.s), "Q1^T Q1");
+    chol_inv(x, 0, G, kcap, 1, kcap, k_dev, L, kcap, L2i, kcap, 0.0, "chol(Q1^T Q1)", false);
+    // Q = Qt L2^{-T}; W = Q^T S12; Z = L2^{-T} W; T = L1^{-T} Z
+    mm(kcap, kcap, Qt, kcap, 1, L2i, 1, kcap, Q, kcap, 0, k_dev);
+    mm(kcap, n - 1, Q, 1, kcap, S12, ldo, 1, W, ldo, 0, ncol);
+    mm(kcap, n - 1, L2i, 1, kcap, W, ldo, 1, Z, ldo, 0, ncol);
+    mm(kcap, std::min<int64_t>(n - 1, ldt), L1i, 1, kcap, Z, ldo, 1, T, ldt, dtype, ncol);
+    return;
+  }
   chol_inv(x, 1, S11, 1, kcap, kcap, k_dev, nullptr, 0, S11it, kcap, 0.0, "S11 inverse");
-  GemmDesc g{};   // T = S11^{-1} S12, A(i, kk) = S11it[kk][i]
-  g.M = kcap; g.N = std::min<int64_t>(n - 1, ldt); g.K = kcap;
-  g.A = S11it; g.sam = 1; g.sak = kcap;
-  g.B = S12; g.sbk = ldo; g.sbn = 1;
-  g.C = T; g.ldc = ldt;
-  g.in_type = 0; g.acc_type = 0; g.out_type = dtype;
-  g.alpha = 1.0; g.beta = 0.0;
-  g.m_dev = k_dev; g.k_dev = k_dev; g.n_dev = ncol;
-  gemm(x, g);
+  // T = S11^{-1} S12, A(i, kk) = S11it[kk][i]
+  mm(kcap, std::min<int64_t>(n - 1, ldt), S11it, 1, kcap, S12, ldo, 1, T, ldt, dtype, ncol);
 }
 
 // Exact rank deficiency (Section 2.3), relative to the largest initial column
@@ -463,7 +506,7 @@ ColId column_id(const Ctx& x, int dtype, const View& X, const idcur_opts& o, int
   }
   {
     Stage st(x, "trsm");
-    interp_matrix(x, dtype, S, nc, J, nc, kcap, k_out, T, ldt);
+    interp_matrix(x, dtype, S, nc, J, nc, kcap, k_out, T, ldt, o.t_reg);
   }
   return r;
 }
@@ -471,7 +514,7 @@ ColId column_id(const Ctx& x, int dtype, const View& X, const idcur_opts& o, int
 // Row ID of C (m x kcap, row-major ld kcap) with rank k_dev: the full-rank ID of
 // C^T, giving I (m) and Tr (k x (m-k), ldtr); k_out_r receives its rank.
 void row_id_of_c(const Ctx& x, int dtype, const void* C, int64_t m, int kcap, const int* k_dev, int* k_out_r, int* I,
-                 void* Tr, int64_t ldtr) {
+                 void* Tr, int64_t ldtr, double t_reg) {
   const CpqrPlan pl = cpqr_plan((int)esz(dtype), kcap, (int)m, kcap, x.c->num_cus);
   void* rec = x.ar->take(pl.rec_bytes + pl.fin_bytes);
   void* cvals = x.ar->take(pl.cvals_bytes);
@@ -496,7 +539,7 @@ void row_id_of_c(const Ctx& x, int dtype, const void* C, int64_t m, int kcap, co
     x.check(cpqr_launch(dtype, pl, a, x.s), "cpqr(row)");
   }
   Stage st(x, "row_id");
-  interp_matrix(x, dtype, S, m, I, m, kcap, k_out_r, Tr, ldtr);
+  interp_matrix(x, dtype, S, m, I, m, kcap, k_out_r, Tr, ldtr, t_reg);
 }
 
 // U = argmin |U R - V*|_F through the QR of R^T (Cholesky QR twice, FP64):
@@ -630,6 +673,7 @@ void validate(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const voi
   if (opts->sketch != IDCUR_SKETCH_GAUSSIAN && opts->sketch != IDCUR_SKETCH_SRHT)
     fail(ctx, IDCUR_EINVAL, "unknown sketch kind");
   if (opts->u_correct != 0 && opts->u_correct != 1) fail(ctx, IDCUR_EINVAL, "u_correct must be 0 or 1");
+  if (!(opts->t_reg >= 0.0 && opts->t_reg < 1.0)) fail(ctx, IDCUR_EINVAL, "t_reg must be in [0, 1)");
   if (opts->sketch == IDCUR_SKETCH_SRHT && opts->p >= 0 && (int64_t)kcap + opts->p < mr) {
     if (opts->q != 0) fail(ctx, IDCUR_EINVAL, "the structured sketch takes no power steps (q = 0)");
     if (opts->prec != IDCUR_PREC_NATIVE) fail(ctx, IDCUR_EDTYPE, "the structured sketch runs in the native precision");
@@ -679,7 +723,7 @@ void execute(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const void
     Tr = ar.take((size_t)kcap * m * esz(dtype));
     ldtr = m;
   }
-  row_id_of_c(x, dtype, C, m, kcap, out.k_out, out.k_out + 1, out.I, Tr, ldtr);
+  row_id_of_c(x, dtype, C, m, kcap, out.k_out, out.k_out + 1, out.I, Tr, ldtr, o.t_reg);
   if (op == OP_TWO) return;
   // CUR: R = A(I(1:k), :), optional C output, then U
   void* R = out.R;
@@ -933,6 +977,7 @@ void batched_validate(idcur_ctx* ctx, int dtype, const BatchedCall& c, const idc
   const int kcap = o->k > 0 ? o->k : o->kmax;
   if ((int64_t)kcap + o->p > batched_max_sketch()) fail(ctx, IDCUR_EINVAL, "k (kmax) + p must be <= 64");
   if (o->rank_tol < 0 || !std::isfinite(o->rank_tol)) fail(ctx, IDCUR_EINVAL, "rank_tol must be >= 0");
+  if (o->t_reg != 0.0) fail(ctx, IDCUR_EINVAL, "the batched ID forms T by back-substitution (t_reg = 0)");
 }
 
 std::vector<int64_t> batched_key(const BatchedCall& c, const idcur_opts& o) {

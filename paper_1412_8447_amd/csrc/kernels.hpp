@@ -274,6 +274,9 @@ hipError_t pad_square_launch(const double* G, int64_t gr, int64_t gc, int c_host
 hipError_t diag_shift_launch(const double* G, int64_t gr, int64_t gc, int c_host, const int* c_dev, double rel,
                              double* out, hipStream_t stream);
 hipError_t zero2d_launch(double* p, int64_t rows, int64_t cols, int64_t ld, hipStream_t stream);
+// Y += (*s) X, rows x cols row-major FP64, the weight a device scalar.
+hipError_t axpy_dev_launch(const double* s, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t rows,
+                           int64_t cols, hipStream_t stream);
 hipError_t add_gathered_launch(const double* Q, int64_t ldq, const int* J, int ka_host, const int* ka_dev,
                                int kb_host, const int* kb_dev, double* out, int64_t ldo, hipStream_t stream);
 

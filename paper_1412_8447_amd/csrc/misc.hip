@@ -153,6 +153,18 @@ __global__ __launch_bounds__(256) void diag_shift_kernel(const double* G, int64_
   if (threadIdx.x == 0) *out = rel * fmax(fmax(ws[0], ws[1]), fmax(ws[2], ws[3]));
 }
 
+// Y += (*s) X over rows x cols (row-major, leading dimensions ldx, ldy): an
+// update whose weight was computed on the device.
+__global__ void axpy_dev_kernel(const double* s, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t rows,
+                                int64_t cols) {
+  const double w = *s;
+  const int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / cols, j = e % cols;
+    Y[i * ldy + j] += w * X[i * ldx + j];
+  }
+}
+
 __global__ void zero2d_kernel(double* p, int64_t rows, int64_t cols, int64_t ld) {
   const int64_t total = rows * cols;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
@@ -414,6 +426,13 @@ hipError_t pad_square_launch(const double* G, int64_t gr, int64_t gc, int c_host
 hipError_t diag_shift_launch(const double* G, int64_t gr, int64_t gc, int c_host, const int* c_dev, double rel,
                              double* out, hipStream_t stream) {
   hipLaunchKernelGGL(diag_shift_kernel, dim3(1), dim3(256), 0, stream, G, gr, gc, c_host, c_dev, rel, out);
+  return hipGetLastError();
+}
+
+hipError_t axpy_dev_launch(const double* s, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t rows,
+                           int64_t cols, hipStream_t stream) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(axpy_dev_kernel, dim3(grid_for(rows * cols)), dim3(256), 0, stream, s, X, ldx, Y, ldy, rows, cols);
   return hipGetLastError();
 }
 

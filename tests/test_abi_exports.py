@@ -62,7 +62,7 @@ class _Opts(ctypes.Structure):
                 ("rank_tol", ctypes.c_double), ("p", ctypes.c_int32), ("q", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("omega", ctypes.c_void_p), ("prec", ctypes.c_int32),
                 ("norms", ctypes.c_int32), ("sketch", ctypes.c_int32), ("srht_signs", ctypes.c_void_p),
-                ("srht_rows", ctypes.c_void_p), ("u_correct", ctypes.c_int32)]
+                ("srht_rows", ctypes.c_void_p), ("u_correct", ctypes.c_int32), ("t_reg", ctypes.c_double)]
 
 
 def test_opts_default(lib):
@@ -71,7 +71,7 @@ def test_opts_default(lib):
     lib.idcur_opts_default(ctypes.byref(o))
     assert (o.k, o.kmax, o.tol, o.rank_tol, o.p, o.q, o.seed) == (0, 0, 0.0, 0.0, -1, 0, 0)
     assert not o.omega and o.prec == 0 and o.norms == 0
-    assert o.sketch == 0 and not o.srht_signs and not o.srht_rows and o.u_correct == 0
+    assert o.sketch == 0 and not o.srht_signs and not o.srht_rows and o.u_correct == 0 and o.t_reg == 0.0
 
 
 def test_null_context_is_rejected(lib):
