@@ -401,6 +401,7 @@ def main():
     ap.add_argument("--adjoint-only", action="store_true", help="only run the adjoint measurements")
     ap.add_argument("--no-structured", action="store_true", help="skip the structured (Hadamard) sketch measurements")
     ap.add_argument("--no-ucorrect", action="store_true", help="skip the error-corrected U measurement")
+    ap.add_argument("--no-stabilized", action="store_true", help="skip the stabilized-T measurement")
     ap.add_argument("--no-library-gemm", action="store_true",
                     help="skip timing torch's FP32 GEMM on the sketch shape (context for the roofline)")
     ap.add_argument("--batched-only", action="store_true",
@@ -597,6 +598,36 @@ def main():
                                  "u_solve_ms": round(st_c["u_solve"][0] / reps, 4)}
         log("u_corrected", result["u_corrected"])
         del outc
+
+    # the same step with the Tikhonov-stabilized interpolation matrices
+    # (t_reg = 1e-4: both IDs' T by Cholesky QR twice of [S11; lam I])
+    if not args.no_stabilized:
+        t_reg = 1e-4
+        outs = {kk: torch.empty_like(v) for kk, v in out.items()}
+        for _ in range(2):
+            P.cur(A, k, out=outs, sync=False, t_reg=t_reg, **kw)
+        P.sync_status(dev)
+        P.timing_enable(True, dev)
+        reps = max(3, args.steps)
+        e0.record()
+        for _ in range(reps):
+            P.cur(A, k, out=outs, sync=False, t_reg=t_reg, **kw)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_s = e0.elapsed_time(e1) / reps
+        st_s = P.timing_read(dev)
+        P.timing_enable(False, dev)
+        P.sync_status(dev)
+        er = P.cur_error(A, outs["C"], outs["U"], outs["R"], outs["kout"], k).tolist()
+        e_s = math.sqrt(er[0] / er[1])
+        result["stabilized_t"] = {"t_reg": t_reg, "ms_per_step": round(ms_s, 4), "rel_fro_error": e_s,
+                                  "error_ratio_vs_plain_t": round(e_s / e_cur, 4),
+                                  "column_t_ms": round(st_s["trsm"][0] / reps, 4),
+                                  "column_t_ms_plain": round(stages["trsm"][0] / args.steps, 4),
+                                  "row_id_ms": round(st_s["row_id"][0] / reps, 4),
+                                  "row_id_ms_plain": round(stages["row_id"][0] / args.steps, 4)}
+        log("stabilized_t", result["stabilized_t"])
+        del outs
 
     # the structured sketch (subsampled randomized Hadamard), l = 2k, q = 0
     if not args.no_structured:
