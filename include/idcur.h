@@ -154,7 +154,7 @@ idcur_status idcur_sync_status(idcur_ctx* ctx);
  * stage: "omega", "pack", "sketch_gemm" (the sketch / power-step GEMM kernels
  * alone, without their split-K reduction), "orth", "cpqr", "trsm", "gather",
  * "row_id", "u_solve", "error", "backward", "batched", "srht" (the structured
- * sketch kernels). Enabling (or disabling)
+ * sketch kernels), "spmm" (the sparse sketch kernels). Enabling (or disabling)
  * synchronises the stream and clears the accumulated marks. idcur_timing_read
  * synchronises and returns the summed elapsed milliseconds and the number of
  * marks of one stage (host outputs). */
@@ -181,6 +181,26 @@ idcur_status idcur_workspace_bytes(idcur_ctx* ctx, int32_t op, int32_t dtype, in
 idcur_status idcur_id_col(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, const void* A, int64_t lda,
                           const idcur_opts* opts, void* ws, size_t ws_bytes,
                           int32_t* k_out, int32_t* J, void* T, int64_t ldt);
+
+/* Column ID of a sparse A (Algorithm 4 with q = 0; the sparse matrices of
+ * Sections 1 and 3 that motivate the ID and CUR) in compressed sparse column
+ * form: the entries of column j are p = colptr[j] .. colptr[j+1] - 1, stored at
+ * rows rowidx[p] with values vals[p] (any order within a column; repeated rows
+ * add up). The sketch Y = Omega A (l = k + p rows, Omega as for idcur_id_col:
+ * opts->omega l x m row-major, or drawn from opts->seed) reads each stored entry
+ * once; the CPQR and T then run on Y as in idcur_id_col, so the outputs (k_out, J,
+ * T, ldt) have the same meaning. Requires p >= 0 and k (kmax) + p < m, q = 0, the
+ * Gaussian sketch and NATIVE precision; t_reg applies as usual.
+ *   colptr  device int64[n + 1], nondecreasing, 0 <= colptr[j] <= nnz.
+ *   rowidx  device int32[nnz], each in [0, m).   vals  device, dtype, [nnz].
+ * Index values out of range are skipped and raise IDCUR_EINVAL from
+ * idcur_sync_status. All buffers are the caller's; the workspace is sized by
+ * idcur_id_col_csc_workspace_bytes for the same (dtype, m, n, nnz, opts). */
+idcur_status idcur_id_col_csc_workspace_bytes(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, int64_t nnz,
+                                              const idcur_opts* opts /* host */, size_t* bytes /* host out */);
+idcur_status idcur_id_col_csc(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, int64_t nnz, const int64_t* colptr,
+                              const int32_t* rowidx, const void* vals, const idcur_opts* opts /* host */, void* ws,
+                              size_t ws_bytes, int32_t* k_out, int32_t* J, void* T, int64_t ldt);
 
 /* Row ID (remark closing Section 2.3): the column ID of A^T, computed from A in
  * place (no transposed copy). I (device int32[m]) is the row permutation, Tr the

@@ -90,6 +90,10 @@ _lib.idcur_sync_status.argtypes = [_vp]
 _lib.idcur_workspace_bytes.argtypes = [_vp, _i32, _i32, _i64, _i64, ctypes.POINTER(Opts), ctypes.POINTER(_sz)]
 _common = [_vp, _i32, _i64, _i64, _vp, _i64, ctypes.POINTER(Opts), _vp, _sz, _vp]
 _lib.idcur_id_col.argtypes = _common + [_vp, _vp, _i64]
+_lib.idcur_id_col_csc_workspace_bytes.argtypes = [_vp, _i32, _i64, _i64, _i64, ctypes.POINTER(Opts),
+                                                  ctypes.POINTER(_sz)]
+_lib.idcur_id_col_csc.argtypes = [_vp, _i32, _i64, _i64, _i64, _vp, _vp, _vp, ctypes.POINTER(Opts), _vp, _sz, _vp,
+                                  _vp, _vp, _i64]
 _lib.idcur_id_row.argtypes = _common + [_vp, _vp, _i64]
 _lib.idcur_id_two_sided.argtypes = _common + [_vp, _vp, _i64, _vp, _vp, _i64]
 _lib.idcur_cur.argtypes = _common + [_vp, _vp, _vp, _i64, _vp, _i64, _vp, _i64]
@@ -127,10 +131,11 @@ EXPORTED = ("idcur_opts_default", "idcur_create", "idcur_set_stream", "idcur_des
             "idcur_id_error", "idcur_cur_error", "idcur_id_col_backward_workspace_bytes", "idcur_id_col_backward",
             "idcur_sketch", "idcur_id_col_batched_workspace_bytes", "idcur_id_col_batched",
             "idcur_id_col_batched_autotune", "idcur_id_col_batched_set_variant",
-            "idcur_id_col_batched_backward_workspace_bytes", "idcur_id_col_batched_backward")
+            "idcur_id_col_batched_backward_workspace_bytes", "idcur_id_col_batched_backward",
+            "idcur_id_col_csc_workspace_bytes", "idcur_id_col_csc")
 
 STAGES = ("omega", "pack", "sketch_gemm", "orth", "cpqr", "trsm", "gather", "row_id", "u_solve", "error", "backward",
-          "batched", "srht")
+          "batched", "srht", "spmm")
 
 
 class IDCurError(RuntimeError):
@@ -317,6 +322,40 @@ def id_col(A: torch.Tensor, k: int = 0, *, workspace=None, sync: bool = True, **
     if not sync:
         return ColumnID(J, T, -1, kout)
     sync_status(A.device)
+    kk = int(kout[0].item())
+    return ColumnID(J, T[:kk, : n - kk], kk, kout)
+
+
+def id_col_csc(colptr: torch.Tensor, rowidx: torch.Tensor, vals: torch.Tensor, m: int, n: int, k: int = 0, *,
+               workspace=None, sync: bool = True, **kw) -> ColumnID:
+    """Column ID of a sparse m x n matrix in compressed sparse column form
+    (colptr int64[n+1], rowidx int32[nnz], vals float32/float64[nnz], all on one
+    device): the sketch Omega A read entry by entry, then the dense CPQR and T.
+    Keyword options as :func:`make_opts` (p >= 0, q = 0)."""
+    for t, name, dt in ((colptr, "colptr", torch.int64), (rowidx, "rowidx", torch.int32)):
+        if t.dtype != dt or t.dim() != 1 or not t.is_contiguous() or t.device != vals.device:
+            raise IDCurError(EINVAL, f"{name} must be a contiguous 1-D {dt} tensor on the device of vals")
+    if vals.dim() != 1 or not vals.is_contiguous() or colptr.numel() != n + 1 or rowidx.numel() != vals.numel():
+        raise IDCurError(EINVAL, "vals must be contiguous 1-D with rowidx's length; colptr needs n + 1 entries")
+    h = _context(vals.device)
+    omega = kw.get("omega")
+    if omega is not None:
+        _mat(omega, "omega", vals.dtype)
+    o = make_opts(k, **kw)
+    nnz = vals.numel()
+    kcap = o.k if o.k > 0 else o.kmax
+    nb = _sz(0)
+    _check(h, _lib.idcur_id_col_csc_workspace_bytes(h, _dtype_code(vals), m, n, nnz, ctypes.byref(o), ctypes.byref(nb)))
+    ws = workspace if workspace is not None else torch.empty(nb.value, dtype=torch.uint8, device=vals.device)
+    J = torch.empty(n, dtype=torch.int32, device=vals.device)
+    T = torch.empty(max(kcap, 1), max(n, 1), dtype=vals.dtype, device=vals.device)
+    kout = torch.zeros(2, dtype=torch.int32, device=vals.device)
+    _check(h, _lib.idcur_id_col_csc(h, _dtype_code(vals), m, n, nnz, colptr.data_ptr(), rowidx.data_ptr(),
+                                    vals.data_ptr(), ctypes.byref(o), ws.data_ptr(), ws.numel(), kout.data_ptr(),
+                                    J.data_ptr(), T.data_ptr(), max(n, 1)))
+    if not sync:
+        return ColumnID(J, T, -1, kout)
+    sync_status(vals.device)
     kk = int(kout[0].item())
     return ColumnID(J, T[:kk, : n - kk], kk, kout)
 

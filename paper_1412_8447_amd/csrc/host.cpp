@@ -1207,6 +1207,60 @@ idcur_status run(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const 
   }
 }
 
+// Column ID of a sparse A (compressed sparse column form): the sketch
+// Y = Omega A by spmm_csc_kernel (Section 5.1), then the same CPQR and T as the
+// dense path on Y.
+struct Csc {
+  int64_t m, n, nnz;
+  const int64_t* colptr;
+  const int* rowidx;
+  const void* vals;
+};
+
+void validate_csc(idcur_ctx* ctx, int dtype, const Csc& a, const idcur_opts* o) {
+  validate(ctx, OP_COL, dtype, a.m, a.n, nullptr, std::max<int64_t>(a.n, 1), o);
+  if (a.nnz < 0) fail(ctx, IDCUR_EINVAL, "nnz must be >= 0");
+  if (a.n > 0x7fffffff) fail(ctx, IDCUR_EINVAL, "n must be below 2^31");
+  const int kcap = o->k > 0 ? o->k : o->kmax;
+  if (o->p < 0 || (int64_t)kcap + o->p >= a.m)
+    fail(ctx, IDCUR_EINVAL, "the sparse column ID sketches: p >= 0 and k (kmax) + p < m");
+  if (o->q != 0) fail(ctx, IDCUR_EINVAL, "the sparse column ID takes no power steps (q = 0)");
+  if (o->sketch != IDCUR_SKETCH_GAUSSIAN) fail(ctx, IDCUR_EINVAL, "the sparse column ID takes the Gaussian sketch");
+  if (o->prec != IDCUR_PREC_NATIVE) fail(ctx, IDCUR_EDTYPE, "the sparse column ID computes in the dtype");
+}
+
+void execute_csc(idcur_ctx* ctx, int dtype, const Csc& a, const idcur_opts& o, Arena& ar, const Outs& out) {
+  Ctx x{ctx, ctx->stream, ar.dry, &ar};
+  const int kcap = o.k > 0 ? o.k : o.kmax;
+  const int l = kcap + o.p;
+  const int64_t ll = round_up(l, 4);
+  void* Omt = ar.take((size_t)a.m * ll * esz(dtype));
+  void* Yt = ar.take((size_t)a.n * ll * esz(dtype));
+  SpmmDesc d{};
+  d.m = a.m; d.n = a.n; d.nnz = a.nnz;
+  d.colptr = a.colptr; d.rowidx = a.rowidx; d.vals = a.vals;
+  d.Omt = Omt; d.ldom = ll; d.l = l; d.Yt = Yt; d.ldo = ll;
+  d.splits = spmm_pick_splits(a.n, a.nnz, x.c->num_cus);
+  d.status = x.c->dstatus;
+  void* part = d.splits > 1 ? ar.take(spmm_part_bytes(d, (int)esz(dtype))) : nullptr;
+  if (!x.dry) {
+    {
+      Stage st(x, "omega");
+      if (o.omega)
+        x.check(copy2d_launch(dtype, l, a.m, o.omega, a.m, 1, Omt, 1, ll, x.s), "omega copy");
+      else
+        x.check(gaussian_launch(dtype, l, a.m, o.seed, 0, Omt, 1, ll, x.s), "omega");
+    }
+    Stage st(x, "spmm");
+    x.check(spmm_csc_launch(dtype, d, part, x.s), "sparse sketch");
+  }
+  // Y (l x n) is the sketch: the dense column ID on it, without sketching again
+  idcur_opts o2 = o;
+  o2.p = -1;
+  const View Y{Yt, l, a.n, 1, ll};
+  column_id(x, dtype, Y, o2, out.k_out, out.J, out.T, out.ldt, false);
+}
+
 }  // namespace
 }  // namespace idcur
 
@@ -1302,6 +1356,50 @@ idcur_status idcur_workspace_bytes(idcur_ctx* ctx, int32_t op, int32_t dtype, in
     out.ldt = out.ldtr = std::max(m, n);
     execute(ctx, op, dtype, m, n, nullptr, n, *opts, dry, out);
     *bytes = dry.off + 256;
+    return IDCUR_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  }
+}
+
+idcur_status idcur_id_col_csc_workspace_bytes(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, int64_t nnz,
+                                              const idcur_opts* opts, size_t* bytes) {
+  try {
+    if (!bytes) fail(ctx, IDCUR_EINVAL, "bytes is NULL");
+    const Csc a{m, n, nnz, nullptr, nullptr, nullptr};
+    validate_csc(ctx, dtype, a, opts);
+    Arena dry;
+    Outs out;
+    out.ldt = n;
+    execute_csc(ctx, dtype, a, *opts, dry, out);
+    *bytes = dry.off + 256;
+    return IDCUR_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  }
+}
+
+idcur_status idcur_id_col_csc(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, int64_t nnz, const int64_t* colptr,
+                              const int32_t* rowidx, const void* vals, const idcur_opts* opts, void* ws, size_t ws_bytes,
+                              int32_t* k_out, int32_t* J, void* T, int64_t ldt) {
+  try {
+    const Csc a{m, n, nnz, colptr, rowidx, vals};
+    validate_csc(ctx, dtype, a, opts);
+    if (!colptr || (nnz > 0 && (!rowidx || !vals))) fail(ctx, IDCUR_EINVAL, "colptr, rowidx and vals are required");
+    if (!k_out || !J || !T) fail(ctx, IDCUR_EINVAL, "k_out, J and T are required");
+    const int kcap = opts->k > 0 ? opts->k : opts->kmax;
+    if (ldt < (opts->k > 0 ? n - kcap : n)) fail(ctx, IDCUR_EINVAL, "ldt too small");
+    Outs out;
+    out.k_out = k_out; out.J = J; out.T = T; out.ldt = ldt;
+    Arena dry;
+    execute_csc(ctx, dtype, a, *opts, dry, out);
+    if (!ws || ws_bytes < dry.off) fail(ctx, IDCUR_EWORKSPACE, "workspace missing or too small");
+    Arena ar;
+    ar.dry = false;
+    ar.base = static_cast<char*>(ws);
+    ar.cap = ws_bytes;
+    hipcheck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    execute_csc(ctx, dtype, a, *opts, ar, out);
     return IDCUR_OK;
   } catch (const Fail& f) {
     return f.code;

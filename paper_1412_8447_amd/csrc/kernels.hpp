@@ -274,6 +274,27 @@ hipError_t pad_square_launch(const double* G, int64_t gr, int64_t gc, int c_host
 hipError_t diag_shift_launch(const double* G, int64_t gr, int64_t gc, int c_host, const int* c_dev, double rel,
                              double* out, hipStream_t stream);
 hipError_t zero2d_launch(double* p, int64_t rows, int64_t cols, int64_t ld, hipStream_t stream);
+// Sketch of a sparse m x n matrix in compressed sparse column form:
+// Y^T (n x l, row-major, ld ldo; columns l..ldo-1 zero) with
+// Y^T(j, :) = sum over the entries p of column j (colptr[j] <= p < colptr[j+1])
+// of vals[p] Omega(:, rowidx[p])^T, Omega^T given m x ldom row-major. splits > 1
+// (a multiple of 4) takes spmm_part_bytes of partial rows in `part`. Column
+// pointers outside [0, nnz] or decreasing, and row indices outside [0, m),
+// set ST_BADINDEX (the offending entries are skipped).
+struct SpmmDesc {
+  int64_t m, n, nnz;
+  const int64_t* colptr;
+  const int* rowidx;
+  const void* vals;
+  const void* Omt; int64_t ldom;
+  int l;
+  void* Yt; int64_t ldo;
+  int splits;
+  int* status;
+};
+int spmm_pick_splits(int64_t n, int64_t nnz, int num_cus);
+size_t spmm_part_bytes(const SpmmDesc& d, int esize);
+hipError_t spmm_csc_launch(int dtype, const SpmmDesc& d, void* part, hipStream_t stream);
 // Y += (*s) X, rows x cols row-major FP64, the weight a device scalar.
 hipError_t axpy_dev_launch(const double* s, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t rows,
                            int64_t cols, hipStream_t stream);

@@ -1,0 +1,126 @@
+// Sketch of a sparse matrix in compressed sparse column form (Section 5.1, eq.
+// (Y=OmegaA), for the sparse matrices that motivate the ID and CUR): for each
+// column j, Y^T(j, :) = sum over the stored A(i, j) of A(i, j) Omega(:, i)^T.
+// Omega^T is stored m x ldom row-major, so every stored entry reads one
+// contiguous row of it: a wave takes a column (or a split of its entries) and
+// its 64 lanes read consecutive elements of each row, 64 R sketch rows at a
+// time. Splits of a column's entries write partial rows that a second kernel
+// adds in split order, so the result does not depend on scheduling.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace idcur {
+namespace {
+
+template <typename T>
+struct SpArgs {
+  int64_t m, n, nnz;
+  const int64_t* colptr;
+  const int* rowidx;
+  const T* vals;
+  const T* Omt; int64_t ldom;
+  int l;
+  T* out; int64_t ldo;   // split s writes rows s*n .. (s+1)*n - 1 (ld ldo)
+  int splits;
+  int* status;
+};
+
+template <typename T, int R>
+__global__ __launch_bounds__(256) void spmm_csc_kernel(SpArgs<T> a) {
+  const int lane = threadIdx.x & 63;
+  const int wpg = blockDim.x >> 6;                       // waves per workgroup
+  const int s = blockIdx.y * wpg + (threadIdx.x >> 6);   // this wave's split
+  const int64_t j = blockIdx.x;
+  if (s >= a.splits) return;   // whole wave; the kernel has no barrier
+  int64_t p0 = a.colptr[j], p1 = a.colptr[j + 1];
+  if (p0 < 0 || p1 > a.nnz || p0 > p1) {
+    if (lane == 0) set_status(a.status, ST_BADINDEX);
+    p0 = p1 = 0;
+  }
+  const int64_t len = p1 - p0;
+  const int64_t q0 = p0 + len * s / a.splits, q1 = p0 + len * (s + 1) / a.splits;
+  T* o = a.out + ((int64_t)s * a.n + j) * a.ldo;
+  for (int c0 = 0; c0 < a.ldo; c0 += 64 * R) {
+    T acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = T(0);
+    for (int64_t p = q0; p < q1; ++p) {
+      const int i = a.rowidx[p];   // the same for every lane
+      const T v = a.vals[p];
+      if (i < 0 || i >= a.m) {
+        if (lane == 0) set_status(a.status, ST_BADINDEX);
+        continue;
+      }
+      const T* om = a.Omt + (int64_t)i * a.ldom;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int c = c0 + lane + 64 * r;
+        if (c < a.l) acc[r] += v * om[c];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int c = c0 + lane + 64 * r;
+      if (c < a.ldo) o[c] = c < a.l ? acc[r] : T(0);
+    }
+  }
+}
+
+// Y^T(j, c) = sum over splits s (in order) of part[s](j, c).
+template <typename T>
+__global__ void spmm_reduce_kernel(const T* part, int splits, int64_t n, int64_t ldo, T* Yt) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * ldo) return;
+  T acc = T(0);
+  for (int q = 0; q < splits; ++q) acc += part[(int64_t)q * n * ldo + e];
+  Yt[e] = acc;
+}
+
+template <typename T>
+hipError_t launch_t(const SpmmDesc& d, void* part, hipStream_t stream) {
+  SpArgs<T> a{};
+  a.m = d.m; a.n = d.n; a.nnz = d.nnz;
+  a.colptr = d.colptr; a.rowidx = d.rowidx; a.vals = static_cast<const T*>(d.vals);
+  a.Omt = static_cast<const T*>(d.Omt); a.ldom = d.ldom;
+  a.l = d.l; a.ldo = d.ldo; a.splits = d.splits; a.status = d.status;
+  a.out = d.splits > 1 ? static_cast<T*>(part) : static_cast<T*>(d.Yt);
+  const int wpg = d.splits >= 4 ? 4 : 1;
+  const dim3 grid((unsigned)d.n, (unsigned)ceil_div(d.splits, wpg));
+  const dim3 block(64 * wpg);
+  if (d.l <= 64) hipLaunchKernelGGL((spmm_csc_kernel<T, 1>), grid, block, 0, stream, a);
+  else if (d.l <= 128) hipLaunchKernelGGL((spmm_csc_kernel<T, 2>), grid, block, 0, stream, a);
+  else hipLaunchKernelGGL((spmm_csc_kernel<T, 4>), grid, block, 0, stream, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || d.splits == 1) return e;
+  const int64_t tot = d.n * d.ldo;
+  hipLaunchKernelGGL((spmm_reduce_kernel<T>), dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, stream,
+                     static_cast<const T*>(part), d.splits, d.n, d.ldo, static_cast<T*>(d.Yt));
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// Splits of each column's entries: enough waves to fill the chip (32 per CU)
+// over few columns, each split about 64 entries or more; 1 when the columns
+// alone fill it.
+int spmm_pick_splits(int64_t n, int64_t nnz, int num_cus) {
+  const int64_t want = ceil_div(32LL * std::max(num_cus, 1), std::max<int64_t>(n, 1));
+  const int64_t most = std::max<int64_t>(1, nnz / (64 * std::max<int64_t>(n, 1)));
+  int64_t s = std::min(want, most);
+  if (s <= 1) return 1;
+  s = std::min<int64_t>(round_up(s, 4), 256);
+  return (int)s;
+}
+
+size_t spmm_part_bytes(const SpmmDesc& d, int esize) {
+  return d.splits > 1 ? (size_t)d.splits * d.n * d.ldo * esize : 0;
+}
+
+hipError_t spmm_csc_launch(int dtype, const SpmmDesc& d, void* part, hipStream_t stream) {
+  if (d.l < 1 || d.ldo < d.l || d.ldom < d.l || d.splits < 1 || (d.splits > 1 && d.splits % 4)) return hipErrorInvalidValue;
+  if (d.n <= 0) return hipSuccess;
+  if (d.n > 0x7fffffff) return hipErrorInvalidValue;
+  return dtype == 0 ? launch_t<double>(d, part, stream) : launch_t<float>(d, part, stream);
+}
+
+}  // namespace idcur

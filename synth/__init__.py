@@ -245,3 +245,30 @@ CONFIGS = {
     "mixed_50000x20000_k500": Config("mixed_50000x20000_k500", 50000, 20000, 500, 20, 1, "f32", "exp:80"),
     "diff_fp32_8192x4096_k128": Config("diff_fp32_8192x4096_k128", 8192, 4096, 128, 10, 0, "f32", "pow:1.5"),
 }
+
+
+def sparse_nonneg_csc(m: int, n: int, terms: int, xdens: float, ydens: float, decay: float, seed: int,
+                      dtype=np.float64):
+    """A sparse non-negative m x n matrix built from rank-1 terms, in compressed
+    sparse column form: A = sum_t w_t x_t y_t^T with x_t (m) and y_t (n) sparse,
+    their nonzeros uniform in (0, 1] at densities xdens and ydens, and weights
+    w_t = exp(-t / decay). Returns (colptr int64[n+1], rowidx int32[nnz] sorted
+    within each column, vals[nnz]) as NumPy arrays."""
+    import scipy.sparse as sp
+    g = rng(seed)
+    X = sp.random(m, terms, density=xdens, format="csc", random_state=g,
+                  data_rvs=lambda k: 1.0 - g.random(k))
+    Y = sp.random(n, terms, density=ydens, format="csc", random_state=g,
+                  data_rvs=lambda k: 1.0 - g.random(k))
+    W = sp.diags(np.exp(-np.arange(terms, dtype=np.float64) / decay))
+    A = (X @ W @ Y.T).tocsc()
+    A.sort_indices()
+    return (A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data.astype(dtype))
+
+
+def csc_to_dense(colptr, rowidx, vals, m: int, n: int) -> np.ndarray:
+    """The dense m x n matrix of a compressed sparse column triple (repeated rows
+    add up), by scipy."""
+    import scipy.sparse as sp
+    return sp.csc_matrix((np.asarray(vals, dtype=np.float64), np.asarray(rowidx), np.asarray(colptr)),
+                         shape=(m, n)).toarray()

@@ -1,0 +1,149 @@
+"""GPU parity of the column ID of a sparse matrix in compressed sparse column
+form (Algorithm 4 with q = 0, the sketch read entry by entry) against the FP64
+oracle on the densified matrix with the same Omega: pivots identical on clear
+gaps, T within tolerance; empty columns, unsorted and repeated row entries,
+exact rank deficiency, out-of-range indices, and the full 300000 x 300 workload
+against the dense GPU path."""
+import numpy as np
+import pytest
+
+import synth
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1412_8447_amd as P  # noqa: E402
+from gpu_helpers import say, to_dev, clear_prefix  # noqa: E402
+
+
+def _dev_csc(cp, ri, v, dtype):
+    return (torch.as_tensor(cp, dtype=torch.int64, device="cuda"), torch.as_tensor(ri, dtype=torch.int32, device="cuda"),
+            torch.as_tensor(v, dtype=dtype, device="cuda"))
+
+
+@pytest.mark.parametrize("m,n,k,p", [(3000, 120, 20, 10), (2049, 257, 33, 7)])
+def test_sparse_col_id_fp64(m, n, k, p):
+    say(f"sparse col id fp64 {m}x{n} k={k} p={p}")
+    cp, ri, v = synth.sparse_nonneg_csc(m, n, 40, 0.02, 0.3, 6.0, seed=m + n)
+    A = synth.csc_to_dense(cp, ri, v, m, n)
+    om = synth.gaussian(k + p, m, seed=k)
+    ref = oracle.id_col(A, k, omega=om)
+    assert clear_prefix(ref.qr.gaps, 1e-10) == k, "test input should have clear gaps"
+    got = P.id_col_csc(*_dev_csc(cp, ri, v, torch.float64), m, n, k, p=p, omega=to_dev(om, torch.float64))
+    assert got.k == k
+    assert np.array_equal(got.J.cpu().numpy(), ref.J)
+    T = got.T.cpu().numpy()
+    assert np.abs(T - ref.T).max() <= 1e-9 * max(1.0, np.abs(ref.T).max())
+
+
+def test_sparse_col_id_fp32():
+    m, n, k, p = 3000, 120, 20, 10
+    say(f"sparse col id fp32 {m}x{n} k={k}")
+    cp, ri, v = synth.sparse_nonneg_csc(m, n, 40, 0.02, 0.3, 6.0, seed=7)
+    v = v.astype(np.float32)
+    A = synth.csc_to_dense(cp, ri, v, m, n)
+    om = synth.gaussian(k + p, m, seed=8).astype(np.float32)
+    ref = oracle.id_col(A, k, omega=om.astype(np.float64))
+    got = P.id_col_csc(*_dev_csc(cp, ri, v, torch.float32), m, n, k, p=p, omega=to_dev(om, torch.float32))
+    c = clear_prefix(ref.qr.gaps, 1e-4)
+    assert np.array_equal(got.J.cpu().numpy()[:c], ref.J[:c])
+    if c == k:
+        T = got.T.cpu().numpy().astype(np.float64)
+        assert np.abs(T - ref.T).max() <= 2e-3 * max(1.0, np.abs(ref.T).max())
+    e_g = oracle.e_id(A, got.J.cpu().numpy().astype(np.int64), got.T.cpu().numpy().astype(np.float64))
+    e_o = oracle.e_id(A, ref.J, ref.T)
+    assert e_g <= 1.02 * e_o
+
+
+def test_sparse_irregular_storage():
+    """Empty columns, rows unsorted within a column and repeated rows (which add
+    up), against the densified matrix."""
+    m, n, k, p = 400, 60, 8, 6
+    g = np.random.default_rng(11)
+    cols = []
+    for j in range(n):
+        if j % 7 == 3:
+            cols.append((np.zeros(0, np.int32), np.zeros(0)))
+            continue
+        nz = int(g.integers(1, 40))
+        r = g.integers(0, m, size=nz).astype(np.int32)
+        r = np.concatenate([r, r[: nz // 3]])          # repeats
+        vals = g.standard_normal(r.size)
+        perm = g.permutation(r.size)                    # unsorted
+        cols.append((r[perm], vals[perm]))
+    cp = np.zeros(n + 1, np.int64)
+    cp[1:] = np.cumsum([c[0].size for c in cols])
+    ri = np.concatenate([c[0] for c in cols]).astype(np.int32)
+    v = np.concatenate([c[1] for c in cols])
+    A = synth.csc_to_dense(cp, ri, v, m, n)
+    om = synth.gaussian(k + p, m, seed=12)
+    ref = oracle.id_col(A, k, omega=om)
+    got = P.id_col_csc(*_dev_csc(cp, ri, v, torch.float64), m, n, k, p=p, omega=to_dev(om, torch.float64))
+    c = clear_prefix(ref.qr.gaps, 1e-10)
+    assert c >= 1
+    assert np.array_equal(got.J.cpu().numpy()[:c], ref.J[:c])
+    e_g = oracle.e_id(A, got.J.cpu().numpy().astype(np.int64), got.T.cpu().numpy())
+    assert abs(e_g / oracle.e_id(A, ref.J, ref.T) - 1) <= 1e-8
+
+
+def test_sparse_exact_rank_deficiency():
+    """Rank 40 matrix, k = 45: the ID stops where the oracle stops."""
+    m, n, k, p = 3000, 120, 45, 10
+    cp, ri, v = synth.sparse_nonneg_csc(m, n, 40, 0.02, 0.3, 6.0, seed=13)
+    A = synth.csc_to_dense(cp, ri, v, m, n)
+    om = synth.gaussian(k + p, m, seed=14)
+    ref = oracle.id_col(A, k, omega=om)
+    got = P.id_col_csc(*_dev_csc(cp, ri, v, torch.float64), m, n, k, p=p, omega=to_dev(om, torch.float64))
+    say(f"  rank produced gpu {got.k} oracle {ref.k}")
+    assert got.k == ref.k < k
+
+
+def test_sparse_bad_indices_and_arguments():
+    m, n = 100, 10
+    cp = np.arange(0, 2 * n + 1, 2, dtype=np.int64)
+    ri = np.tile(np.array([5, 7], np.int32), n)
+    v = np.ones(2 * n)
+    ri_bad = ri.copy()
+    ri_bad[3] = m + 5                                  # past the last row: skipped, reported
+    with pytest.raises(P.IDCurError):
+        P.id_col_csc(*_dev_csc(cp, ri_bad, v, torch.float64), m, n, 2, p=3, seed=1)
+    cp_bad = cp.copy()
+    cp_bad[4] = 10 ** 6                                 # past nnz: column treated as empty, reported
+    with pytest.raises(P.IDCurError):
+        P.id_col_csc(*_dev_csc(cp_bad, ri, v, torch.float64), m, n, 2, p=3, seed=1)
+    with pytest.raises(P.IDCurError):                   # no sketch requested
+        P.id_col_csc(*_dev_csc(cp, ri, v, torch.float64), m, n, 2)
+    with pytest.raises(P.IDCurError):                   # power steps are not taken
+        P.id_col_csc(*_dev_csc(cp, ri, v, torch.float64), m, n, 2, p=3, q=1)
+    # the good call still works after the reported ones
+    got = P.id_col_csc(*_dev_csc(cp, ri, v, torch.float64), m, n, 2, p=3, seed=1)
+    assert got.k >= 1
+
+
+def test_sparse_full_size_fp32_against_dense_path():
+    """300000 x 300 (14.8M stored entries), k = 50, p = 10: the sparse path's ID
+    error within 1.02x of the dense GPU path's on the densified matrix with the
+    same Omega."""
+    m, n, k, p = 300000, 300, 50, 10
+    say(f"sparse col id full size fp32 {m}x{n} k={k}")
+    cp, ri, v = synth.sparse_nonneg_csc(m, n, 60, 0.01, 0.3, 8.0, seed=5, dtype=np.float32)
+    colptr, rowidx, vals = _dev_csc(cp, ri, v, torch.float32)
+    Ad = torch.zeros(n, m, dtype=torch.float32, device="cuda")      # A^T, then transposed
+    cols = torch.repeat_interleave(torch.arange(n, device="cuda"), colptr[1:] - colptr[:-1])
+    Ad.index_put_((cols, rowidx.long()), vals, accumulate=True)
+    A = Ad.t().contiguous()
+    del Ad
+    om = P.gaussian(k + p, m, seed=21)
+    s = P.id_col_csc(colptr, rowidx, vals, m, n, k, p=p, omega=om)
+    d = P.id_col(A, k, p=p, omega=om)
+    es = P.id_error(A, s.J, s.T, s.kout, k).cpu().numpy()
+    ed = P.id_error(A, d.J, d.T, d.kout, k).cpu().numpy()
+    rs, rd = np.sqrt(es[0] / es[1]), np.sqrt(ed[0] / ed[1])
+    say(f"  rel fro error sparse {rs:.4e} dense {rd:.4e}; leading pivots equal "
+        f"{int((s.J[:k] == d.J[:k]).all().item())}")
+    assert s.k == d.k == k
+    assert rs <= 1.02 * rd
