@@ -318,6 +318,79 @@ def bench_adjoint(args, P, synth, torch, dev, reps=10):
     return out
 
 
+def bench_sparse(args, P, synth, torch, dev):
+    """Column ID of a sparse 300000 x 300 matrix of rank-1 terms (compressed
+    sparse column form, 14.8M stored entries), k = 50, p = 10, q = 0: the sparse
+    path's step and its sketch kernel's bytes, against the dense path on the
+    densified matrix with the same Omega."""
+    import ctypes
+    m, n, k, p = 300000, 300, 50, 10
+    l = k + p
+    import numpy as np
+    cp, ri, v = synth.sparse_nonneg_csc(m, n, 60, 0.01, 0.3, 8.0, seed=args.seed + 11, dtype=np.float32)
+    colptr = torch.as_tensor(cp, dtype=torch.int64, device=dev)
+    rowidx = torch.as_tensor(ri, dtype=torch.int32, device=dev)
+    vals = torch.as_tensor(v, dtype=torch.float32, device=dev)
+    nnz = vals.numel()
+    om = P.gaussian(l, m, seed=args.seed + 12)
+    o = P.make_opts(k, p=p, omega=om)
+    nb = ctypes.c_size_t(0)
+    P._check(P._context(vals.device), P._lib.idcur_id_col_csc_workspace_bytes(
+        P._context(vals.device), 1, m, n, nnz, ctypes.byref(o), ctypes.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(3, args.steps)
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        P.sync_status(dev)
+        P.timing_enable(True, dev)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        st = P.timing_read(dev)
+        P.timing_enable(False, dev)
+        P.sync_status(dev)
+        return e0.elapsed_time(e1) / reps, st
+
+    ms_s, st_s = timed(lambda: P.id_col_csc(colptr, rowidx, vals, m, n, k, p=p, omega=om, workspace=ws, sync=False))
+    res_s = P.id_col_csc(colptr, rowidx, vals, m, n, k, p=p, omega=om, workspace=ws)
+    Ad = torch.zeros(n, m, dtype=torch.float32, device=dev)
+    cols = torch.repeat_interleave(torch.arange(n, device=dev), colptr[1:] - colptr[:-1])
+    Ad.index_put_((cols, rowidx.long()), vals, accumulate=True)
+    A = Ad.t().contiguous()
+    del Ad, cols
+    ms_d, st_d = timed(lambda: P.id_col(A, k, p=p, omega=om, sync=False))
+    res_d = P.id_col(A, k, p=p, omega=om)
+    es = P.id_error(A, res_s.J, res_s.T, res_s.kout, k).tolist()
+    ed = P.id_error(A, res_d.J, res_d.T, res_d.kout, k).tolist()
+    sp_ms, sp_n = st_s["spmm"]
+    sp_avg = sp_ms / max(sp_n, 1)
+    ll = (l + 3) // 4 * 4
+    nbytes = nnz * (4 + 4) + (n + 1) * 8 + m * l * 4 + n * ll * 4
+    gbs = nbytes / (sp_avg * 1e-3) / 1e9
+    out = {"workload": f"sparse FP32 {m}x{n}, {nnz} stored entries (60 rank-1 terms, x density 0.01, "
+                       f"y density 0.3), k={k}, p={p}, q=0",
+           "ms_per_id": round(ms_s, 4),
+           "stages_ms_per_id": {sname: round(vv[0] / reps, 4) for sname, vv in st_s.items() if vv[1]},
+           "rel_fro_error": math.sqrt(es[0] / es[1]),
+           "dense_path": {"ms_per_id": round(ms_d, 4), "rel_fro_error": math.sqrt(ed[0] / ed[1]),
+                          "sketch_gemm_ms": round(st_d["sketch_gemm"][0] / reps, 4) if "sketch_gemm" in st_d else None},
+           "leading_pivots_identical": int(bool((res_s.J[:k] == res_d.J[:k]).all().item())),
+           "sketch_kernel": {"avg_launch_ms": round(sp_avg, 4), "launches": sp_n,
+                             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                                          "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
+                                          "bytes_per_launch": nbytes,
+                                          "note": "algorithmic bytes: the stored entries and column pointers, "
+                                                  "Omega^T and Y^T once each"}}}
+    log("sparse", out)
+    del A
+    return out
+
+
 def bench_structured(args, P, synth, torch, dev, A, k):
     """The structured sketch (subsampled randomized Hadamard, the real form of
     Section 5.2's) on the bench matrix with l = 2k and q = 0: the sketch
@@ -402,6 +475,7 @@ def main():
     ap.add_argument("--no-structured", action="store_true", help="skip the structured (Hadamard) sketch measurements")
     ap.add_argument("--no-ucorrect", action="store_true", help="skip the error-corrected U measurement")
     ap.add_argument("--no-stabilized", action="store_true", help="skip the stabilized-T measurement")
+    ap.add_argument("--no-sparse", action="store_true", help="skip the sparse column ID measurement")
     ap.add_argument("--no-library-gemm", action="store_true",
                     help="skip timing torch's FP32 GEMM on the sketch shape (context for the roofline)")
     ap.add_argument("--batched-only", action="store_true",
@@ -632,6 +706,10 @@ def main():
     # the structured sketch (subsampled randomized Hadamard), l = 2k, q = 0
     if not args.no_structured:
         result["structured_sketch"] = bench_structured(args, P, synth, torch, dev, A, k)
+
+    # column ID of a sparse matrix (compressed sparse columns)
+    if not args.no_sparse:
+        result["sparse"] = bench_sparse(args, P, synth, torch, dev)
 
     # gradient of the ID reconstruction loss (single matrix and 256 blocks)
     if not args.no_adjoint:

@@ -4,7 +4,7 @@
 // Omega^T is stored m x ldom row-major, so every stored entry reads one
 // contiguous row of it: a wave takes a column (or a split of its entries) and
 // its 64 lanes read consecutive elements of each row, 64 R sketch rows at a
-// time. Splits of a column's entries write partial rows that a second kernel
+// time, eight rows in flight. Splits of a column's entries write partial rows that a second kernel
 // adds in split order, so the result does not depend on scheduling.
 #include "common.hpp"
 #include "kernels.hpp"
@@ -40,22 +40,43 @@ __global__ __launch_bounds__(256) void spmm_csc_kernel(SpArgs<T> a) {
   const int64_t len = p1 - p0;
   const int64_t q0 = p0 + len * s / a.splits, q1 = p0 + len * (s + 1) / a.splits;
   T* o = a.out + ((int64_t)s * a.n + j) * a.ldo;
+  // 64 entries at a time: lane t loads entry t (coalesced), then their row
+  // indices and values are broadcast one by one and eight rows of Omega^T are
+  // in flight together; entries are added in storage order.
+  bool bad = false;
   for (int c0 = 0; c0 < a.ldo; c0 += 64 * R) {
     T acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = T(0);
-    for (int64_t p = q0; p < q1; ++p) {
-      const int i = a.rowidx[p];   // the same for every lane
-      const T v = a.vals[p];
-      if (i < 0 || i >= a.m) {
-        if (lane == 0) set_status(a.status, ST_BADINDEX);
-        continue;
+    for (int64_t pb = q0; pb < q1; pb += 64) {
+      const int64_t pp = pb + lane;
+      const bool in = pp < q1;
+      int iv = in ? a.rowidx[pp] : 0;
+      T vv = in ? a.vals[pp] : T(0);
+      if (iv < 0 || iv >= a.m) {   // skipped and reported
+        bad = true;
+        iv = 0;
+        vv = T(0);
       }
-      const T* om = a.Omt + (int64_t)i * a.ldom;
+      const int cnt = (int)min<int64_t>(64, q1 - pb);   // the same for every lane
+      for (int u0 = 0; u0 < cnt; u0 += 8) {
+        T x[8][R];
+        T w[8];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int c = c0 + lane + 64 * r;
-        if (c < a.l) acc[r] += v * om[c];
+        for (int u = 0; u < 8; ++u) {   // entries past cnt carry value 0 and row 0
+          const int i = __shfl(iv, u0 + u, 64);
+          w[u] = __shfl(vv, u0 + u, 64);
+          const T* om = a.Omt + (int64_t)i * a.ldom;
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const int c = c0 + lane + 64 * r;
+            x[u][r] = c < a.l ? om[c] : T(0);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int r = 0; r < R; ++r) acc[r] += w[u] * x[u][r];
       }
     }
 #pragma unroll
@@ -64,6 +85,7 @@ __global__ __launch_bounds__(256) void spmm_csc_kernel(SpArgs<T> a) {
       if (c < a.ldo) o[c] = c < a.l ? acc[r] : T(0);
     }
   }
+  if (bad) set_status(a.status, ST_BADINDEX);
 }
 
 // Y^T(j, c) = sum over splits s (in order) of part[s](j, c).
