@@ -40,3 +40,30 @@ def test_config_floors():
     assert abs(s[50] / s[0] - np.exp(-5.0)) < 1e-15
     c2 = synth.CONFIGS["rand_fp32_20000x10000_k200"]
     assert abs(c2.frobenius_floor() - 1.955e-4) < 2e-6
+
+
+def test_sparse_nonneg_csc_structure_and_densify():
+    """The sparse generator gives a valid compressed-sparse-column triple
+    (nondecreasing pointers, sorted in-range rows, non-negative values), its rank
+    is at most the number of terms, and csc_to_dense agrees with an entry-by-
+    entry loop, repeated rows adding up."""
+    m, n, terms = 500, 40, 12
+    cp, ri, v = synth.sparse_nonneg_csc(m, n, terms, 0.05, 0.4, 4.0, seed=3)
+    assert cp[0] == 0 and cp[-1] == ri.size == v.size and np.all(np.diff(cp) >= 0)
+    assert ri.min() >= 0 and ri.max() < m and v.min() > 0
+    for j in range(n):
+        assert np.all(np.diff(ri[cp[j]:cp[j + 1]]) > 0)
+    D = synth.csc_to_dense(cp, ri, v, m, n)
+    assert np.linalg.matrix_rank(D) <= terms
+    # an irregular triple with a repeated row, against a loop
+    cp2 = np.array([0, 3, 3, 5], np.int64)
+    ri2 = np.array([4, 1, 4, 0, 2], np.int32)
+    v2 = np.array([1.0, 2.0, 3.0, -1.0, 0.5])
+    E = np.zeros((6, 3))
+    for j in range(3):
+        for q in range(cp2[j], cp2[j + 1]):
+            E[ri2[q], j] += v2[q]
+    assert np.array_equal(synth.csc_to_dense(cp2, ri2, v2, 6, 3), E)
+    assert E[4, 0] == 4.0
+    a = synth.sparse_nonneg_csc(m, n, terms, 0.05, 0.4, 4.0, seed=3)
+    assert all(np.array_equal(x, y) for x, y in zip(a, (cp, ri, v)))
