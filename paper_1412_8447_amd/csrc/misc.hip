@@ -61,6 +61,27 @@ __global__ void copy2d_kernel(int64_t rows, int64_t cols, const T* in, int64_t s
   }
 }
 
+// out(r, c) = in(r, c) with in's rows and out's columns contiguous (a
+// transpose): 32 x 32 tiles through LDS, so reads and writes are both coalesced.
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_kernel(int64_t rows, int64_t cols, const T* in, int64_t sir, T* out,
+                                                        int64_t soc) {
+  __shared__ T tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+  for (int k = 0; k < 32; k += 8) {
+    const int64_t r = r0 + ty + k, c = c0 + tx;
+    if (r < rows && c < cols) tile[ty + k][tx] = in[r * sir + c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 32; k += 8) {
+    const int64_t c = c0 + ty + k, r = r0 + tx;
+    if (r < rows && c < cols) out[r + c * soc] = tile[tx][ty + k];
+  }
+}
+
 template <typename T, typename TO>
 __global__ void gather_cols_kernel(int64_t m, const T* A, int64_t lda, const int* idx, int k_host, const int* k_dev,
                                    TO* out, int64_t ldo) {
@@ -275,6 +296,17 @@ hipError_t gaussian_launch(int dtype, int64_t rows, int64_t cols, uint64_t seed,
 hipError_t copy2d_launch(int dtype, int64_t rows, int64_t cols, const void* in, int64_t sir, int64_t sic, void* out,
                          int64_t sor, int64_t soc, hipStream_t stream) {
   if (rows <= 0 || cols <= 0) return hipSuccess;
+  const int64_t gx = ceil_div(cols, 32), gy = ceil_div(rows, 32);
+  if (sic == 1 && sor == 1 && rows > 1 && cols > 1 && gx <= 0x7fffffff && gy <= 65535) {
+    const dim3 grid((unsigned)gx, (unsigned)gy);
+    if (dtype == 1)
+      hipLaunchKernelGGL(transpose_kernel<float>, grid, dim3(256), 0, stream, rows, cols,
+                         static_cast<const float*>(in), sir, static_cast<float*>(out), soc);
+    else
+      hipLaunchKernelGGL(transpose_kernel<double>, grid, dim3(256), 0, stream, rows, cols,
+                         static_cast<const double*>(in), sir, static_cast<double*>(out), soc);
+    return hipGetLastError();
+  }
   const unsigned g = grid_for(rows * cols);
   if (dtype == 1)
     hipLaunchKernelGGL(copy2d_kernel<float>, dim3(g), dim3(256), 0, stream, rows, cols, static_cast<const float*>(in), sir,
