@@ -387,19 +387,26 @@ __global__ __launch_bounds__(kThreads) void cpqr_kernel(CpqrArgs a) {
     cstore(a.fin + g * 16, sel + 1);
   }
   __syncthreads();
-  int before = 0;
+  int before = 0, ftmo = 0;
+  if (tid == 0) sh_flags[3] = 0;
+  __syncthreads();
   if (tid < g) {
     long spins = 0;
     int vfin = cload(a.fin + tid * 16);
     while (vfin == 0) {
       __builtin_amdgcn_s_sleep(1);
-      if (++spins > kSpinLimit) break;
+      if (++spins > kSpinLimit) { ftmo = 1; break; }
       vfin = cload(a.fin + tid * 16);
     }
     before = vfin > 0 ? vfin - 1 : 0;
   }
+  if (ftmo) atomicOr(&sh_flags[3], 1);
   const double bsum = block_sum((double)before, red);
-  if (tid == 0) {
+  if (sh_flags[3]) {
+    // a count never arrived: the positions would be wrong, so leave J alone
+    // and report the time-out
+    if (tid == 0) set_status(a.status, ST_TIMEOUT);
+  } else if (tid == 0) {
     int pos = kout + (c0 - (int)bsum);
     for (int c = 0; c < ncl; ++c)
       if (act[c]) {
@@ -427,11 +434,17 @@ static size_t cpqr_lds_bytes(int cols_per_wg, int lpad, int kmax, bool in_lds) {
   return b;
 }
 
+// Kernel choice: the register-slab kernel when the columns fit in the
+// registers of at most one workgroup per CU, else the blocked kernel (short
+// form when its panel of reflectors fits in LDS, else tall), else the
+// unblocked slab kernel below. IDCUR_CPQR_SLAB selects a kernel for testing:
+// 1 the blocked kernel (its own form), 2 its tall form, 3 the unblocked one.
 CpqrPlan cpqr_plan(int dtype_size, int l, int n, int kmax, int num_cus) {
   CpqrPlan p{};
   p.reg_cfg = -1;
-  const char* force_slab = getenv("IDCUR_CPQR_SLAB");
-  if (!(force_slab && force_slab[0] == '1')) {
+  const char* fs = getenv("IDCUR_CPQR_SLAB");
+  const int force = (fs && fs[0] >= '1' && fs[0] <= '3') ? fs[0] - '0' : 0;
+  if (force == 0) {
     int G = 0, cpw = 0;
     const int cfg = cpqr_reg_pick(dtype_size, l, n, num_cus, &G, &cpw);
     if (cfg >= 0) {
@@ -449,6 +462,11 @@ CpqrPlan cpqr_plan(int dtype_size, int l, int n, int kmax, int num_cus) {
       return p;
     }
   }
+  if (force != 3) {
+    CpqrPlan b = p;
+    if (cpqr_blk_plan(b, dtype_size, l, n, kmax, num_cus, force == 2 ? 2 : 0) > 0) return b;
+  }
+  p.blk = 0;
   p.G = (int)std::max(1, std::min(num_cus, n));
   p.cols_per_wg = (int)ceil_div(n, p.G);
   p.lpad = (int)round_up(std::max(l, 1), 4) + (dtype_size == 4 ? 1 : 0);
@@ -475,6 +493,7 @@ hipError_t cpqr_launch(int dtype, const CpqrPlan& p, CpqrArgs a, hipStream_t str
   a.lpad = p.lpad;
   a.cols_per_wg = p.cols_per_wg;
   a.lanes_per_col = p.lanes_per_col;
+  if (p.blk > 0) return cpqr_blk_launch(dtype, p, a, stream);
   if (p.reg_cfg >= 0) {
     // exchanged words carry the publish index: clear what an earlier call left
     hipError_t e = zero_launch(a.cvals, p.cvals_bytes, stream);

@@ -1,5 +1,7 @@
 // Host side of the register-slab CPQR (kernel in cpqr_reg_kernel.hpp; the FP32
 // and FP64 instantiations are compiled in cpqr_reg_f32.hip and cpqr_reg_f64.hip).
+#include <cstdlib>
+
 #include "cpqr_reg_kernel.hpp"
 
 namespace idcur {
@@ -9,10 +11,13 @@ const void* cpqr_reg_fn_f32(int cfg);
 const void* cpqr_reg_fn_f64(int cfg);
 
 int cpqr_reg_pick(int dtype_size, int l, int n, int num_cus, int* G, int* cols_per_wg) {
+  const char* force = getenv("IDCUR_CPQR_REGCFG");
+  const int forced = force ? atoi(force) : -1;
   for (int i = 0; i < kNumRegCfgs; ++i) {
     const RegCfg c = kRegCfgs[i];
+    if (forced >= 0 && i != forced) continue;
     if (c.R * c.RPL < l) continue;
-    if (c.NC * c.RPL * dtype_size / 4 > 128) continue;
+    if (c.NC * c.RPL * dtype_size / 4 > (dtype_size == 4 ? kRegSlabCap<float> : kRegSlabCap<double>)) continue;
     const int cp = (kRT / c.R) * c.NC;
     const int64_t g = ceil_div(n, cp);
     if (g > num_cus || g < 1) continue;

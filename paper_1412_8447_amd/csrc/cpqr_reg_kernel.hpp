@@ -663,26 +663,38 @@ __global__ __launch_bounds__(kRT) void cpqr_reg_kernel(CpqrArgs a) {
     for (int cl = 0; cl < ncl; ++cl) sel += act_s[cl] ? 0 : 1;
     cstore(a.fin + g * 16, sel + 1);
   }
-  int before = 0;
+  int before = 0, ftmo = 0;
   if (tid < g) {
     long spins = 0;
     int vfin = cload(a.fin + tid * 16);
     while (vfin == 0) {
       __builtin_amdgcn_s_sleep(1);
-      if (++spins > kSpinLimit) break;
+      if (++spins > kSpinLimit) { ftmo = 1; break; }
       vfin = cload(a.fin + tid * 16);
     }
     before = vfin > 0 ? vfin - 1 : 0;
   }
+  const int ftmo_w = __any(ftmo) ? 1 : 0;
   // workgroup sum of `before` (integers: any order is exact)
   int bsum = before;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) bsum += __shfl_xor(bsum, o, 64);
-  if (lane == 0) x_t[wv] = bsum;
+  if (lane == 0) {
+    x_t[wv] = bsum;
+    p_i[wv] = ftmo_w;
+  }
   __syncthreads();
   bsum = 0;
-  for (int q = 0; q < kRW; ++q) bsum += x_t[q];
-  if (tid == 0) {
+  int fin_tmo = 0;
+  for (int q = 0; q < kRW; ++q) {
+    bsum += x_t[q];
+    fin_tmo |= p_i[q];
+  }
+  if (fin_tmo) {
+    // a count never arrived: the positions would be wrong, so leave J alone
+    // and report the time-out
+    if (tid == 0) set_status(a.status, ST_TIMEOUT);
+  } else if (tid == 0) {
     int pos = kout + (c0 - bsum);
     for (int cl = 0; cl < ncl; ++cl)
       if (act_s[cl]) {
@@ -707,13 +719,21 @@ constexpr RegCfg kRegCfgs[] = {{16, 8, 1}, {16, 16, 1}, {16, 8, 2}, {16, 13, 2},
                                {16, 8, 5}, {16, 13, 5}, {16, 14, 5}, {16, 16, 5},
                                {16, 8, 6}, {16, 13, 6}, {16, 14, 6}, {16, 16, 6}, {16, 16, 8},
                                {64, 16, 1}, {64, 16, 2}, {64, 16, 4}, {64, 16, 8},
-                               {64, 32, 1}, {64, 32, 2}, {64, 32, 4}};
+                               {64, 32, 1}, {64, 32, 2}, {64, 32, 4},
+                               // sketch heights up to 528 / 576 rows (e.g. 520 x 20000): the
+                               // slab takes up to 180 registers per lane, part of it in AGPRs
+                               {16, 33, 3}, {16, 33, 4}, {16, 33, 5},
+                               {64, 9, 12}, {64, 9, 16}, {64, 9, 20}};
 constexpr int kNumRegCfgs = sizeof(kRegCfgs) / sizeof(kRegCfgs[0]);
+// slab registers per lane (4-byte units): FP32 slabs up to 180 (the compiler
+// keeps the excess in AGPRs, no scratch), FP64 slabs up to 128
+template <typename T>
+constexpr int kRegSlabCap = sizeof(T) == 4 ? 180 : 128;
 
 template <typename T, int I>
 const void* reg_kernel_ptr() {
   constexpr RegCfg c = kRegCfgs[I];
-  if constexpr (c.NC * c.RPL * (int)sizeof(T) / 4 > 128) return nullptr;
+  if constexpr (c.NC * c.RPL * (int)sizeof(T) / 4 > kRegSlabCap<T>) return nullptr;
   else return (const void*)cpqr_reg_kernel<T, c.R, c.RPL, c.NC>;
 }
 

@@ -37,6 +37,9 @@ struct CpqrArgs {
   int lpad;               // set by cpqr_launch
   int cols_per_wg;        // set by cpqr_launch
   int lanes_per_col;      // set by cpqr_launch
+  int nb;                 // blocked kernel: panel width (set by cpqr_launch)
+  int rpw;                // blocked kernel, tall form: rows per workgroup
+  int vch;                // blocked kernel, tall form: rows of v staged in LDS
 };
 
 struct CpqrPlan {
@@ -44,7 +47,9 @@ struct CpqrPlan {
   int cols_per_wg;
   int lpad;
   int lanes_per_col;
-  int reg_cfg;        // >= 0: register-slab kernel configuration; -1: LDS/global slab kernel
+  int reg_cfg;        // >= 0: register-slab kernel configuration; -1: blocked or slab kernel
+  int blk;            // blocked kernel: 1 short form, 2 tall form; 0: not used
+  int nb, rpw, vch;   // blocked kernel geometry
   bool in_lds;
   size_t lds_bytes;
   size_t rec_bytes, cvals_bytes, fin_bytes, gslab_bytes;
@@ -52,6 +57,10 @@ struct CpqrPlan {
 
 CpqrPlan cpqr_plan(int dtype_size, int l, int n, int kmax, int num_cus);
 hipError_t cpqr_launch(int dtype, const CpqrPlan& p, CpqrArgs a, hipStream_t stream);
+// blocked kernel (cpqr_blk.hip): fills p and returns its form (1 short, 2 tall)
+// or 0 when the shape does not fit; force 1 / 2 restricts it to one form
+int cpqr_blk_plan(CpqrPlan& p, int esz, int l, int n, int kmax, int num_cus, int force);
+hipError_t cpqr_blk_launch(int dtype, const CpqrPlan& p, CpqrArgs a, hipStream_t stream);
 // register-slab variant (cpqr_reg.hip): configuration index or -1 when the
 // shape does not fit; sets the grid size and the columns per workgroup
 int cpqr_reg_pick(int dtype_size, int l, int n, int num_cus, int* G, int* cols_per_wg);
