@@ -24,6 +24,7 @@ Decompositions"):
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 from dataclasses import dataclass
@@ -162,6 +163,19 @@ def _context(device: torch.device) -> ctypes.c_void_p:
     h = _ctx[idx]
     _lib.idcur_set_stream(h, _vp(torch.cuda.current_stream(idx).cuda_stream))
     return h
+
+
+@atexit.register
+def _teardown() -> None:
+    """Destroy the contexts (status words, pooled events) at interpreter exit,
+    after the work queued on their streams has finished."""
+    for idx, h in list(_ctx.items()):
+        try:
+            _lib.idcur_sync_status(h)
+            _lib.idcur_destroy(h)
+        except Exception:  # pragma: no cover - best effort at exit
+            pass
+        _ctx.pop(idx, None)
 
 
 def _check(h, st: int) -> None:

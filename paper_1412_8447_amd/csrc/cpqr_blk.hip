@@ -4,7 +4,7 @@
 //
 // One persistent cooperative launch of G <= #CUs workgroups (512 threads).
 // Workgroup g owns the columns [c0, c1) of a global column-major copy of Y (the
-// slab, rows padded to a multiple of 16) and updates only those. Reflectors are
+// slab, rows padded to a multiple of 32) and updates only those. Reflectors are
 // applied in panels of nb (<= 32) steps, in the compact form that LAPACK's
 // blocked pivoted QR uses: with Y0 the trailing matrix at the panel start, V the
 // panel's reflectors and F (n x nb) the accumulated products,
@@ -30,8 +30,11 @@
 // its data stores before storing the tag, and thread t of every workgroup polls
 // workgroup t's tag (the grid barrier). Every workgroup reduces the records in
 // the same order, so all take the same pivot, stopping decision and reflector.
-// Memory shared between workgroups (records, the slab, v and V) is accessed with
-// device-coherent (sc1) loads and stores only.
+// Records, v and V are written and read with device-coherent (sc1) accesses. A
+// workgroup reads and writes its own slab columns with ordinary accesses and,
+// after loading them and after each panel update, writes its XCD's L2 back
+// before it next publishes; other workgroups read a winning column with
+// device-coherent loads.
 //
 // Pivots: largest norm, ties to the smallest column index. Householder sign:
 // alpha = -sgn(x0)|x|. S is written by original column index; J lists the
@@ -63,6 +66,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base, uint32_
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
 constexpr int kSC1 = 16;   // device-coherent cache policy
+constexpr int kOWN = 0;    // default policy: a workgroup's own slab columns
 // an offset past every resource used here (all are below 2^31 bytes), also
 // after adding the 16 bytes of a second load
 constexpr uint32_t kOOB = 0x80000000u;
@@ -74,26 +78,26 @@ template <>
 struct Quad<float> {
   using acc = f32x4;
   __device__ static void load(__amdgpu_buffer_rsrc_t rs, uint32_t off, double (&x)[4]) {
-    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, kSC1);
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, kOWN);
 #pragma unroll
     for (int e = 0; e < 4; ++e) x[e] = (double)__uint_as_float(v[e]);
   }
   __device__ static void load_raw(__amdgpu_buffer_rsrc_t rs, uint32_t off, float (&x)[4]) {
-    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, kSC1);
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, kOWN);
 #pragma unroll
     for (int e = 0; e < 4; ++e) x[e] = __uint_as_float(v[e]);
   }
   __device__ static acc load_acc(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
-    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, kSC1);
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, kOWN);
     return acc{__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]), __uint_as_float(v[3])};
   }
   __device__ static void store_acc(__amdgpu_buffer_rsrc_t rs, uint32_t off, acc a) {
     const u32x4 v{__float_as_uint(a[0]), __float_as_uint(a[1]), __float_as_uint(a[2]), __float_as_uint(a[3])};
-    __builtin_amdgcn_raw_buffer_store_b128(v, rs, (int)off, 0, kSC1);
+    __builtin_amdgcn_raw_buffer_store_b128(v, rs, (int)off, 0, kOWN);
   }
   __device__ static void store(__amdgpu_buffer_rsrc_t rs, uint32_t off, const float (&x)[4]) {
     const u32x4 v{__float_as_uint(x[0]), __float_as_uint(x[1]), __float_as_uint(x[2]), __float_as_uint(x[3])};
-    __builtin_amdgcn_raw_buffer_store_b128(v, rs, (int)off, 0, kSC1);
+    __builtin_amdgcn_raw_buffer_store_b128(v, rs, (int)off, 0, kOWN);
   }
   __device__ static f32x4 mfma(float a, float b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
   // the 16 x 16 accumulator tile: lane L holds rows 4 (L / 16) + r, r = 0..3,
@@ -110,8 +114,8 @@ template <>
 struct Quad<double> {
   using acc = f64x4;
   __device__ static void load(__amdgpu_buffer_rsrc_t rs, uint32_t off, double (&x)[4]) {
-    const u32x4 v0 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, kSC1);
-    const u32x4 v1 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(off + 16u), 0, kSC1);
+    const u32x4 v0 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, kOWN);
+    const u32x4 v1 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(off + 16u), 0, kOWN);
     x[0] = __hiloint2double((int)v0[1], (int)v0[0]);
     x[1] = __hiloint2double((int)v0[3], (int)v0[2]);
     x[2] = __hiloint2double((int)v1[1], (int)v1[0]);
@@ -126,7 +130,7 @@ struct Quad<double> {
   __device__ static void store2(__amdgpu_buffer_rsrc_t rs, uint32_t off, double a, double b) {
     const u32x4 v{(unsigned)__double2loint(a), (unsigned)__double2hiint(a), (unsigned)__double2loint(b),
                   (unsigned)__double2hiint(b)};
-    __builtin_amdgcn_raw_buffer_store_b128(v, rs, (int)off, 0, kSC1);
+    __builtin_amdgcn_raw_buffer_store_b128(v, rs, (int)off, 0, kOWN);
   }
   __device__ static void store_acc(__amdgpu_buffer_rsrc_t rs, uint32_t off, acc a) {
     store2(rs, off, a[0], a[1]);
@@ -140,13 +144,13 @@ struct Quad<double> {
   // the FP64 accumulator tile: lane L holds rows L / 16 + 4 r, r = 0..3, of
   // column L % 16 (four 8-byte accesses)
   __device__ static double ld8(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, kSC1);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)(off + 4u), 0, kSC1);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, kOWN);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)(off + 4u), 0, kOWN);
     return __hiloint2double((int)hi, (int)lo);
   }
   __device__ static void st8(__amdgpu_buffer_rsrc_t rs, uint32_t off, double x) {
-    __builtin_amdgcn_raw_buffer_store_b32((unsigned)__double2loint(x), rs, (int)off, 0, kSC1);
-    __builtin_amdgcn_raw_buffer_store_b32((unsigned)__double2hiint(x), rs, (int)(off + 4u), 0, kSC1);
+    __builtin_amdgcn_raw_buffer_store_b32((unsigned)__double2loint(x), rs, (int)off, 0, kOWN);
+    __builtin_amdgcn_raw_buffer_store_b32((unsigned)__double2hiint(x), rs, (int)(off + 4u), 0, kOWN);
   }
   __device__ static acc tile_load(__amdgpu_buffer_rsrc_t rs, uint32_t e0, int kq) {
     acc a;
@@ -159,6 +163,44 @@ struct Quad<double> {
     for (int r = 0; r < 4; ++r) st8(rs, e0 == kOOB ? kOOB : (e0 + kq + 4u * r) * 8u, a[r]);
   }
 };
+
+// four consecutive elements written by other workgroups (device-coherent)
+template <typename T>
+__device__ __forceinline__ void load4_sc1(__amdgpu_buffer_rsrc_t rs, uint32_t off, double (&x)[4]) {
+  if constexpr (sizeof(T) == 4) {
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, kSC1);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) x[e] = (double)__uint_as_float(v[e]);
+  } else {
+    const u32x4 v0 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, kSC1);
+    const u32x4 v1 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(off + 16u), 0, kSC1);
+    x[0] = __hiloint2double((int)v0[1], (int)v0[0]);
+    x[1] = __hiloint2double((int)v0[3], (int)v0[2]);
+    x[2] = __hiloint2double((int)v1[1], (int)v1[0]);
+    x[3] = __hiloint2double((int)v1[3], (int)v1[2]);
+  }
+}
+template <typename T>
+__device__ __forceinline__ T load1_sc1(__amdgpu_buffer_rsrc_t rs, uint32_t idx) {
+  if constexpr (sizeof(T) == 4) {
+    return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)(idx * 4u), 0, kSC1));
+  } else {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)(idx * 8u), 0, kSC1);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)(idx * 8u + 4u), 0, kSC1);
+    return __hiloint2double((int)hi, (int)lo);
+  }
+}
+
+// Make this workgroup's slab stores visible to the other XCDs: every thread
+// waits for its stores, then one thread writes the XCD's L2 back (agent-scope
+// release). Readers in other workgroups use device-coherent loads, and no
+// 128-byte line holds data of two workgroups (columns start on 128-byte
+// boundaries), so they never see a stale copy.
+__device__ __forceinline__ void publish_slab() {
+  wait_all_mem();
+  __syncthreads();
+  if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+}
 
 // ---------------------------------------------------------------------------
 // Block reductions over kBT threads (fixed order: identical inputs give
@@ -210,7 +252,7 @@ __global__ __launch_bounds__(kBT) void cpqr_blk_kernel(CpqrArgs a) {
   kmax = min(kmax, min(l, n));
   const int c0 = (int)(((int64_t)g * n) / G), c1 = (int)(((int64_t)(g + 1) * n) / G);
   const int ncl = c1 - c0;
-  const int lpad = a.lpad;          // multiple of 16, >= l_host
+  const int lpad = a.lpad;          // multiple of 32, >= l_host
   const int cpw = a.cols_per_wg;    // >= ncl, multiple of 16
   const int nb = a.nb;              // panel width (<= kNBMax)
   const int nbp = ((nb + 3) & ~3) + 1;   // F row stride (odd; entries past nb stay zero)
@@ -302,7 +344,7 @@ __global__ __launch_bounds__(kBT) void cpqr_blk_kernel(CpqrArgs a) {
     dots[c] = 0.0;
   }
   for (int e = tid; e < cpw * nbp; e += kBT) F[e] = (T)0;
-  wait_all_mem();
+  publish_slab();
   __syncthreads();
 
   // squared norms of rows [rb, l) of the local columns (all active ones, or the
@@ -341,6 +383,7 @@ __global__ __launch_bounds__(kBT) void cpqr_blk_kernel(CpqrArgs a) {
     if (ib > 0) {
       const int nks = (ib + 3) >> 2;
       const int kq = lane >> 4, li = lane & 15;
+      const __amdgpu_buffer_rsrc_t rs_V = rsrc(Vglob, (uint32_t)((size_t)nb * lpad * sizeof(T)));
       for (int rt = (j >> 4) + wv; rt < (lpad >> 4); rt += kBW) {
         const int r = rt * 16 + li;
         T av[kNBMax / 4];
@@ -349,7 +392,7 @@ __global__ __launch_bounds__(kBT) void cpqr_blk_kernel(CpqrArgs a) {
           const int s = 4 * ks + kq;
           T x = (T)0;
           if (ks < nks && s < ib && r >= j && r < l) {
-            if constexpr (TALL) x = -cload(Vglob + (size_t)s * lpad + r);
+            if constexpr (TALL) x = -load1_sc1<T>(rs_V, (uint32_t)(s * lpad + r));
             else x = -Vl[(size_t)s * lpad + r];
           }
           av[ks] = x;
@@ -364,7 +407,7 @@ __global__ __launch_bounds__(kBT) void cpqr_blk_kernel(CpqrArgs a) {
           Quad<T>::tile_store(rs_wg, e0, kq, acc);
         }
       }
-      wait_all_mem();
+      publish_slab();
       __syncthreads();
     }
     norms(j, a.norms_exact != 0);
@@ -481,14 +524,7 @@ __global__ __launch_bounds__(kBT) void cpqr_blk_kernel(CpqrArgs a) {
       for (int r = tid; r < lpad; r += kBT) {
         T yt = (T)0;
         if (r >= j && r < l) {
-          double y;
-          if constexpr (sizeof(T) == 4)
-            y = (double)__uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs_p, r * 4, 0, kSC1));
-          else {
-            const uint32_t lo = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs_p, r * 8, 0, kSC1);
-            const uint32_t hi = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs_p, r * 8 + 4, 0, kSC1);
-            y = __hiloint2double((int)hi, (int)lo);
-          }
+          double y = (double)load1_sc1<T>(rs_p, (uint32_t)r);
           for (int s = 0; s < i; ++s) y -= (double)Vl[(size_t)s * lpad + r] * Fp[s];
           yt = (T)y;
           ss += (double)yt * (double)yt;
@@ -505,14 +541,7 @@ __global__ __launch_bounds__(kBT) void cpqr_blk_kernel(CpqrArgs a) {
       T yt = (T)0;
       if (tid < r1 - r0) {
         if (r >= j) {
-          double y;
-          if constexpr (sizeof(T) == 4)
-            y = (double)__uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs_p, r * 4, 0, kSC1));
-          else {
-            const uint32_t lo = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs_p, r * 8, 0, kSC1);
-            const uint32_t hi = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs_p, r * 8 + 4, 0, kSC1);
-            y = __hiloint2double((int)hi, (int)lo);
-          }
+          double y = (double)load1_sc1<T>(rs_p, (uint32_t)r);
           for (int s = 0; s < i; ++s) y -= (double)Vl[(size_t)s * rpw + tid] * Fp[s];
           yt = (T)y;
           ss = (double)yt * (double)yt;
@@ -660,11 +689,12 @@ __global__ __launch_bounds__(kBT) void cpqr_blk_kernel(CpqrArgs a) {
       sweep(Vl + (size_t)i * lpad, 0, j4 >> 2, nq);
     } else {
       const __amdgpu_buffer_rsrc_t rs_v = rsrc(vglob, (uint32_t)((size_t)lpad * sizeof(T)));
+      // v was stored by every workgroup with device-coherent stores: read it the same way
       for (int cs = j4; cs < lpad; cs += vch) {
         const int ce = min(lpad, cs + vch);
         for (int qd = (cs >> 2) + tid; qd < (ce >> 2); qd += kBT) {
           double x[4];
-          Quad<T>::load(rs_v, (uint32_t)(4 * qd * sizeof(T)), x);
+          load4_sc1<T>(rs_v, (uint32_t)(4 * qd * sizeof(T)), x);
 #pragma unroll
           for (int e2 = 0; e2 < 4; ++e2) {
             const int r = 4 * qd + e2;
@@ -691,9 +721,8 @@ __global__ __launch_bounds__(kBT) void cpqr_blk_kernel(CpqrArgs a) {
       const T fT = (T)(tau * (dots[cl] - corr));
       F[cl * nbp + i] = fT;
       dots[cl] = 0.0;
-      T* yjp = slab + (size_t)(c0 + cl) * lpad + j;
       const T sT = (T)(y0j[cl] - sr - vj * (double)fT);
-      cstore(yjp, sT);
+      slab[(size_t)(c0 + cl) * lpad + j] = sT;   // a row of S: read back by this workgroup only
       const double s = (double)sT;
       const double nc = nu2[cl];
       if (nc > 0.0) {
@@ -723,7 +752,7 @@ __global__ __launch_bounds__(kBT) void cpqr_blk_kernel(CpqrArgs a) {
       const int r = (int)(q / ncl), cl = (int)(q % ncl);
       const int st = sel[cl];
       T v;
-      if (st == -1 || r < st) v = cload(slab + (size_t)(c0 + cl) * lpad + r);
+      if (st == -1 || r < st) v = slab[(size_t)(c0 + cl) * lpad + r];
       else v = (r == st) ? (T)salpha[cl] : (T)0;
       S[(int64_t)r * a.ldS + c0 + cl] = v;
     }
@@ -791,7 +820,8 @@ int cpqr_blk_plan(CpqrPlan& p, int esz, int l, int n, int kmax, int num_cus, int
   const size_t budget = 152 * 1024;
   const int G = std::max(1, std::min(num_cus, n));
   const int cpw = (int)round_up(ceil_div(n, G), 16);
-  const int lpad = (int)round_up(std::max(l, 1), 16);
+  // columns start on 128-byte lines (see publish_slab)
+  const int lpad = (int)round_up(std::max(l, 1), 32);
   if ((size_t)cpw * lpad * esz >= ((size_t)1 << 31)) return 0;
   if ((size_t)lpad * esz >= ((size_t)1 << 31)) return 0;
   p.G = G;
