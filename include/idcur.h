@@ -182,6 +182,22 @@ idcur_status idcur_id_col(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, c
                           const idcur_opts* opts, void* ws, size_t ws_bytes,
                           int32_t* k_out, int32_t* J, void* T, int64_t ldt);
 
+/* idcur_id_col without a workspace, for callers that cannot allocate device
+ * memory (code under stream capture into a graph, serving loops, harnesses that
+ * forbid allocation): the scratch memory is a fixed 64 MiB device array inside
+ * the library, one per GPU, held until the process ends; the call itself
+ * allocates nothing (no device or event allocation; stage timers are not taken).
+ * Arguments, outputs and results are those of idcur_id_col on the same inputs.
+ * Returns IDCUR_EWORKSPACE, with the size in idcur_last_error, when
+ * idcur_workspace_bytes(IDCUR_OP_ID_COL, ...) exceeds 64 MiB (an FP32
+ * 2400 x 1600, k = 100, p = 10, q = 1 column ID needs 28 MB and fits; the FP32
+ * 20000 x 10000, k = 200 one needs 339 MB and is refused). Every call on one
+ * GPU uses the same array and leaves its contents behind: calls that overlap on
+ * one GPU (different streams or threads) race and must be serialised by the
+ * caller. */
+idcur_status idcur_id_col_noalloc(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+                                  const idcur_opts* opts, int32_t* k_out, int32_t* J, void* T, int64_t ldt);
+
 /* Column ID of a sparse A (Algorithm 4 with q = 0; the sparse matrices of
  * Sections 1 and 3 that motivate the ID and CUR) in compressed sparse column
  * form: the entries of column j are p = colptr[j] .. colptr[j+1] - 1, stored at

@@ -91,6 +91,8 @@ _lib.idcur_sync_status.argtypes = [_vp]
 _lib.idcur_workspace_bytes.argtypes = [_vp, _i32, _i32, _i64, _i64, ctypes.POINTER(Opts), ctypes.POINTER(_sz)]
 _common = [_vp, _i32, _i64, _i64, _vp, _i64, ctypes.POINTER(Opts), _vp, _sz, _vp]
 _lib.idcur_id_col.argtypes = _common + [_vp, _vp, _i64]
+_lib.idcur_id_col_noalloc.argtypes = [_vp, _i32, _i64, _i64, _vp, _i64, ctypes.POINTER(Opts), _vp, _vp, _vp, _i64]
+_lib.idcur_id_col_noalloc.restype = ctypes.c_int
 _lib.idcur_id_col_csc_workspace_bytes.argtypes = [_vp, _i32, _i64, _i64, _i64, ctypes.POINTER(Opts),
                                                   ctypes.POINTER(_sz)]
 _lib.idcur_id_col_csc.argtypes = [_vp, _i32, _i64, _i64, _i64, _vp, _vp, _vp, ctypes.POINTER(Opts), _vp, _sz, _vp,
@@ -133,7 +135,7 @@ EXPORTED = ("idcur_opts_default", "idcur_create", "idcur_set_stream", "idcur_des
             "idcur_sketch", "idcur_id_col_batched_workspace_bytes", "idcur_id_col_batched",
             "idcur_id_col_batched_autotune", "idcur_id_col_batched_set_variant",
             "idcur_id_col_batched_backward_workspace_bytes", "idcur_id_col_batched_backward",
-            "idcur_id_col_csc_workspace_bytes", "idcur_id_col_csc")
+            "idcur_id_col_csc_workspace_bytes", "idcur_id_col_csc", "idcur_id_col_noalloc")
 
 STAGES = ("omega", "pack", "sketch_gemm", "orth", "cpqr", "trsm", "gather", "row_id", "u_solve", "error", "backward",
           "batched", "srht", "spmm")
@@ -333,6 +335,30 @@ def id_col(A: torch.Tensor, k: int = 0, *, workspace=None, sync: bool = True, **
     kout = torch.zeros(2, dtype=torch.int32, device=A.device)
     _check(h, _lib.idcur_id_col(h, _dtype_code(A), m, n, A.data_ptr(), A.stride(0), ctypes.byref(o), ws.data_ptr(),
                                 ws.numel(), kout.data_ptr(), J.data_ptr(), T.data_ptr(), max(ldt, 1)))
+    if not sync:
+        return ColumnID(J, T, -1, kout)
+    sync_status(A.device)
+    kk = int(kout[0].item())
+    return ColumnID(J, T[:kk, : n - kk], kk, kout)
+
+
+def id_col_noalloc(A: torch.Tensor, k: int = 0, *, out=None, sync: bool = True, **kw) -> ColumnID:
+    """Column ID through idcur_id_col_noalloc: no workspace, the library's fixed
+    scratch array instead. ``out`` = (J, T, kout) reuses caller buffers (J int32[n],
+    T of A's dtype with n columns and at least k (kmax) rows, kout int32[2])."""
+    h = _prep(A, kw.get("omega"))
+    o = make_opts(k, **kw)
+    m, n = A.shape
+    kcap = o.k if o.k > 0 else o.kmax
+    if out is None:
+        J = torch.empty(n, dtype=torch.int32, device=A.device)
+        T = torch.empty(max(kcap, 1), max(n, 1), dtype=A.dtype, device=A.device)
+        kout = torch.zeros(2, dtype=torch.int32, device=A.device)
+    else:
+        J, T, kout = out
+    ldt = T.shape[1]
+    _check(h, _lib.idcur_id_col_noalloc(h, _dtype_code(A), m, n, A.data_ptr(), A.stride(0), ctypes.byref(o),
+                                        kout.data_ptr(), J.data_ptr(), T.data_ptr(), max(ldt, 1)))
     if not sync:
         return ColumnID(J, T, -1, kout)
     sync_status(A.device)

@@ -23,6 +23,9 @@ struct idcur_ctx {
   int device = 0;
   int num_cus = 256;
   int* dstatus = nullptr;
+  // device address of the file-scope scratch array on this context's device
+  // (the workspace of idcur_id_col_noalloc), set once at context creation
+  void* noalloc_scratch = nullptr;
   std::string err;
   // per-stage timers (HIP events on the stream), enabled by idcur_timing_enable
   bool timing = false;
@@ -1276,6 +1279,13 @@ void idcur_opts_default(idcur_opts* o) {
   o->norms = IDCUR_NORMS_DOWNDATE;
 }
 
+// Workspace of idcur_id_col_noalloc: a fixed device array, one copy per GPU the
+// library runs on, held until the process ends. In host code the name stands for
+// a host-side symbol, not a device address: hipGetSymbolAddress gives the device
+// address, once per device, at context creation.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 idcur_status idcur_create(idcur_ctx** out, void* stream) {
   if (!out) return IDCUR_EINVAL;
   *out = nullptr;
@@ -1287,6 +1297,11 @@ idcur_status idcur_create(idcur_ctx** out, void* stream) {
   c->num_cus = prop.multiProcessorCount;
   if (hipMalloc(&c->dstatus, 64) != hipSuccess) { delete c; return IDCUR_EHIP; }
   if (hipMemset(c->dstatus, 0, 64) != hipSuccess) { (void)hipFree(c->dstatus); delete c; return IDCUR_EHIP; }
+  if (hipGetSymbolAddress(&c->noalloc_scratch, HIP_SYMBOL(scratch)) != hipSuccess || !c->noalloc_scratch) {
+    (void)hipFree(c->dstatus);
+    delete c;
+    return IDCUR_EHIP;
+  }
   *out = c;
   return IDCUR_OK;
 }
@@ -1412,6 +1427,31 @@ idcur_status idcur_id_col(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, c
   Outs o;
   o.k_out = k_out; o.J = J; o.T = T; o.ldt = ldt;
   return run(ctx, OP_COL, dtype, m, n, A, lda, opts, ws, ws_bytes, o);
+}
+
+idcur_status idcur_id_col_noalloc(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+                                  const idcur_opts* opts, int32_t* k_out, int32_t* J, void* T, int64_t ldt) {
+  if (!ctx) return IDCUR_EINVAL;
+  if (!ctx->noalloc_scratch) {
+    ctx->err = "no scratch address for this device";
+    return IDCUR_EHIP;
+  }
+  size_t need = 0;
+  const idcur_status st = idcur_workspace_bytes(ctx, IDCUR_OP_ID_COL, dtype, m, n, opts, &need);
+  if (st != IDCUR_OK) return st;
+  if (need > kNoAllocScratchBytes) {
+    ctx->err = "problem needs " + std::to_string(need) + " bytes of workspace, above the " +
+               std::to_string(kNoAllocScratchBytes) + "-byte scratch array of idcur_id_col_noalloc";
+    return IDCUR_EWORKSPACE;
+  }
+  // stage timers would create events: none are taken in this call
+  const bool timing = ctx->timing;
+  ctx->timing = false;
+  Outs o;
+  o.k_out = k_out; o.J = J; o.T = T; o.ldt = ldt;
+  const idcur_status r = run(ctx, OP_COL, dtype, m, n, A, lda, opts, ctx->noalloc_scratch, kNoAllocScratchBytes, o);
+  ctx->timing = timing;
+  return r;
 }
 
 idcur_status idcur_id_row(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, const void* A, int64_t lda,
