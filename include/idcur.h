@@ -218,6 +218,24 @@ idcur_status idcur_id_col_csc(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t 
                               const int32_t* rowidx, const void* vals, const idcur_opts* opts /* host */, void* ws,
                               size_t ws_bytes, int32_t* k_out, int32_t* J, void* T, int64_t ldt);
 
+/* CUR-ID of a sparse A in compressed sparse column form (Algorithm 3 on the
+ * sparse column ID above; Section 1 and Section 3 motivate the CUR by sparse
+ * matrices, whose C and R are sparse): C = A(:, J(1:k)) and R = A(I(1:k), :) are
+ * gathered from the stored entries into dense blocks (repeated rows of a column
+ * add up), the row ID of C and U = V* R^+ follow as in idcur_cur. Arguments as in
+ * idcur_id_col_csc for A and the options (p >= 0, q = 0, Gaussian sketch, NATIVE
+ * precision) and as in idcur_cur for the outputs: k_out device int32[2] (column
+ * rank, rank of C), J int32[n], I int32[m], U (ldu >= k), optional C (m x k, ldc
+ * >= k) and R (k x n, ldr >= n), all dtype. u_correct must be 0 (the corrected
+ * system needs the dense A). The workspace comes from
+ * idcur_cur_csc_workspace_bytes for the same (dtype, m, n, nnz, opts). */
+idcur_status idcur_cur_csc_workspace_bytes(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, int64_t nnz,
+                                           const idcur_opts* opts /* host */, size_t* bytes /* host out */);
+idcur_status idcur_cur_csc(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, int64_t nnz, const int64_t* colptr,
+                           const int32_t* rowidx, const void* vals, const idcur_opts* opts, void* ws, size_t ws_bytes,
+                           int32_t* k_out, int32_t* J, int32_t* I, void* U, int64_t ldu, void* C, int64_t ldc, void* R,
+                           int64_t ldr);
+
 /* Row ID (remark closing Section 2.3): the column ID of A^T, computed from A in
  * place (no transposed copy). I (device int32[m]) is the row permutation, Tr the
  * k_out x (m - k_out) row interpolation matrix (ldtr as ldt above with m for n);

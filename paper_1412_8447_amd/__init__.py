@@ -97,6 +97,11 @@ _lib.idcur_id_col_csc_workspace_bytes.argtypes = [_vp, _i32, _i64, _i64, _i64, c
                                                   ctypes.POINTER(_sz)]
 _lib.idcur_id_col_csc.argtypes = [_vp, _i32, _i64, _i64, _i64, _vp, _vp, _vp, ctypes.POINTER(Opts), _vp, _sz, _vp,
                                   _vp, _vp, _i64]
+_lib.idcur_cur_csc_workspace_bytes.argtypes = [_vp, _i32, _i64, _i64, _i64, ctypes.POINTER(Opts), ctypes.POINTER(_sz)]
+_lib.idcur_cur_csc_workspace_bytes.restype = ctypes.c_int
+_lib.idcur_cur_csc.argtypes = [_vp, _i32, _i64, _i64, _i64, _vp, _vp, _vp, ctypes.POINTER(Opts), _vp, _sz, _vp, _vp,
+                               _vp, _vp, _i64, _vp, _i64, _vp, _i64]
+_lib.idcur_cur_csc.restype = ctypes.c_int
 _lib.idcur_id_row.argtypes = _common + [_vp, _vp, _i64]
 _lib.idcur_id_two_sided.argtypes = _common + [_vp, _vp, _i64, _vp, _vp, _i64]
 _lib.idcur_cur.argtypes = _common + [_vp, _vp, _vp, _i64, _vp, _i64, _vp, _i64]
@@ -135,7 +140,8 @@ EXPORTED = ("idcur_opts_default", "idcur_create", "idcur_set_stream", "idcur_des
             "idcur_sketch", "idcur_id_col_batched_workspace_bytes", "idcur_id_col_batched",
             "idcur_id_col_batched_autotune", "idcur_id_col_batched_set_variant",
             "idcur_id_col_batched_backward_workspace_bytes", "idcur_id_col_batched_backward",
-            "idcur_id_col_csc_workspace_bytes", "idcur_id_col_csc", "idcur_id_col_noalloc")
+            "idcur_id_col_csc_workspace_bytes", "idcur_id_col_csc", "idcur_id_col_noalloc",
+            "idcur_cur_csc_workspace_bytes", "idcur_cur_csc")
 
 STAGES = ("omega", "pack", "sketch_gemm", "orth", "cpqr", "trsm", "gather", "row_id", "u_solve", "error", "backward",
           "batched", "srht", "spmm")
@@ -398,6 +404,42 @@ def id_col_csc(colptr: torch.Tensor, rowidx: torch.Tensor, vals: torch.Tensor, m
     sync_status(vals.device)
     kk = int(kout[0].item())
     return ColumnID(J, T[:kk, : n - kk], kk, kout)
+
+
+def cur_csc(colptr: torch.Tensor, rowidx: torch.Tensor, vals: torch.Tensor, m: int, n: int, k: int = 0, *,
+            workspace=None, sync: bool = True, **kw) -> CUR:
+    """CUR-ID of a sparse m x n matrix in compressed sparse column form
+    (idcur_cur_csc): the sparse column ID, C and R gathered from the stored
+    entries, the row ID of C and U = V* R^+. Options as :func:`id_col_csc`."""
+    for t, name, dt in ((colptr, "colptr", torch.int64), (rowidx, "rowidx", torch.int32)):
+        if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise IDCurError(EINVAL, f"{name} must be a contiguous device tensor of {dt}")
+    if not vals.is_cuda or not vals.is_contiguous() or vals.dtype not in (torch.float32, torch.float64):
+        raise IDCurError(EINVAL, "vals must be a contiguous FP32 / FP64 device tensor")
+    h = _context(vals.device)
+    o = make_opts(k, **kw)
+    kcap = o.k if o.k > 0 else o.kmax
+    code = _dtype_code(vals)
+    nnz = int(vals.numel())
+    if workspace is None:
+        nb = _sz(0)
+        _check(h, _lib.idcur_cur_csc_workspace_bytes(h, code, m, n, nnz, ctypes.byref(o), ctypes.byref(nb)))
+        workspace = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=vals.device)
+    dev = vals.device
+    J = torch.empty(n, dtype=torch.int32, device=dev)
+    I = torch.empty(m, dtype=torch.int32, device=dev)
+    U = torch.empty(kcap, kcap, dtype=vals.dtype, device=dev)
+    C = torch.empty(m, kcap, dtype=vals.dtype, device=dev)
+    R = torch.empty(kcap, n, dtype=vals.dtype, device=dev)
+    kout = torch.zeros(2, dtype=torch.int32, device=dev)
+    _check(h, _lib.idcur_cur_csc(h, code, m, n, nnz, colptr.data_ptr(), rowidx.data_ptr(), vals.data_ptr(),
+                                 ctypes.byref(o), workspace.data_ptr(), workspace.numel(), kout.data_ptr(), J.data_ptr(),
+                                 I.data_ptr(), U.data_ptr(), kcap, C.data_ptr(), kcap, R.data_ptr(), n))
+    if not sync:
+        return CUR(J, I, C, U, R, -1, -1, kout)
+    sync_status(dev)
+    k1, k2 = (int(v) for v in kout.tolist())
+    return CUR(J, I, C[:, :k1], U[:k1, :k2], R[:k2], k1, k2, kout)
 
 
 def id_row(A: torch.Tensor, k: int = 0, *, workspace=None, sync: bool = True, **kw) -> ColumnID:

@@ -1264,6 +1264,44 @@ void execute_csc(idcur_ctx* ctx, int dtype, const Csc& a, const idcur_opts& o, A
   column_id(x, dtype, Y, o2, out.k_out, out.J, out.T, out.ldt, false);
 }
 
+// CUR of a sparse A (Algorithm 3 on the sparse column ID): C = A(:, J(1:k)) and
+// R = A(I(1:k), :) gathered from the compressed columns into dense blocks, the
+// row ID of C and U = V* R^+ as on the dense path.
+void execute_cur_csc(idcur_ctx* ctx, int dtype, const Csc& a, const idcur_opts& o, Arena& ar, const Outs& out) {
+  Ctx x{ctx, ctx->stream, ar.dry, &ar};
+  const int kcap = o.k > 0 ? o.k : o.kmax;
+  const int64_t m = a.m, n = a.n;
+  Outs oc;
+  oc.k_out = out.k_out;
+  oc.J = out.J;
+  oc.T = ar.take((size_t)kcap * n * esz(dtype));
+  oc.ldt = n;
+  execute_csc(ctx, dtype, a, o, ar, oc);
+  void* C = ar.take((size_t)m * kcap * esz(dtype));
+  if (!ar.dry) {
+    Stage st(x, "gather");
+    x.check(zero_launch(C, (size_t)m * kcap * esz(dtype), x.s), "zero C");
+    x.check(csc_gather_cols_launch(dtype, m, n, a.nnz, a.colptr, a.rowidx, a.vals, out.J, kcap, out.k_out, C, kcap,
+                                   x.c->dstatus, x.s),
+            "gather C");
+  }
+  void* Tr = ar.take((size_t)kcap * m * esz(dtype));
+  row_id_of_c(x, dtype, C, m, kcap, out.k_out, out.k_out + 1, out.I, Tr, m, o.t_reg);
+  void* R = ar.take((size_t)kcap * n * esz(dtype));
+  int* slot = static_cast<int*>(ar.take((size_t)m * sizeof(int)));
+  if (!ar.dry) {
+    Stage st(x, "gather");
+    x.check(zero_launch(R, (size_t)kcap * n * esz(dtype), x.s), "zero R");
+    x.check(csc_gather_rows_launch(dtype, m, n, a.nnz, a.colptr, a.rowidx, a.vals, out.I, kcap, out.k_out + 1, slot,
+                                   R, n, x.s),
+            "gather R");
+    if (out.C) x.check(copy2d_launch(dtype, m, kcap, C, kcap, 1, out.C, out.ldc, 1, x.s), "C out");
+    if (out.R) x.check(copy2d_launch(dtype, kcap, n, R, n, 1, out.R, out.ldr, 1, x.s), "R out");
+  }
+  Stage st(x, "u_solve");
+  solve_u(x, dtype, R, n, n, kcap, out.k_out, out.J, oc.T, oc.ldt, out.U, out.ldu);
+}
+
 }  // namespace
 }  // namespace idcur
 
@@ -1415,6 +1453,54 @@ idcur_status idcur_id_col_csc(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t 
     ar.cap = ws_bytes;
     hipcheck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     execute_csc(ctx, dtype, a, *opts, ar, out);
+    return IDCUR_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  }
+}
+
+idcur_status idcur_cur_csc_workspace_bytes(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, int64_t nnz,
+                                           const idcur_opts* opts, size_t* bytes) {
+  try {
+    if (!bytes) fail(ctx, IDCUR_EINVAL, "bytes is NULL");
+    const Csc a{m, n, nnz, nullptr, nullptr, nullptr};
+    validate_csc(ctx, dtype, a, opts);
+    if (opts->u_correct) fail(ctx, IDCUR_EINVAL, "the sparse CUR solves the plain U system (u_correct = 0)");
+    Arena dry;
+    Outs out;
+    execute_cur_csc(ctx, dtype, a, *opts, dry, out);
+    *bytes = dry.off + 256;
+    return IDCUR_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  }
+}
+
+idcur_status idcur_cur_csc(idcur_ctx* ctx, int32_t dtype, int64_t m, int64_t n, int64_t nnz, const int64_t* colptr,
+                           const int32_t* rowidx, const void* vals, const idcur_opts* opts, void* ws, size_t ws_bytes,
+                           int32_t* k_out, int32_t* J, int32_t* I, void* U, int64_t ldu, void* C, int64_t ldc, void* R,
+                           int64_t ldr) {
+  try {
+    const Csc a{m, n, nnz, colptr, rowidx, vals};
+    validate_csc(ctx, dtype, a, opts);
+    if (opts->u_correct) fail(ctx, IDCUR_EINVAL, "the sparse CUR solves the plain U system (u_correct = 0)");
+    if (!colptr || (nnz > 0 && (!rowidx || !vals))) fail(ctx, IDCUR_EINVAL, "colptr, rowidx and vals are required");
+    if (!k_out || !J || !I || !U) fail(ctx, IDCUR_EINVAL, "k_out, J, I and U are required");
+    const int kcap = opts->k > 0 ? opts->k : opts->kmax;
+    if (ldu < kcap) fail(ctx, IDCUR_EINVAL, "ldu too small");
+    if (C && ldc < kcap) fail(ctx, IDCUR_EINVAL, "ldc too small");
+    if (R && ldr < n) fail(ctx, IDCUR_EINVAL, "ldr too small");
+    Outs out;
+    out.k_out = k_out; out.J = J; out.I = I; out.U = U; out.ldu = ldu; out.C = C; out.ldc = ldc; out.R = R; out.ldr = ldr;
+    Arena dry;
+    execute_cur_csc(ctx, dtype, a, *opts, dry, out);
+    if (!ws || ws_bytes < dry.off) fail(ctx, IDCUR_EWORKSPACE, "workspace missing or too small");
+    Arena ar;
+    ar.dry = false;
+    ar.base = static_cast<char*>(ws);
+    ar.cap = ws_bytes;
+    hipcheck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    execute_cur_csc(ctx, dtype, a, *opts, ar, out);
     return IDCUR_OK;
   } catch (const Fail& f) {
     return f.code;

@@ -302,6 +302,17 @@ struct SpmmDesc {
   int* status;
 };
 int spmm_pick_splits(int64_t n, int64_t nnz, int num_cus);
+// C (m x kcap, row-major ldc, zero on entry) = the columns J[0:k] of a sparse
+// matrix in compressed sparse column form, k = min(*k_dev, kcap); repeated rows
+// add up; bad indices set ST_BADINDEX.
+hipError_t csc_gather_cols_launch(int dtype, int64_t m, int64_t n, int64_t nnz, const int64_t* colptr,
+                                  const int* rowidx, const void* vals, const int* J, int kcap, const int* k_dev,
+                                  void* C, int64_t ldc, int* status, hipStream_t stream);
+// R (kcap x n, row-major ldr, zero on entry) = the rows I[0:k] of the same
+// matrix; slot is an int[m] scratch array.
+hipError_t csc_gather_rows_launch(int dtype, int64_t m, int64_t n, int64_t nnz, const int64_t* colptr,
+                                  const int* rowidx, const void* vals, const int* I, int kcap, const int* k_dev,
+                                  int* slot, void* R, int64_t ldr, hipStream_t stream);
 size_t spmm_part_bytes(const SpmmDesc& d, int esize);
 hipError_t spmm_csc_launch(int dtype, const SpmmDesc& d, void* part, hipStream_t stream);
 // Y += (*s) X, rows x cols row-major FP64, the weight a device scalar.

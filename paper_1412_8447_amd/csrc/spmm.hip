@@ -120,7 +120,115 @@ hipError_t launch_t(const SpmmDesc& d, void* part, hipStream_t stream) {
   return hipGetLastError();
 }
 
+// C (m x kcap, row-major ldc, zero on entry) = A(:, J[0:k]) for a matrix in
+// compressed sparse column form: column s of C receives the stored entries of
+// column J[s]. Workgroup (s, y) scatters slice y of the entries; repeated rows
+// add up (in a scheduling-dependent order when a column repeats a row three or
+// more times). k = min(*k_dev, kcap).
+template <typename T>
+__global__ __launch_bounds__(256) void csc_gather_cols_kernel(int64_t m, int64_t n, int64_t nnz, const int64_t* colptr,
+                                                            const int* rowidx, const T* vals, const int* J, int kcap,
+                                                            const int* k_dev, T* C, int64_t ldc, int* status) {
+  const int s = blockIdx.x;
+  const int k = min(*k_dev, kcap);
+  if (s >= k) return;
+  const int j = J[s];
+  if (j < 0 || j >= n) {
+    if (threadIdx.x == 0) set_status(status, ST_BADINDEX);
+    return;
+  }
+  int64_t p0 = colptr[j], p1 = colptr[j + 1];
+  if (p0 < 0 || p1 > nnz || p0 > p1) {
+    if (threadIdx.x == 0) set_status(status, ST_BADINDEX);
+    return;
+  }
+  const int64_t len = p1 - p0;
+  const int64_t q0 = p0 + len * blockIdx.y / gridDim.y, q1 = p0 + len * (blockIdx.y + 1) / gridDim.y;
+  for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+    const int i = rowidx[q];
+    if (i < 0 || i >= m) {
+      set_status(status, ST_BADINDEX);
+      continue;
+    }
+    atomicAdd(&C[(int64_t)i * ldc + s], vals[q]);
+  }
+}
+
+__global__ __launch_bounds__(256) void fill_i32_kernel(int* p, int64_t n, int v) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) p[e] = v;
+}
+hipError_t fill_i32_launch(int* p, int64_t n, int v, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(n, 256), 4096)), dim3(256), 0, stream,
+                     p, n, v);
+  return hipGetLastError();
+}
+
+// slot[i] = s for the selected rows i = I[s], s < min(*k_dev, kcap) (slot is -1
+// everywhere else on entry).
+__global__ __launch_bounds__(256) void csc_row_slots_kernel(int64_t m, const int* I, int kcap, const int* k_dev,
+                                                          int* slot) {
+  const int k = min(*k_dev, kcap);
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < k; s += gridDim.x * blockDim.x) {
+    const int i = I[s];
+    if (i >= 0 && i < m) slot[i] = s;
+  }
+}
+
+// R (kcap x n, row-major ldr, zero on entry) = A(I[0:k], :): every stored entry
+// whose row is selected goes to its slot's row. Workgroup j reads column j's
+// entries once.
+template <typename T>
+__global__ __launch_bounds__(256) void csc_gather_rows_kernel(int64_t m, int64_t nnz, const int64_t* colptr,
+                                                            const int* rowidx, const T* vals, const int* slot, T* R,
+                                                            int64_t ldr) {
+  const int64_t j = blockIdx.x;
+  int64_t p0 = colptr[j], p1 = colptr[j + 1];
+  if (p0 < 0 || p1 > nnz || p0 > p1) return;   // reported by the sketch
+  for (int64_t q = p0 + threadIdx.x; q < p1; q += blockDim.x) {
+    const int i = rowidx[q];
+    if (i < 0 || i >= m) continue;
+    const int sl = slot[i];
+    if (sl >= 0) atomicAdd(&R[(int64_t)sl * ldr + j], vals[q]);
+  }
+}
+
 }  // namespace
+
+hipError_t csc_gather_cols_launch(int dtype, int64_t m, int64_t n, int64_t nnz, const int64_t* colptr,
+                                  const int* rowidx, const void* vals, const int* J, int kcap, const int* k_dev,
+                                  void* C, int64_t ldc, int* status, hipStream_t stream) {
+  if (kcap <= 0) return hipSuccess;
+  const int64_t per = std::max<int64_t>(1, nnz / std::max<int64_t>(n, 1));
+  const unsigned ys = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, per / 2048));
+  const dim3 grid((unsigned)kcap, ys);
+  if (dtype == 0)
+    hipLaunchKernelGGL(csc_gather_cols_kernel<double>, grid, dim3(256), 0, stream, m, n, nnz, colptr, rowidx,
+                       static_cast<const double*>(vals), J, kcap, k_dev, static_cast<double*>(C), ldc, status);
+  else
+    hipLaunchKernelGGL(csc_gather_cols_kernel<float>, grid, dim3(256), 0, stream, m, n, nnz, colptr, rowidx,
+                       static_cast<const float*>(vals), J, kcap, k_dev, static_cast<float*>(C), ldc, status);
+  return hipGetLastError();
+}
+
+hipError_t csc_gather_rows_launch(int dtype, int64_t m, int64_t n, int64_t nnz, const int64_t* colptr,
+                                  const int* rowidx, const void* vals, const int* I, int kcap, const int* k_dev,
+                                  int* slot, void* R, int64_t ldr, hipStream_t stream) {
+  if (kcap <= 0 || n <= 0) return hipSuccess;
+  hipError_t e = fill_i32_launch(slot, m, -1, stream);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(csc_row_slots_kernel, dim3((unsigned)ceil_div(kcap, 256)), dim3(256), 0, stream, m, I, kcap,
+                     k_dev, slot);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (dtype == 0)
+    hipLaunchKernelGGL(csc_gather_rows_kernel<double>, dim3((unsigned)n), dim3(256), 0, stream, m, nnz, colptr,
+                       rowidx, static_cast<const double*>(vals), slot, static_cast<double*>(R), ldr);
+  else
+    hipLaunchKernelGGL(csc_gather_rows_kernel<float>, dim3((unsigned)n), dim3(256), 0, stream, m, nnz, colptr,
+                       rowidx, static_cast<const float*>(vals), slot, static_cast<float*>(R), ldr);
+  return hipGetLastError();
+}
 
 // Splits of each column's entries: enough waves to fill the chip (32 per CU)
 // over few columns, each split about 64 entries or more; 1 when the columns
