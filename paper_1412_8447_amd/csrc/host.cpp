@@ -12,6 +12,7 @@
 #include <string>
 
 #include "../../include/idcur.h"
+#include "args.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -62,7 +63,7 @@ namespace idcur {
 namespace {
 
 constexpr double kU32 = 5.9604644775390625e-08;   // 2^-24
-constexpr int kMaxRank = 4096;   // largest k (and k + p): bounds the k x k FP64 work buffers
+static_assert(kSrhtMaxRowsArg == kSrhtMaxRows, "argument check and kernel agree on the sketch rows");
 constexpr double kU64 = 1.1102230246251565e-16;   // 2^-53
 
 struct Fail {
@@ -629,62 +630,12 @@ void solve_u(const Ctx& x, int dtype, const void* R, int64_t ldr, int64_t n, int
   prod(kcap, kcap, kcap, Y1, 1, kcap, 0, L1i, kcap, 1, 0, U, ldu, dtype, k_dev, kr_dev, kr_dev);
 }
 
-enum Op { OP_COL = 0, OP_ROW = 1, OP_TWO = 2, OP_CUR = 3, OP_SKETCH = 4, OP_SKETCH_ROW = 5 };
-
-struct Outs {
-  int* k_out = nullptr;
-  int* J = nullptr; void* T = nullptr; int64_t ldt = 0;
-  int* I = nullptr; void* Tr = nullptr; int64_t ldtr = 0;
-  void* U = nullptr; int64_t ldu = 0;
-  void* C = nullptr; int64_t ldc = 0;
-  void* R = nullptr; int64_t ldr = 0;
-  void* Yt = nullptr; int64_t ldy = 0;
-};
-
 void validate(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const void* A, int64_t lda,
               const idcur_opts* opts) {
   if (!ctx) throw Fail{IDCUR_EINVAL};
-  if (!opts) fail(ctx, IDCUR_EINVAL, "opts is NULL");
-  if (dtype != IDCUR_F32 && dtype != IDCUR_F64) fail(ctx, IDCUR_EDTYPE, "dtype must be IDCUR_F32 or IDCUR_F64");
-  if (opts->prec != IDCUR_PREC_NATIVE && opts->prec != IDCUR_PREC_BF16 && opts->prec != IDCUR_PREC_FP16)
-    fail(ctx, IDCUR_EINVAL, "unknown precision");
-  if (opts->prec != IDCUR_PREC_NATIVE && dtype != IDCUR_F32)
-    fail(ctx, IDCUR_EDTYPE, "BF16 / FP16 sketches take FP32 data");
-  if (op < 0 || op > 5) fail(ctx, IDCUR_EINVAL, "unknown op");
-  if (m <= 0 || n <= 0) fail(ctx, IDCUR_EINVAL, "m and n must be positive");
-  if (m > (1LL << 30) || n > (1LL << 30)) fail(ctx, IDCUR_EINVAL, "m and n must be below 2^30");
-  if (lda < n) fail(ctx, IDCUR_EINVAL, "lda must be >= n");
   (void)A;
-  const bool rowop = op == OP_ROW || op == OP_SKETCH_ROW;
-  const int64_t mr = rowop ? n : m, nc = rowop ? m : n;
-  const int64_t mn = std::min(m, n);
-  if (opts->k < 0) fail(ctx, IDCUR_EINVAL, "k must be >= 0");
-  if (opts->k > 0) {
-    if (opts->k >= mn) fail(ctx, IDCUR_EINVAL, "k must be < min(m, n)");
-  } else {
-    if (!(opts->tol > 0.0) || !std::isfinite(opts->tol)) fail(ctx, IDCUR_EINVAL, "tolerance mode needs tol > 0");
-    if (opts->kmax <= 0 || opts->kmax >= mn) fail(ctx, IDCUR_EINVAL, "tolerance mode needs 0 < kmax < min(m, n)");
-  }
-  const int kcap = opts->k > 0 ? opts->k : opts->kmax;
-  if (opts->q < 0) fail(ctx, IDCUR_EINVAL, "q must be >= 0");
-  if (kcap > kMaxRank || (opts->p >= 0 && (int64_t)kcap + opts->p > kMaxRank))
-    fail(ctx, IDCUR_EINVAL, "k (kmax) and k + p must be <= 4096");
-  if ((op == OP_SKETCH || op == OP_SKETCH_ROW) && !(opts->p >= 0 && (int64_t)kcap + opts->p < mr))
-    fail(ctx, IDCUR_EINVAL, "a sketch needs p >= 0 and k + p below the sketched dimension");
-  if (opts->rank_tol < 0 || !std::isfinite(opts->rank_tol)) fail(ctx, IDCUR_EINVAL, "rank_tol must be >= 0");
-  if (opts->norms != IDCUR_NORMS_DOWNDATE && opts->norms != IDCUR_NORMS_EXACT) fail(ctx, IDCUR_EINVAL, "bad norms");
-  if (opts->sketch != IDCUR_SKETCH_GAUSSIAN && opts->sketch != IDCUR_SKETCH_SRHT)
-    fail(ctx, IDCUR_EINVAL, "unknown sketch kind");
-  if (opts->u_correct != 0 && opts->u_correct != 1) fail(ctx, IDCUR_EINVAL, "u_correct must be 0 or 1");
-  if (!(opts->t_reg >= 0.0 && opts->t_reg < 1.0)) fail(ctx, IDCUR_EINVAL, "t_reg must be in [0, 1)");
-  if (opts->sketch == IDCUR_SKETCH_SRHT && opts->p >= 0 && (int64_t)kcap + opts->p < mr) {
-    if (opts->q != 0) fail(ctx, IDCUR_EINVAL, "the structured sketch takes no power steps (q = 0)");
-    if (opts->prec != IDCUR_PREC_NATIVE) fail(ctx, IDCUR_EDTYPE, "the structured sketch runs in the native precision");
-    if (opts->omega) fail(ctx, IDCUR_EINVAL, "omega and the structured sketch exclude each other");
-    if (!opts->srht_rows || !opts->srht_signs) fail(ctx, IDCUR_EINVAL, "srht_rows and srht_signs are required");
-    if ((int64_t)kcap + opts->p > kSrhtMaxRows) fail(ctx, IDCUR_EINVAL, "k (kmax) + p must be <= 512 for the structured sketch");
-  }
-  (void)nc;
+  const ArgCheck r = check_id_args(op, dtype, m, n, lda, opts);
+  if (r.code != IDCUR_OK) fail(ctx, r.code, r.msg);
 }
 
 void execute(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const void* A, int64_t lda,
@@ -964,23 +915,8 @@ struct BatchedCall {
 
 void batched_validate(idcur_ctx* ctx, int dtype, const BatchedCall& c, const idcur_opts* o) {
   if (!ctx) throw Fail{IDCUR_EINVAL};
-  if (!o) fail(ctx, IDCUR_EINVAL, "opts is NULL");
-  if (dtype != IDCUR_F32) fail(ctx, IDCUR_EDTYPE, "the batched ID takes FP32 blocks");
-  if (o->prec != IDCUR_PREC_NATIVE) fail(ctx, IDCUR_EDTYPE, "the batched ID sketches in FP32");
-  if (c.nblk < 0 || c.nblk > (1 << 20)) fail(ctx, IDCUR_EINVAL, "nblk must be in [0, 2^20]");
-  if (c.mmax < 1 || c.mmax > (1 << 24)) fail(ctx, IDCUR_EINVAL, "mmax must be in [1, 2^24]");
-  if (c.nmax < 1 || c.nmax > batched_max_width()) fail(ctx, IDCUR_EINVAL, "nmax must be in [1, 512]");
-  if (o->p < 1) fail(ctx, IDCUR_EINVAL, "the batched ID needs oversampling p >= 1");
-  if (o->q != 0) fail(ctx, IDCUR_EINVAL, "the batched ID takes no power steps (q = 0)");
-  if (o->k < 0) fail(ctx, IDCUR_EINVAL, "k must be >= 0");
-  if (o->k == 0) {
-    if (!(o->tol > 0.0) || !std::isfinite(o->tol)) fail(ctx, IDCUR_EINVAL, "tolerance mode needs tol > 0");
-    if (o->kmax < 1) fail(ctx, IDCUR_EINVAL, "tolerance mode needs kmax >= 1");
-  }
-  const int kcap = o->k > 0 ? o->k : o->kmax;
-  if ((int64_t)kcap + o->p > batched_max_sketch()) fail(ctx, IDCUR_EINVAL, "k (kmax) + p must be <= 64");
-  if (o->rank_tol < 0 || !std::isfinite(o->rank_tol)) fail(ctx, IDCUR_EINVAL, "rank_tol must be >= 0");
-  if (o->t_reg != 0.0) fail(ctx, IDCUR_EINVAL, "the batched ID forms T by back-substitution (t_reg = 0)");
+  const ArgCheck r = check_batched_args(dtype, c.nblk, c.mmax, c.nmax, o, batched_max_width(), batched_max_sketch());
+  if (r.code != IDCUR_OK) fail(ctx, r.code, r.msg);
 }
 
 std::vector<int64_t> batched_key(const BatchedCall& c, const idcur_opts& o) {
@@ -1167,34 +1103,8 @@ idcur_status run(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const 
                  const idcur_opts* opts, void* ws, size_t ws_bytes, const Outs& out) {
   try {
     validate(ctx, op, dtype, m, n, A, lda, opts);
-    if (!A) fail(ctx, IDCUR_EINVAL, "A is NULL");
-    const int kcap = opts->k > 0 ? opts->k : opts->kmax;
-    const int64_t nc = op == OP_ROW ? m : n;
-    if (op == OP_SKETCH || op == OP_SKETCH_ROW) {
-      if (!out.Yt) fail(ctx, IDCUR_EINVAL, "Yt is NULL");
-      if (out.ldy < kcap + opts->p) fail(ctx, IDCUR_EINVAL, "ldy too small");
-    } else if (!out.k_out) {
-      fail(ctx, IDCUR_EINVAL, "k_out is NULL");
-    } else if (op == OP_ROW) {
-      if (!out.I || !out.Tr) fail(ctx, IDCUR_EINVAL, "I and Tr are required");
-      if (out.ldtr < (opts->k > 0 ? m - kcap : m)) fail(ctx, IDCUR_EINVAL, "ldtr too small");
-    } else {
-      if (!out.J) fail(ctx, IDCUR_EINVAL, "J is required");
-      if (op != OP_CUR) {
-        if (!out.T) fail(ctx, IDCUR_EINVAL, "T is required");
-        if (out.ldt < (opts->k > 0 ? nc - kcap : nc)) fail(ctx, IDCUR_EINVAL, "ldt too small");
-      }
-      if (op == OP_TWO) {
-        if (!out.I || !out.Tr) fail(ctx, IDCUR_EINVAL, "I and Tr are required");
-        if (out.ldtr < (opts->k > 0 ? m - kcap : m)) fail(ctx, IDCUR_EINVAL, "ldtr too small");
-      }
-      if (op == OP_CUR) {
-        if (!out.I || !out.U) fail(ctx, IDCUR_EINVAL, "I and U are required");
-        if (out.ldu < kcap) fail(ctx, IDCUR_EINVAL, "ldu too small");
-        if (out.C && out.ldc < kcap) fail(ctx, IDCUR_EINVAL, "ldc too small");
-        if (out.R && out.ldr < n) fail(ctx, IDCUR_EINVAL, "ldr too small");
-      }
-    }
+    const ArgCheck r = check_id_outs(op, m, n, A, *opts, out);
+    if (r.code != IDCUR_OK) fail(ctx, r.code, r.msg);
     Arena dry;
     execute(ctx, op, dtype, m, n, A, lda, *opts, dry, out);
     if (!ws || ws_bytes < dry.off) fail(ctx, IDCUR_EWORKSPACE, "workspace missing or too small");
