@@ -46,12 +46,12 @@ from .errors import (
     e_two_sided,
     e_cur,
 )
-from .stabilized import interp_tikhonov, tikhonov_weight
+from .stabilized import interp_tikhonov, interp_tsvd, tikhonov_weight
 from . import philox
 
 __all__ = [
     "cpqr", "CPQRResult", "default_rank_tol", "back_substitute", "orth", "sketch",
     "id_col", "id_row", "two_sided", "cur", "vstar_from", "w_from",
     "IDResult", "TwoSidedResult", "CURResult", "rel_fro", "e_id", "e_two_sided",
-    "e_cur", "philox", "interp_tikhonov", "tikhonov_weight",
+    "e_cur", "philox", "interp_tikhonov", "interp_tsvd", "tikhonov_weight",
 ]

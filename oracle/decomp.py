@@ -25,7 +25,7 @@ import numpy as np
 
 from .cpqr import cpqr, CPQRResult
 from .backsub import back_substitute
-from .stabilized import interp_tikhonov
+from .stabilized import interp_tikhonov, interp_tsvd
 
 
 def orth(Y: np.ndarray) -> np.ndarray:
@@ -54,7 +54,7 @@ class IDResult:
     Y: np.ndarray      # the matrix the CPQR ran on (A itself, or the sketch)
 
 
-def _id_from_y(Y: np.ndarray, k: int, tol, rank_tol, t_reg: float = 0.0) -> IDResult:
+def _id_from_y(Y: np.ndarray, k: int, tol, rank_tol, t_reg: float = 0.0, t_svd: float = 0.0) -> IDResult:
     res = cpqr(Y, k, tol=tol, rank_tol=rank_tol)
     kk = res.k_out
     S11 = res.S[:, :kk]
@@ -63,27 +63,32 @@ def _id_from_y(Y: np.ndarray, k: int, tol, rank_tol, t_reg: float = 0.0) -> IDRe
         T = np.zeros((0, Y.shape[1]))
     elif t_reg > 0.0:   # the stabilized T of Section 4.1 (Tikhonov form)
         T = interp_tikhonov(S11[:kk], S12[:kk], t_reg)
+    elif t_svd > 0.0:   # the stabilized T of Section 4.1 (truncated SVD of S11)
+        T = interp_tsvd(S11[:kk], S12[:kk], t_svd)
     else:
         T = back_substitute(S11, S12)
     return IDResult(J=res.J, T=T, k=kk, qr=res, Y=Y)
 
 
 def id_col(A: np.ndarray, k: int, omega: np.ndarray | None = None, q: int = 0,
-           tol: float | None = None, rank_tol: float | None = None, t_reg: float = 0.0) -> IDResult:
+           tol: float | None = None, rank_tol: float | None = None, t_reg: float = 0.0,
+           t_svd: float = 0.0) -> IDResult:
     """Rank-k column ID of A (Algorithm 1), or of its sketch when ``omega`` is
     given (Algorithm 4 with the power scheme of Section 5.3). ``t_reg > 0`` takes
-    the Tikhonov-stabilized T (oracle.stabilized) with delta = t_reg."""
+    the Tikhonov-stabilized T (oracle.stabilized) with delta = t_reg; ``t_svd >
+    0`` the truncated-SVD T with relative threshold t_svd."""
     A = np.asarray(A, dtype=np.float64)
     Y = A if omega is None else sketch(A, omega, q)
-    return _id_from_y(Y, k, tol, rank_tol, t_reg)
+    return _id_from_y(Y, k, tol, rank_tol, t_reg, t_svd)
 
 
 def id_row(A: np.ndarray, k: int, omega: np.ndarray | None = None, q: int = 0,
-           tol: float | None = None, rank_tol: float | None = None, t_reg: float = 0.0) -> IDResult:
+           tol: float | None = None, rank_tol: float | None = None, t_reg: float = 0.0,
+           t_svd: float = 0.0) -> IDResult:
     """Row ID A ~ W A(I(1:k), :): the column ID of A^T. ``J`` of the result is
     the row index vector I, ``T`` the row interpolation matrix."""
     return id_col(np.asarray(A, dtype=np.float64).T, k, omega=omega, q=q, tol=tol,
-                  rank_tol=rank_tol, t_reg=t_reg)
+                  rank_tol=rank_tol, t_reg=t_reg, t_svd=t_svd)
 
 
 def vstar_from(J: np.ndarray, T: np.ndarray, n: int) -> np.ndarray:
@@ -115,13 +120,14 @@ class TwoSidedResult:
 
 def two_sided(A: np.ndarray, k: int, omega: np.ndarray | None = None, q: int = 0,
               tol: float | None = None, rank_tol: float | None = None,
-              row_rank_tol: float | None = None, t_reg: float = 0.0) -> TwoSidedResult:
+              row_rank_tol: float | None = None, t_reg: float = 0.0, t_svd: float = 0.0) -> TwoSidedResult:
     """Algorithm 2: column ID of A, then a full-rank ID of C^T (k steps of CPQR on
-    the k x m matrix C^T). ``t_reg`` stabilizes both interpolation matrices."""
+    the k x m matrix C^T). ``t_reg`` or ``t_svd`` stabilizes both interpolation
+    matrices."""
     A = np.asarray(A, dtype=np.float64)
-    col = id_col(A, k, omega=omega, q=q, tol=tol, rank_tol=rank_tol, t_reg=t_reg)
+    col = id_col(A, k, omega=omega, q=q, tol=tol, rank_tol=rank_tol, t_reg=t_reg, t_svd=t_svd)
     C = A[:, col.J[:col.k]]
-    row = _id_from_y(C.T, col.k, None, row_rank_tol, t_reg)
+    row = _id_from_y(C.T, col.k, None, row_rank_tol, t_reg, t_svd)
     return TwoSidedResult(col=col, row=row, C=C)
 
 
@@ -152,12 +158,13 @@ def corrected_rhs(A: np.ndarray, C: np.ndarray, Vstar: np.ndarray) -> np.ndarray
 
 def cur(A: np.ndarray, k: int, omega: np.ndarray | None = None, q: int = 0,
         tol: float | None = None, rank_tol: float | None = None,
-        row_rank_tol: float | None = None, u_correct: bool = False, t_reg: float = 0.0) -> CURResult:
+        row_rank_tol: float | None = None, u_correct: bool = False, t_reg: float = 0.0,
+        t_svd: float = 0.0) -> CURResult:
     """Algorithm 3 (CUR-ID): C = A(:, J(1:k)), R = A(I(1:k), :), U = V* R^+;
     with ``u_correct`` U solves U R = V* + C^+ E instead (Section 4.3)."""
     A = np.asarray(A, dtype=np.float64)
     ts = two_sided(A, k, omega=omega, q=q, tol=tol, rank_tol=rank_tol,
-                   row_rank_tol=row_rank_tol, t_reg=t_reg)
+                   row_rank_tol=row_rank_tol, t_reg=t_reg, t_svd=t_svd)
     n = A.shape[1]
     kr = ts.row.k
     R = A[ts.row.J[:kr], :]

@@ -6,8 +6,16 @@ baseline call this module; the library never does.
 
 When S11 is ill-conditioned the paper treats T as the minimizer of
 |S11 U - S12| and names two stabilized solutions: a truncated-SVD pseudo-inverse
-of S11, or a Tikhonov term added to the minimization. This module gives the
-Tikhonov form, whose minimizer
+of S11, or a Tikhonov term added to the minimization. This module gives both.
+
+Truncated SVD: with S11 = Ut diag(s) Vt^T, the terms whose singular value is
+below thr times the largest are dropped and
+
+    T = Vt_kept diag(1 / s_kept) Ut_kept^T S12,
+
+the minimum-norm least-squares solution for the truncated S11.
+
+Tikhonov: the minimizer
 
     T = argmin_U |S11 U - S12|_F^2 + lam^2 |U|_F^2,   lam = delta * max_j |S11(:, j)|_2
 
@@ -43,3 +51,19 @@ def interp_tikhonov(S11: np.ndarray, S12: np.ndarray, delta: float) -> np.ndarra
     Ut, s, Vth = np.linalg.svd(S11)
     filt = s / (s * s + lam * lam)
     return Vth.T @ (filt[:, None] * (Ut.T @ S12))
+
+
+def interp_tsvd(S11: np.ndarray, S12: np.ndarray, thr: float) -> np.ndarray:
+    """The truncated-SVD T (k x r) for S11 (k x k) and S12 (k x r), in FP64
+    (Section 4.1's stabilized pseudo-inverse of S11 in eq. (lsqr_for_T)): the
+    SVD of S11, the terms with a singular value below thr times the largest
+    dropped, T = V D^{-1} U^T S12 over the rest."""
+    S11 = np.asarray(S11, dtype=np.float64)
+    S12 = np.asarray(S12, dtype=np.float64)
+    k = S11.shape[0]
+    if k == 0:
+        return np.zeros((0, S12.shape[1]))
+    Ut, s, Vth = np.linalg.svd(S11)
+    keep = s >= float(thr) * s[0] if s[0] > 0 else np.zeros_like(s, dtype=bool)
+    keep &= s > 0
+    return Vth[keep].T @ ((Ut[:, keep].T @ S12) / s[keep, None])

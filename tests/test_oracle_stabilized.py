@@ -104,3 +104,76 @@ def test_id_col_with_t_reg():
     e0 = np.linalg.norm(A[:, plain.J[k:]] - C @ plain.T)
     e1 = np.linalg.norm(A[:, reg.J[k:]] - C @ reg.T)
     assert e1 <= 1.5 * e0 + 1e-12 * np.linalg.norm(A)
+
+
+# ---------------------------------------------------------------------------
+# Truncated-SVD pseudo-inverse of S11 (Section 4.1)
+# ---------------------------------------------------------------------------
+def _thr_between(s, i):
+    """A relative threshold strictly between s[i] / s[0] and s[i-1] / s[0]."""
+    return float(np.sqrt(s[i] * s[i - 1])) / float(s[0])
+
+
+def test_tsvd_matches_lapack_lstsq_rcond():
+    """With the cut between two singular values, T is LAPACK's minimum-norm
+    least-squares solution (gelsd through numpy's lstsq) with rcond = thr, which
+    drops the singular values below rcond times the largest."""
+    from oracle.stabilized import interp_tsvd
+    S11, S12 = _graded_triangle(14, 10.0, seed=311)
+    s = np.linalg.svd(S11, compute_uv=False)
+    for i in (4, 9, 13):
+        thr = _thr_between(s, i)
+        T = interp_tsvd(S11, S12, thr)
+        T_ls = np.linalg.lstsq(S11, S12, rcond=thr)[0]
+        assert np.abs(T - T_ls).max() <= 1e-9 * max(1.0, np.abs(T_ls).max())
+
+
+def test_tsvd_without_truncation_is_the_inverse():
+    """Nothing dropped: T = S11^{-1} S12, here by LU (numpy.linalg.solve) and by
+    the oracle's own back-substitution."""
+    from oracle.stabilized import interp_tsvd
+    S11, S12 = _graded_triangle(10, 2.0, seed=312)
+    T = interp_tsvd(S11, S12, 1e-14)
+    T_lu = np.linalg.solve(S11, S12)
+    assert np.abs(T - T_lu).max() <= 1e-10 * max(1.0, np.abs(T_lu).max())
+    assert np.abs(T - back_substitute(S11, S12)).max() <= 1e-10 * max(1.0, np.abs(T_lu).max())
+
+
+def test_tsvd_diagonal_closed_form():
+    """S11 = diag(d): row i of T is S12(i, :) / d_i where d_i >= thr max|d|,
+    zero elsewhere."""
+    from oracle.stabilized import interp_tsvd
+    d = np.array([5.0, 3.0, 1e-3, 2.0, 1e-6, 0.5])
+    rng = np.random.default_rng(313)
+    S12 = rng.standard_normal((6, 4))
+    T = interp_tsvd(np.diag(d), S12, 1e-2)
+    want = np.where((d >= 0.05)[:, None], S12 / d[:, None], 0.0)
+    assert np.abs(T - want).max() <= 1e-14 * np.abs(want).max()
+
+
+def test_tsvd_exact_null_space():
+    """S11 of rank 3 (two zero singular values, built from random orthogonal
+    factors): T has no component in the null space of S11, and S11 T is the
+    projection of S12 onto the range of S11."""
+    from oracle.stabilized import interp_tsvd
+    rng = np.random.default_rng(314)
+    Q = np.linalg.qr(rng.standard_normal((5, 5)))[0]
+    Z = np.linalg.qr(rng.standard_normal((5, 5)))[0]
+    S11 = Q @ np.diag([3.0, 2.0, 1.0, 0.0, 0.0]) @ Z.T
+    S12 = rng.standard_normal((5, 7))
+    T = interp_tsvd(S11, S12, 1e-8)
+    assert np.abs(Z[:, 3:].T @ T).max() <= 1e-12
+    P = Q[:, :3] @ Q[:, :3].T
+    assert np.abs(S11 @ T - P @ S12).max() <= 1e-12
+
+
+def test_id_col_tsvd_threshold_small_equals_plain():
+    """The column ID with a negligible threshold gives the plain T (Section 2.3,
+    eq. (S11T=S12)); a threshold inside the spectrum of S11 changes it."""
+    A = synth.lowrank(300, 200, synth.sigma_exp(200, 5.0), seed=315)
+    plain = id_col(A, 20)
+    stab = id_col(A, 20, t_svd=1e-15)
+    assert np.array_equal(plain.J, stab.J)
+    assert np.abs(stab.T - plain.T).max() <= 1e-9 * max(1.0, np.abs(plain.T).max())
+    cut = id_col(A, 20, t_svd=1e-2)
+    assert np.abs(cut.T - plain.T).max() > 1e-6
