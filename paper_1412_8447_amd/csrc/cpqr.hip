@@ -118,7 +118,7 @@ __global__ __launch_bounds__(kThreads) void cpqr_kernel(CpqrArgs a) {
     slab.p = static_cast<T*>(a.gslab) + (size_t)c0 * lpad;
   }
   T* v = reinterpret_cast<T*>(sp);                 sp += (size_t)lpad * sizeof(T);
-  sp = (unsigned char*)(((uintptr_t)sp + 15) & ~(uintptr_t)15);
+  sp = smem + (((sp - smem) + 15) & ~(ptrdiff_t)15);   // offset arithmetic keeps LDS addressing
   double* nu = reinterpret_cast<double*>(sp);      sp += (size_t)a.cols_per_wg * sizeof(double);
   double* nuref = reinterpret_cast<double*>(sp);   sp += (size_t)a.cols_per_wg * sizeof(double);
   double* red = reinterpret_cast<double*>(sp);     sp += 16 * sizeof(double);

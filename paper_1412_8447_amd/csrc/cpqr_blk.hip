@@ -13,9 +13,10 @@
 // and writes nothing but the new row of S; the trailing matrix is brought up to
 // date once per panel by a rank-nb update on the matrix cores
 // (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64). Norms are downdated
-// (nu^2 -= s^2) and recomputed in FP64 from the updated slab when a downdate has
-// cancelled; a cancellation anywhere ends the panel early (every workgroup
-// flushes, recomputes and picks again), so pivots always come from valid norms.
+// (nu^2 -= s^2); when a downdate has cancelled, the owning workgroup brings that
+// column alone up to date (Y0(:, c) -= V F(c, :)^T, F(c, :) = 0 -- the panel's
+// formulas stay valid) and recomputes its norm in FP64 before it publishes its
+// next candidate, so pivots always come from valid norms.
 //
 // Two forms, fixed per launch:
 //  * short (V fits in LDS, e.g. the 500 x 50000 C^T of a rank-500 CUR): every
@@ -50,7 +51,7 @@ namespace cb {
 constexpr int kBT = 512;
 constexpr int kBW = kBT / 64;
 constexpr int kNBMax = 32;
-constexpr int kW1 = 40;   // words per step record: key, sumsq, flag, tag, F[0:nb]
+constexpr int kW1 = 40;   // words per step record: key, sumsq, (unused), tag, F[0:nb]
 constexpr int kW2 = 40;   // words per row record (tall): ssq, tag, w'[0:nb]
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -273,11 +274,14 @@ __global__ __launch_bounds__(kBT) void cpqr_blk_kernel(CpqrArgs a) {
   unsigned char* sp = smem;
   T* Vl = reinterpret_cast<T*>(sp);   // short: nb x lpad; tall: nb x rpw (own rows)
   sp += (size_t)nb * (TALL ? rpw : lpad) * sizeof(T);
-  T* vloc = reinterpret_cast<T*>(sp);  // tall: vch rows of v
-  if (TALL) sp += (size_t)vch * sizeof(T);
-  sp = (unsigned char*)(((uintptr_t)sp + 15) & ~(uintptr_t)15);
+  sp = smem + (((sp - smem) + 15) & ~(ptrdiff_t)15);   // offset arithmetic keeps LDS addressing
+  // v of the current step in FP64 (its T values, exact): short lpad rows, tall
+  // vch rows at a time
+  double* vd = reinterpret_cast<double*>(sp);
+  double* vloc = vd;
+  sp += (size_t)(TALL ? vch : lpad) * 8;
   T* F = reinterpret_cast<T*>(sp);     sp += (size_t)cpw * nbp * sizeof(T);
-  sp = (unsigned char*)(((uintptr_t)sp + 15) & ~(uintptr_t)15);
+  sp = smem + (((sp - smem) + 15) & ~(ptrdiff_t)15);   // offset arithmetic keeps LDS addressing
   double* nu2 = reinterpret_cast<double*>(sp);    sp += (size_t)cpw * 8;
   double* lim = reinterpret_cast<double*>(sp);    sp += (size_t)cpw * 8;
   double* dots = reinterpret_cast<double*>(sp);   sp += (size_t)cpw * 8;
@@ -289,6 +293,8 @@ __global__ __launch_bounds__(kBT) void cpqr_blk_kernel(CpqrArgs a) {
   double* rd = reinterpret_cast<double*>(sp);     sp += 4 * kBW * 8;
   int* sel = reinterpret_cast<int*>(sp);          sp += (size_t)cpw * 4;   // -1 active, else its step
   int* need = reinterpret_cast<int*>(sp);         sp += (size_t)cpw * 4;
+  int* flist = reinterpret_cast<int*>(sp);        sp += (size_t)cpw * 4;   // columns to refresh
+  double* rfl = reinterpret_cast<double*>(sp);    sp += 8 * kBW * 8;       // their partial sums
   int* ri = reinterpret_cast<int*>(sp);           sp += 2 * kBW * 4;
   int* win = reinterpret_cast<int*>(sp);          // kmax_host
   __shared__ int sh[4];
@@ -384,28 +390,50 @@ __global__ __launch_bounds__(kBT) void cpqr_blk_kernel(CpqrArgs a) {
       const int nks = (ib + 3) >> 2;
       const int kq = lane >> 4, li = lane & 15;
       const __amdgpu_buffer_rsrc_t rs_V = rsrc(Vglob, (uint32_t)((size_t)nb * lpad * sizeof(T)));
-      for (int rt = (j >> 4) + wv; rt < (lpad >> 4); rt += kBW) {
+      const int ntc = cpw >> 4;
+      // the V operand of row tile rt (16 rows x ib), zero outside rows [j, l)
+      auto vload = [&](int rt, T (&av)[kNBMax / 4]) {
         const int r = rt * 16 + li;
-        T av[kNBMax / 4];
 #pragma unroll
         for (int ks = 0; ks < kNBMax / 4; ++ks) {
           const int s = 4 * ks + kq;
           T x = (T)0;
-          if (ks < nks && s < ib && r >= j && r < l) {
+          if (ks < nks && s < ib && r >= j && r < l && rt < (lpad >> 4)) {
             if constexpr (TALL) x = -load1_sc1<T>(rs_V, (uint32_t)(s * lpad + r));
             else x = -Vl[(size_t)s * lpad + r];
           }
           av[ks] = x;
         }
-        for (int ct = 0; ct < (cpw >> 4); ++ct) {
-          const int cl = ct * 16 + li;
-          const uint32_t e0 = cl < ncl ? (uint32_t)((size_t)cl * lpad + rt * 16) : kOOB;
-          typename Quad<T>::acc acc = Quad<T>::tile_load(rs_wg, e0, kq);
+      };
+      T av[kNBMax / 4], avn[kNBMax / 4];
+      int rt = (j >> 4) + wv;
+      vload(rt, av);
+      for (; rt < (lpad >> 4); rt += kBW) {
+        vload(rt + kBW, avn);   // the next row tile's operand, in flight during this one
+        // four column tiles at a time: their loads in flight together
+        for (int ct0 = 0; ct0 < ntc; ct0 += 4) {
+          typename Quad<T>::acc acc[4];
+          uint32_t e0[4];
 #pragma unroll
-          for (int ks = 0; ks < kNBMax / 4; ++ks)
-            if (ks < nks) acc = Quad<T>::mfma(av[ks], F[cl * nbp + 4 * ks + kq], acc);
-          Quad<T>::tile_store(rs_wg, e0, kq, acc);
+          for (int u = 0; u < 4; ++u) {
+            const int cl = (ct0 + u) * 16 + li;
+            e0[u] = (ct0 + u < ntc && cl < ncl) ? (uint32_t)((size_t)cl * lpad + rt * 16) : kOOB;
+            acc[u] = Quad<T>::tile_load(rs_wg, e0[u], kq);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (ct0 + u < ntc) {
+              const int cl = (ct0 + u) * 16 + li;
+#pragma unroll
+              for (int ks = 0; ks < kNBMax / 4; ++ks)
+                if (ks < nks) acc[u] = Quad<T>::mfma(av[ks], F[cl * nbp + 4 * ks + kq], acc[u]);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) Quad<T>::tile_store(rs_wg, e0[u], kq, acc[u]);
         }
+#pragma unroll
+        for (int ks = 0; ks < kNBMax / 4; ++ks) av[ks] = avn[ks];
       }
       publish_slab();
       __syncthreads();
@@ -416,9 +444,105 @@ __global__ __launch_bounds__(kBT) void cpqr_blk_kernel(CpqrArgs a) {
     __syncthreads();
   };
 
+  // Columns whose downdated norm cancelled: bring their trailing rows [j, l) up
+  // to date with the panel's ib reflectors (Y0(:, c) -= V F(c, :)^T, then F(c, :)
+  // = 0, which keeps every later formula of the panel valid for them), recompute
+  // their norms in FP64 and write the slab back for the other workgroups. Local
+  // to the workgroup: no other workgroup waits for it.
+  auto refresh = [&](int ib, int j) {
+    constexpr int NF = 4;
+    if (tid == 0) sh[3] = 0;
+    __syncthreads();
+    for (int c = tid; c < ncl; c += kBT)
+      if (need[c] && sel[c] == -1) flist[atomicAdd(&sh[3], 1)] = c;
+    __syncthreads();
+    const int nflag = sh[3];
+    if (nflag == 0) return;
+    const __amdgpu_buffer_rsrc_t rs_V = rsrc(Vglob, (uint32_t)((size_t)nb * lpad * sizeof(T)));
+    for (int f0 = 0; f0 < nflag; f0 += NF) {
+      const int nf = min(NF, nflag - f0);
+      double ss[NF];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) ss[f] = 0.0;
+      // four consecutive rows per thread: V(r..r+3, s) is one 16-byte load
+      for (int qd = (j >> 2) + tid; 4 * qd < l; qd += kBT) {
+        double y[NF][4];
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+          for (int e2 = 0; e2 < 4; ++e2) {
+            const int r = 4 * qd + e2;
+            y[f][e2] = (f < nf && r >= j && r < l) ? (double)slab[(size_t)(c0 + flist[f0 + f]) * lpad + r] : 0.0;
+          }
+        for (int sb = 0; sb < ib; sb += 4) {
+          double vr[4][4];
+#pragma unroll
+          for (int s2 = 0; s2 < 4; ++s2) {
+            if (sb + s2 < ib) {
+              if constexpr (TALL) {
+                load4_sc1<T>(rs_V, (uint32_t)(((sb + s2) * lpad + 4 * qd) * sizeof(T)), vr[s2]);
+              } else {
+#pragma unroll
+                for (int e2 = 0; e2 < 4; ++e2) vr[s2][e2] = (double)Vl[(size_t)(sb + s2) * lpad + 4 * qd + e2];
+              }
+            } else {
+#pragma unroll
+              for (int e2 = 0; e2 < 4; ++e2) vr[s2][e2] = 0.0;
+            }
+          }
+#pragma unroll
+          for (int f = 0; f < NF; ++f) {
+            if (f < nf) {
+              const T* fc = F + flist[f0 + f] * nbp + sb;
+#pragma unroll
+              for (int s2 = 0; s2 < 4; ++s2) {
+                const double fv = (sb + s2 < ib) ? (double)fc[s2] : 0.0;
+#pragma unroll
+                for (int e2 = 0; e2 < 4; ++e2) y[f][e2] -= vr[s2][e2] * fv;
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          if (f < nf) {
+#pragma unroll
+            for (int e2 = 0; e2 < 4; ++e2) {
+              const int r = 4 * qd + e2;
+              if (r >= j && r < l) {
+                const T yt = (T)y[f][e2];
+                slab[(size_t)(c0 + flist[f0 + f]) * lpad + r] = yt;
+                ss[f] += (double)yt * (double)yt;
+              }
+            }
+          }
+        }
+      }
+      // per-column sums in a fixed order: waves, then the waves' partials
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const double w = wave_sum(ss[f]);
+        if (lane == 0) rfl[wv * NF + f] = w;
+      }
+      __syncthreads();
+      if (tid < nf) {
+        double t = 0.0;
+        for (int w2 = 0; w2 < kBW; ++w2) t += rfl[w2 * NF + tid];
+        const int c = flist[f0 + tid];
+        nu2[c] = t;
+        lim[c] = tol3z * t;
+        need[c] = 0;
+      }
+      __syncthreads();
+    }
+    for (int q = tid; q < nflag * nbp; q += kBT) F[flist[q / nbp] * nbp + q % nbp] = (T)0;
+    publish_slab();
+    __syncthreads();
+  };
+
   // Publish this workgroup's candidate for publish index e: the best active
-  // column's squared norm and index, the sum of the active squared norms, the
-  // recompute flag and the candidate's F row (panel entries [0, i)).
+  // column's squared norm and index, the sum of the active squared norms and
+  // the candidate's F row (panel entries [0, i)).
   auto publish = [&](int e, int i) {
     ArgMax best{-1.0, 0x7fffffff};
     double ssq = 0.0;
@@ -428,7 +552,6 @@ __global__ __launch_bounds__(kBT) void cpqr_blk_kernel(CpqrArgs a) {
         ssq += nu2[c];
         if (better(nu2[c], c0 + c, best.v, best.i)) { best.v = nu2[c]; best.i = c0 + c; }
       }
-      flag |= need[c];
     }
     best = bargmax_sum(best, ssq, flag, rd, ri, rd + kBW, ri + kBW);
     uint64_t* r = rec1 + ((size_t)(e & 1) * G + g) * kW1;
@@ -436,7 +559,6 @@ __global__ __launch_bounds__(kBT) void cpqr_blk_kernel(CpqrArgs a) {
     if (tid == 0) {
       cstore(r + 0, dbits(best.v));
       cstore(r + 1, dbits(ssq));
-      cstore(r + 2, (uint64_t)flag);
     }
     wait_all_mem();
     __syncthreads();
@@ -468,7 +590,6 @@ __global__ __launch_bounds__(kBT) void cpqr_blk_kernel(CpqrArgs a) {
         cand.v = bitsd(cload(r + 0));
         cand.i = (int)(uint32_t)(tag & 0xffffffffu);
         tot = bitsd(cload(r + 1));
-        flag = (int)cload(r + 2);
       }
     }
     if (tid == 0) sh[1] = 0;
@@ -490,15 +611,7 @@ __global__ __launch_bounds__(kBT) void cpqr_blk_kernel(CpqrArgs a) {
     }
     const ArgMax w = cand;
     if (any_tmo) stop = ST_TIMEOUT;
-    else if (flag) {
-      // a downdate cancelled somewhere: flush the panel, recompute the flagged
-      // norms and pick again
-      flush(i, j);
-      i = 0;
-      ++e;
-      publish(e, 0);
-      continue;
-    } else {
+    else {
       if (e == 0) { y0fro2 = tot; nu0sq = w.v; }
       if (!(tot == tot) || !(w.v == w.v) || isinf(tot) || isinf(w.v)) stop = ST_NONFINITE;
       else if (tolmode && tot <= a.tol * a.tol * y0fro2) stop = -1;
@@ -618,6 +731,8 @@ __global__ __launch_bounds__(kBT) void cpqr_blk_kernel(CpqrArgs a) {
         if (lane == 0) wv_[s] = acc;
       }
       if (tid < i) Vj[tid] = (double)Vl[(size_t)tid * lpad + j];
+      // v in FP64 for the sweep (rows above j are zero)
+      for (int r = tid; r < lpad; r += kBT) vd[r] = (double)Vl[(size_t)i * lpad + r];
     } else {
       // v differs from y only in row j
       if (tid < i) wv_[tid] += Vj[tid] * (vj - yj);
@@ -647,46 +762,52 @@ __global__ __launch_bounds__(kBT) void cpqr_blk_kernel(CpqrArgs a) {
     // and keeps U loads in flight; a pass's group sum is taken when its last unit
     // is consumed (the same unit index on every lane). The lane holding row j
     // keeps Y0(j, c) for the new row of S.
-    auto sweep = [&](const T* vsrc, int vbase, int qa, int qb) {
+    auto sweep = [&](const double* vsrc, int vbase, int qa, int qb) {
       constexpr int U = sizeof(T) == 4 ? 8 : 4;
       const int qpl = (qb - qa + R - 1) / R;
+      if (qpl <= 0) return;
       const int npass = (ncl + groups - 1) / groups;
       const int total = npass * qpl;
-      const int qj = j >> 2;
+      const int qj = j >> 2, jr = j & 3;
+      const int gcol = wv * gpw + gidx;
+      // (pass, quad) of the next unit to load and to consume, advanced by one per
+      // unit (the same sequence on every lane of a wave), and whether the load
+      // side's current column is active
+      int lps = 0, lt = 0, cps = 0, ct = 0;
+      bool lact = false;
       double dot = 0.0;
       for (int u0 = 0; u0 < total; u0 += U) {
         T x[U][4];
 #pragma unroll
         for (int v = 0; v < U; ++v) {
-          const int u = u0 + v;
-          const int ps = u / qpl, t = u - ps * qpl;
-          const int cl = ps * groups + wv * gpw + gidx;
-          const int qd = qa + rgi + R * t;
-          const bool ok = u < total && cl < ncl && qd < qb && sel[min(cl, cpw - 1)] == -1;
+          const int cl = lps * groups + gcol;
+          if (lt == 0) lact = cl < ncl && sel[min(cl, cpw - 1)] == -1;
+          const int qd = qa + rgi + R * lt;
+          const bool ok = u0 + v < total && lact && qd < qb;
           Quad<T>::load_raw(rs_wg, ok ? (uint32_t)(((size_t)cl * lpad + 4 * qd) * sizeof(T)) : kOOB, x[v]);
+          if (++lt == qpl) { lt = 0; ++lps; }
         }
 #pragma unroll
         for (int v = 0; v < U; ++v) {
-          const int u = u0 + v;
-          if (u >= total) continue;   // the same on every lane
-          const int ps = u / qpl, t = u - ps * qpl;
-          const int cl = ps * groups + wv * gpw + gidx;
-          const int qd = qa + rgi + R * t;
-          const int qv = min(qd, qb - 1);   // x is zero past qb
+          if (u0 + v >= total) break;   // the same on every lane
+          const int cl = cps * groups + gcol;
+          const int qd = qa + rgi + R * ct;
+          const double* vq = vsrc + 4 * min(qd, qb - 1) - vbase;   // x is zero past qb
 #pragma unroll
-          for (int e2 = 0; e2 < 4; ++e2) dot = fma((double)x[v][e2], (double)vsrc[4 * qv + e2 - vbase], dot);
-          if (qd == qj && cl < ncl) y0j[cl] = (double)x[v][j & 3];
-          if (t == qpl - 1) {
+          for (int e2 = 0; e2 < 4; ++e2) dot = fma((double)x[v][e2], vq[e2], dot);
+          if (qd == qj && cl < ncl) y0j[cl] = (double)x[v][jr];
+          if (ct == qpl - 1) {
             const double d = group_sum(dot, R);
             if (rgi == 0 && cl < ncl && sel[cl] == -1) dots[cl] += d;
             dot = 0.0;
           }
+          if (++ct == qpl) { ct = 0; ++cps; }
         }
       }
     };
     if constexpr (!TALL) {
       // rows below j of column i are zero, so the sweep may start at the quad of j
-      sweep(Vl + (size_t)i * lpad, 0, j4 >> 2, nq);
+      sweep(vd, 0, j4 >> 2, nq);
     } else {
       const __amdgpu_buffer_rsrc_t rs_v = rsrc(vglob, (uint32_t)((size_t)lpad * sizeof(T)));
       // v was stored by every workgroup with device-coherent stores: read it the same way
@@ -698,7 +819,7 @@ __global__ __launch_bounds__(kBT) void cpqr_blk_kernel(CpqrArgs a) {
 #pragma unroll
           for (int e2 = 0; e2 < 4; ++e2) {
             const int r = 4 * qd + e2;
-            vloc[r - cs] = (r < j || r >= l) ? (T)0 : (r == j ? vjT : (T)x[e2]);
+            vloc[r - cs] = (r < j || r >= l) ? 0.0 : (r == j ? vj : x[e2]);
           }
         }
         __syncthreads();
@@ -735,6 +856,7 @@ __global__ __launch_bounds__(kBT) void cpqr_blk_kernel(CpqrArgs a) {
     ++j;
     ++i;
     if (!tolmode && j >= kmax) break;   // fixed rank: nothing left to decide
+    refresh(i, j);
     if (i == nb) {
       flush(i, j);
       i = 0;
@@ -805,12 +927,12 @@ using namespace cb;
 // LDS bytes of one workgroup
 static size_t blk_lds_bytes(bool tall, int esz, int lpad, int nb, int cpw, int rpw, int vch, int kmax) {
   size_t b = (size_t)nb * (tall ? rpw : lpad) * esz;
-  if (tall) b += (size_t)vch * esz;
   b = (b + 15) & ~(size_t)15;
+  b += (size_t)(tall ? vch : lpad) * 8;
   b += (size_t)cpw * (((nb + 3) & ~3) + 1) * esz;
   b = (b + 15) & ~(size_t)15;
   b += (size_t)cpw * 8 * 5 + 3 * kNBMax * 8 + 4 * kBW * 8;
-  b += (size_t)cpw * 4 * 2 + 2 * kBW * 4 + (size_t)kmax * 4;
+  b += (size_t)cpw * 4 * 3 + 8 * kBW * 8 + 2 * kBW * 4 + (size_t)kmax * 4;
   return b;
 }
 
@@ -852,8 +974,8 @@ int cpqr_blk_plan(CpqrPlan& p, int esz, int l, int n, int kmax, int num_cus, int
   if (rpw > kBT) return 0;
   const int nb = 32;
   const size_t base = blk_lds_bytes(true, esz, lpad, nb, cpw, rpw, 0, kmax);
-  if (base + 4096 * (size_t)esz > budget) return 0;
-  int vch = (int)std::min<size_t>((size_t)lpad, ((budget - base) / esz) / 16 * 16);
+  if (base + 4096 * (size_t)8 > budget) return 0;
+  int vch = (int)std::min<size_t>((size_t)lpad, ((budget - base) / 8) / 16 * 16);
   vch = std::max(16, vch / 16 * 16);
   p.blk = 2;
   p.nb = nb;

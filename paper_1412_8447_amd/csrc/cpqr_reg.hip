@@ -10,6 +10,9 @@ using namespace cr;
 const void* cpqr_reg_fn_f32(int cfg);
 const void* cpqr_reg_fn_f64(int cfg);
 
+// IDCUR_CPQR_REGCFG=i restricts the search to table entry i, so that a test
+// can run every configuration on a matrix it covers; an entry that does not fit
+// then leaves the choice to the other kernels.
 int cpqr_reg_pick(int dtype_size, int l, int n, int num_cus, int* G, int* cols_per_wg) {
   const char* force = getenv("IDCUR_CPQR_REGCFG");
   const int forced = force ? atoi(force) : -1;

@@ -76,7 +76,7 @@ __device__ __forceinline__ f32x4 mfma16(u32x4 a, u32x4 b, f32x4 c) {
                                                    0, 0);
 }
 
-template <bool H, int NT, bool A_KC>
+template <bool H, int NT, bool A_KC, int D>
 __global__ __launch_bounds__(256, 2) void gemm16_kernel(Args p) {
   constexpr int BN = 16 * NT;
   constexpr int HN = NT / 2;                    // column blocks per wave
@@ -97,11 +97,14 @@ __global__ __launch_bounds__(256, 2) void gemm16_kernel(Args p) {
   const float s_in = p.scale ? p.scale[0] : 1.0f;
   const float s_out = p.scale ? p.scale[1] : 1.0f;
 
-  float fa[16];
-  u32x4 rb[BQ];
+  // D k-steps in registers: the loads of D k-steps are in flight while the
+  // matrix cores work on the k-step in LDS (a load takes microseconds under
+  // full-chip traffic, a k-step's products a few hundred cycles)
+  float fas[D][16];
+  u32x4 rbs[D][BQ];
 
   // ---- global -> registers (one k-step) -----------------------------------
-  auto gload = [&](int64_t k0) {
+  auto gload = [&](int64_t k0, float (&fa)[16], u32x4 (&rb)[BQ]) {
     const bool full = p.vec && (k0 + BK <= ke) && (m0 + BM <= p.M);
     if (A_KC) {
       // thread: rows r0 and r0 + 64, k = k0 + 8g .. +7
@@ -159,7 +162,7 @@ __global__ __launch_bounds__(256, 2) void gemm16_kernel(Args p) {
     }
   };
   // ---- registers -> LDS ------------------------------------------------------
-  auto sstore = [&](int buf) {
+  auto sstore = [&](int buf, const float (&fa)[16], const u32x4 (&rb)[BQ]) {
     if (A_KC) {
       const int r0 = tid >> 2, g = tid & 3;
 #pragma unroll
@@ -193,25 +196,37 @@ __global__ __launch_bounds__(256, 2) void gemm16_kernel(Args p) {
 
   const int64_t nk = ke > kb ? (ke - kb + BK - 1) / BK : 0;
   if (nk > 0) {
-    gload(kb);
-    sstore(0);
+    // k-step s is loaded into register stage s % D; k-step t is in LDS buffer
+    // t % 2 while it is multiplied. After the products of step t, step t + 1
+    // goes from its stage to LDS and step t + 1 + D is loaded into that stage.
+#pragma unroll
+    for (int s = 0; s < D; ++s)
+      if (s < nk) gload(kb + s * BK, fas[s], rbs[s]);
+    sstore(0, fas[0], rbs[0]);
+    if (D < nk) gload(kb + D * BK, fas[0], rbs[0]);
     __syncthreads();
-    for (int64_t it = 0; it < nk; ++it) {
-      const int buf = (int)(it & 1);
-      if (it + 1 < nk) gload(kb + (it + 1) * BK);
-      const u32x4* as = As[buf];
-      const u32x4* bs = Bs[buf];
-      u32x4 a[4];
+    for (int64_t t0 = 0; t0 < nk; t0 += D) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = as[(wm * 64 + i * 16 + (lane & 15)) * RS + (lane >> 4)];
+      for (int d = 0; d < D; ++d) {
+        const int64_t it = t0 + d;
+        if (it >= nk) break;
+        const int buf = (int)(it & 1);
+        const u32x4* as = As[buf];
+        const u32x4* bs = Bs[buf];
+        u32x4 a[4];
 #pragma unroll
-      for (int c = 0; c < HN; ++c) {
-        const u32x4 b = bs[(wn * HN * 16 + c * 16 + (lane & 15)) * RS + (lane >> 4)];
+        for (int i = 0; i < 4; ++i) a[i] = as[(wm * 64 + i * 16 + (lane & 15)) * RS + (lane >> 4)];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i][c] = mfma16<H>(a[i], b, acc[i][c]);
+        for (int c = 0; c < HN; ++c) {
+          const u32x4 b = bs[(wn * HN * 16 + c * 16 + (lane & 15)) * RS + (lane >> 4)];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[i][c] = mfma16<H>(a[i], b, acc[i][c]);
+        }
+        const int sn = (d + 1) % D;   // stage of k-step it + 1 (constant once unrolled)
+        if (it + 1 < nk) sstore(buf ^ 1, fas[sn], rbs[sn]);
+        if (it + 1 + D < nk) gload(kb + (it + 1 + D) * BK, fas[sn], rbs[sn]);
+        __syncthreads();
       }
-      if (it + 1 < nk) sstore(buf ^ 1);
-      __syncthreads();
     }
   }
 
@@ -234,11 +249,16 @@ __global__ __launch_bounds__(256, 2) void gemm16_kernel(Args p) {
   }
 }
 
+// register stages of the k-step prefetch: three where the registers allow it
+// (two waves per SIMD, 256 registers each), one for the widest tiles (more
+// stages there spill)
+constexpr int prefetch_stages(int nt) { return nt >= 14 ? 1 : 3; }
+
 template <bool H, int NT>
 hipError_t launch_nt(const Args& a, bool akc, hipStream_t s) {
   const unsigned grid = (unsigned)(8 * ((tiles_total(a) + 7) / 8));
-  if (akc) hipLaunchKernelGGL((gemm16_kernel<H, NT, true>), dim3(grid), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL((gemm16_kernel<H, NT, false>), dim3(grid), dim3(256), 0, s, a);
+  if (akc) hipLaunchKernelGGL((gemm16_kernel<H, NT, true, prefetch_stages(NT)>), dim3(grid), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((gemm16_kernel<H, NT, false, prefetch_stages(NT)>), dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -19,7 +19,7 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU container
     pytest.skip("no GPU", allow_module_level=True)
 
 import paper_1412_8447_amd as P  # noqa: E402
-from gpu_helpers import say, to_dev, clear_prefix, rel_err_id, check_perm  # noqa: E402
+from gpu_helpers import say, to_dev, clear_prefix, rel_err_id, check_perm, check_t_fp32  # noqa: E402
 
 
 def _det_case(m, n, k, seed, decay=8.0):
@@ -74,6 +74,8 @@ def test_id_col_det_fp32(m, n, k):
     c = clear_prefix(ref.qr.gaps, 1e-4)
     assert c >= min(k, 10)
     assert np.array_equal(J[:c], ref.J[:c])
+    # T element-wise: Y = A itself in the deterministic ID
+    check_t_fp32(A, J, k, got.T.cpu().numpy(), "det fp32")
     e_g, e_o = rel_err_id(A.astype(np.float64), J, got.T.cpu().numpy()), rel_err_id(A.astype(np.float64), ref.J, ref.T)
     assert e_g <= 1.05 * e_o
 
@@ -119,6 +121,9 @@ def test_id_col_sketched_matches_oracle(dtype, q):
     if dtype == torch.float64 and c == k:
         assert abs(e_g / e_o - 1) <= 1e-8
         assert np.abs(got.T.cpu().numpy() - ref.T).max() <= 1e-8 * max(1.0, np.abs(ref.T).max())
+    if dtype == torch.float32:
+        # T of the device's skeleton on the oracle's sketch of the same inputs
+        check_t_fp32(ref.Y, J, k, got.T.cpu().numpy(), f"sketch fp32 q={q}")
     assert e_g <= 1.05 * e_o
 
 
@@ -168,6 +173,10 @@ def test_two_sided_and_cur_det(dtype):
     cref = clear_prefix(ref.ts.col.qr.gaps, 1e-9 if dtype == torch.float64 else 1e-4)
     assert np.array_equal(J[:cref], ref.ts.col.J[:cref])
     # two-sided error equals the column-ID error (no extra error, Section 2.4)
+    if dtype == torch.float32:
+        # T and Tr element-wise: the column ID is of A itself, the row ID of C^T
+        check_t_fp32(A64, J, k, ts.T.cpu().numpy(), "two-sided T")
+        check_t_fp32(A64[:, J[:k]].T, I, k, ts.Tr.cpu().numpy(), "two-sided Tr")
     e2 = oracle.e_two_sided(A64, J, ts.T.cpu().numpy(), I, ts.Tr.cpu().numpy())
     e1 = oracle.e_id(A64, J, ts.T.cpu().numpy())
     tol = 1e-9 if dtype == torch.float64 else 2e-3
