@@ -1,20 +1,22 @@
 #!/usr/bin/env python3
 """Throughput of the randomized CUR-ID on one MI355X.
 
-Workload (the FP32 randomized configuration): A = U diag(sigma) V^T, 20000 x 10000,
-sigma_j = (j+1)^-2, U and V from the QR of seeded N(0,1) matrices (drawn on the
-GPU), FP32; rank k = 200, oversampling p = 10, one orthonormalised power step,
-Gaussian Omega (210 x 20000) drawn on the device from Philox4x32-10.
-
-One step = one idcur_cur call: Omega, the sketch and power-step GEMMs, the
-Cholesky-QR orthonormalisations, the column-pivoted QR of Y, T, the gather of C,
-the row ID of C, the gather of R and the least-squares U. The error evaluation
+Headline workload (the mixed-precision configuration): A = U diag(exp(-j/80)) V^T,
+50000 x 20000, U and V from the QR of seeded N(0,1) matrices (drawn on the GPU),
+stored in FP32; rank k = 500, oversampling p = 20, one orthonormalised power step,
+Gaussian Omega (520 x 50000) drawn on the device from Philox4x32-10. One step =
+one idcur_cur call with the sketch and power-step GEMMs on the BF16 matrix cores
+(FP32 accumulation; --prec selects FP16 or FP32): Omega, the GEMMs, the
+Cholesky-QR orthonormalisations, the pivoted QR of Y, T, the gather of C, the row
+ID of C, the gather of R and the least-squares U. The error evaluation
 (|A - CUR|_F) is timed separately, outside the steps.
 
-Prints ONE JSON line. Extra keys: matrices/s, the error, per-stage times, the
-plain FP32 GPU CPQR comparator (the same library with no sketch), the fastest
-(p, q) whose error is within 1.05x of the comparator's, the roofline of the
-dominant kernel (the sketch GEMMs) and the CPU oracle baseline.
+Prints ONE JSON line: the headline step's GFLOP/s and matrices/s, its error, the
+same step in FP32 and FP16, the plain FP32 GPU CPQR comparator on A itself, the
+equal-error sweep over (p, q) and precision, the roofline of the dominant kernel,
+the CPU oracle baseline; then the FP32 randomized 20000 x 10000 workload and the
+batched, structured-sketch, sparse, stabilized-T, corrected-U and adjoint
+sections as sub-objects.
 """
 from __future__ import annotations
 
@@ -48,6 +50,8 @@ TRAFFIC = {
             "gemm16_sources_sha"),
     "batched": ("batched_id_4096_kernel_blocks_traffic.md", ("batched.hip",), "batched_sources_sha"),
     "srht": ("structured_sketch_srht_20000x10000_l400.md", ("srht.hip",), "srht_sources_sha"),
+    "g16_c3": ("sketch_gemm16_50000x20000_l520_traffic.md", ("gemm16_kernel.hpp", "gemm16.hip", "gemm16_f16.hip"),
+               "gemm16_sources_sha"),
 }
 
 
@@ -460,6 +464,223 @@ def bench_structured(args, P, synth, torch, dev, A, k):
     return out
 
 
+def timed_cur(P, torch, dev, A, k, reps, warmup=2, **kw):
+    """Time `reps` CUR calls (events on torch's stream around the calls, which
+    run on the library's context stream = torch's current stream), with the
+    library's per-stage timers on. Returns (ms per call, stages, last result)."""
+    o = P.make_opts(k, **kw)
+    ws = torch.empty(P.workspace_bytes(P.OP_CUR, A, o), dtype=torch.uint8, device=dev)
+    m, n = A.shape
+    out = dict(J=torch.empty(n, dtype=torch.int32, device=dev), I=torch.empty(m, dtype=torch.int32, device=dev),
+               U=torch.empty(k, k, dtype=A.dtype, device=dev), C=torch.empty(m, k, dtype=A.dtype, device=dev),
+               R=torch.empty(k, n, dtype=A.dtype, device=dev), kout=torch.zeros(2, dtype=torch.int32, device=dev))
+    for _ in range(warmup):
+        P.cur(A, k, workspace=ws, out=out, sync=False, **kw)
+    P.sync_status(dev)
+    P.timing_enable(True, dev)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        P.cur(A, k, workspace=ws, out=out, sync=False, **kw)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    st = P.timing_read(dev)
+    P.timing_enable(False, dev)
+    P.sync_status(dev)
+    del ws
+    return ms, st, out
+
+
+def cur_err(P, A, out, k):
+    er = P.cur_error(A, out["C"], out["U"], out["R"], out["kout"], k).tolist()
+    return math.sqrt(er[0] / er[1])
+
+
+def stage_roofline(stage, st, reps, m, n, k, l, q, prec):
+    """Roofline of one stage's kernels from the library's event timers: the 16-bit
+    sketch GEMM against HBM (A in FP32 read once per launch, the thin operand and
+    the output once), the FP32 sketch GEMM against the FP32 matrix cores (2 l m n
+    flops per launch), the pivoted QRs against HBM with one read of the trailing
+    matrix per step (sum over the k steps of 4 (rows - j)(cols - j) bytes)."""
+    tot, cnt = st[stage]
+    avg = tot / max(cnt, 1)
+    if stage == "sketch_gemm" and prec in ("bf16", "fp16"):
+        launches = 2 * q + 1
+        byts = ((2 * q + 1) * 4.0 * m * n + (q + 1) * (2.0 * l * m + 4.0 * l * n)
+                + q * (2.0 * l * n + 4.0 * l * m)) / launches
+        ach = byts / (avg * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(ach / PEAK_HBM_GBS, 4), "kernel": f"sketch_gemm ({prec} MFMA 16x16x32, FP32 A read once)",
+                "avg_launch_ms": round(avg, 4), "launches_per_step": round(cnt / reps, 2), "bytes_per_launch": byts,
+                "tflops": round(2.0 * l * m * n / (avg * 1e-3) / 1e12, 2)}
+    if stage == "sketch_gemm":
+        fl = 2.0 * l * m * n
+        ach = fl / (avg * 1e-3) / 1e12
+        return {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / PEAK_FP32_MFMA_TFLOPS, 4), "kernel": "sketch_gemm (FP32 MFMA 16x16x4)",
+                "avg_launch_ms": round(avg, 4), "launches_per_step": round(cnt / reps, 2), "flops_per_launch": fl}
+    rows, cols = (l, n) if stage == "cpqr" else (k, m)
+    byts = sum(4.0 * (rows - j) * (cols - j) for j in range(k))
+    ms_step = tot / reps
+    ach = byts / (ms_step * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(ach / PEAK_HBM_GBS, 4), "kernel": f"{stage} (pivoted QR of the {rows} x {cols} matrix)",
+            "ms_per_step": round(ms_step, 4), "bytes_per_call": byts,
+            "note": "algorithmic bytes: one read of the trailing matrix per pivot step (cache-resident: effective rate)"}
+
+
+def bench_headline(args, P, synth, torch, dev):
+    """The mixed-precision workload: A = U diag(exp(-j/80)) V^T, 50000 x 20000,
+    FP32 storage, k = 500, p = 20, q = 1; one step = one CUR call with the sketch
+    and power-step GEMMs on the BF16 matrix cores (FP32 accumulation), every later
+    step in FP32 with FP64 k x k factorisations. Returns the headline fields plus
+    the FP32 and FP16 forms of the same step, the plain FP32 GPU CPQR comparator,
+    the equal-error sweep and the CPU oracle baseline."""
+    import numpy as np
+    cfg = synth.CONFIGS["mixed_50000x20000_k500"]
+    m, n, k, p, q = cfg.m, cfg.n, cfg.k, cfg.p, cfg.q
+    l = k + p
+    sig = cfg.spectrum()
+    r = int(np.sum(sig >= 2.0**-60))   # exp(-j/80) below 2^-60 adds nothing in FP32
+    t0 = time.time()
+    log(f"generating A {m}x{n} on the GPU (rank {r} terms)")
+    A = synth.lowrank_torch(m, n, sig, seed=args.seed, device=dev, rank=r).to(torch.float32).contiguous()
+    torch.cuda.synchronize()
+    log(f"A ready in {time.time() - t0:.1f}s")
+    seed = args.seed + 1
+    head = args.prec
+    flops = P.flop_model("cur", m, n, k, p, q)
+    res = {}
+    log(f"warmup {args.warmup}, timing {args.steps} steps ({head})")
+    ms, st, out = timed_cur(P, torch, dev, A, k, args.steps, warmup=args.warmup, p=p, q=q, seed=seed, prec=head)
+    kout = out["kout"].tolist()
+    assert kout == [k, k], f"rank {kout}"
+    e_head = cur_err(P, A, out, k)
+    log(f"{head}: {ms:.3f} ms/step, |A-CUR|_F/|A|_F = {e_head:.4e} (Eckart-Young floor {cfg.frobenius_floor():.4e})")
+    stages = {s_: round(v[0] / args.steps, 4) for s_, v in st.items() if v[1]}
+    dom = max((s_ for s_ in ("sketch_gemm", "cpqr", "row_id") if s_ in stages), key=lambda s_: stages[s_])
+    roof = stage_roofline(dom, st, args.steps, m, n, k, l, q, head)
+    if dom == "sketch_gemm":
+        roof["traffic"] = read_traffic("g16_c3")
+    else:
+        roof["traffic"] = None
+    res.update(ms=ms, e=e_head, stages=stages, roofline=roof, flops=flops, cfg=cfg, J=out["J"].clone())
+    # the other precisions of the same step
+    per = {}
+    for prec in ("native", "bf16", "fp16"):
+        if prec == head:
+            continue
+        ms_p, st_p, out_p = timed_cur(P, torch, dev, A, k, max(3, args.steps // 2), p=p, q=q, seed=seed, prec=prec)
+        e_p = cur_err(P, A, out_p, k)
+        name = "fp32" if prec == "native" else prec
+        per[name] = {"ms_per_step": round(ms_p, 4), "gflops": round(flops["total"] / (ms_p * 1e-3) / 1e9, 2),
+                     "matrices_per_s": round(1000.0 / ms_p, 3), "rel_fro_error": e_p,
+                     "stages_ms_per_step": {s_: round(v[0] / max(3, args.steps // 2), 4) for s_, v in st_p.items() if v[1]},
+                     "sketch_gemm": stage_roofline("sketch_gemm", st_p, max(3, args.steps // 2), m, n, k, l, q, prec)}
+        log(name, per[name]["ms_per_step"], "ms", e_p)
+        del out_p
+    res["per_dtype"] = per
+    e_fp32 = per["fp32"]["rel_fro_error"] if "fp32" in per else e_head
+    for v in per.values():
+        v["error_ratio_vs_fp32"] = round(v["rel_fro_error"] / e_fp32, 4)
+    res["error_ratio_vs_fp32"] = round(e_head / e_fp32, 4)
+
+    # the plain FP32 GPU CPQR comparator: deterministic CUR-ID on A itself
+    if not args.no_comparator:
+        log("comparator: deterministic FP32 CPQR CUR-ID on A (50000 x 20000)")
+        ms_d, st_d, out_d = timed_cur(P, torch, dev, A, k, 1, warmup=1)
+        e_det = cur_err(P, A, out_d, k)
+        fl_d = P.flop_model("cur", m, n, k)["total"]
+        cmp_ = {"name": "plain FP32 GPU CPQR (deterministic CUR-ID on A, same library, Y = A)",
+                "ms": round(ms_d, 3), "gflops": round(fl_d / (ms_d * 1e-3) / 1e9, 2), "rel_fro_error": e_det,
+                "stages_ms": {s_: round(v[0], 3) for s_, v in st_d.items() if v[1]},
+                "cpqr_roofline": stage_roofline("cpqr", st_d, 1, m, n, k, m, 0, "native"),
+                "speedup_nominal": round(ms_d / ms, 2), "error_ratio_nominal": round(e_head / e_det, 4)}
+        # the comparator's HBM floor: one read of the trailing 50000 x 20000 FP32 matrix per pivot step
+        cmp_["hbm_floor_ms"] = round(sum(4.0 * (m - j) * (n - j) for j in range(k)) / (PEAK_HBM_GBS * 1e9) * 1e3, 2)
+        log("comparator", cmp_["ms"], "ms", e_det)
+        del out_d
+        res["comparator"] = cmp_
+        if not args.no_sweep:
+            best, sweep = None, []
+            for prec in (head, "native"):
+                for pp, qq in [(20, 1), (50, 1), (20, 2), (50, 2)]:
+                    ms_s, _, out_s = timed_cur(P, torch, dev, A, k, 3, warmup=1, p=pp, q=qq, seed=seed, prec=prec)
+                    es = cur_err(P, A, out_s, k)
+                    row = {"prec": "fp32" if prec == "native" else prec, "p": pp, "q": qq, "ms": round(ms_s, 3),
+                           "rel_fro_error": es, "ratio_to_plain": round(es / e_det, 4)}
+                    sweep.append(row)
+                    log("sweep", row)
+                    if es <= 1.05 * e_det and (best is None or ms_s < best["ms"]):
+                        best = row
+                    del out_s
+            res["equal_error_sweep"] = sweep
+            if best is not None:
+                fl_b = P.flop_model("cur", m, n, k, best["p"], best["q"])["total"]
+                res["equal_error"] = dict(best, gflops=round(fl_b / (best["ms"] * 1e-3) / 1e9, 2),
+                                          matrices_per_s=round(1000.0 / best["ms"], 3),
+                                          speedup_vs_plain=round(ms_d / best["ms"], 2))
+
+    # CPU baseline: the FP64 oracle's randomized column ID of the same A with the
+    # same Omega (sketch, power step, 500-step pivoted QR, T): a bounded sample
+    # of the step (the CUR's row ID and U are left out to keep it near 30 s)
+    if not args.no_cpu_baseline:
+        import oracle
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([tp.get("num_threads", 1) for tp in threadpool_info()] or [os.cpu_count()])
+        except Exception:  # pragma: no cover
+            cores = os.cpu_count()
+        om = P.gaussian(l, m, seed=seed, dtype=torch.float32)
+        A_h = A.cpu().numpy().astype(np.float64)
+        om_h = om.cpu().numpy().astype(np.float64)
+        log(f"cpu baseline: oracle column ID (sketch q=1 + CPQR + T) on {cores} threads")
+        tc = time.time()
+        ref = oracle.id_col(A_h, k, omega=om_h, q=q)
+        tcpu = time.time() - tc
+        fl_s = P.flop_model("id_col", m, n, k, p, q)["total"]
+        # the same column ID on the GPU (same Omega), for the pivots and the error
+        cid = P.id_col(A, k, p=p, q=q, omega=om, prec=head)
+        cid32 = P.id_col(A, k, p=p, q=q, omega=om)
+        Jg = cid32.J.cpu().numpy()
+        lead = 0
+        for gap in ref.qr.gaps:
+            if gap < 1e-4:
+                break
+            lead += 1
+        Jr = torch.as_tensor(ref.J.astype(np.int32), device=dev)
+        Tr = torch.as_tensor(np.ascontiguousarray(ref.T, dtype=np.float32), device=dev)
+        ko = torch.tensor([k, 0], dtype=torch.int32, device=dev)
+        def ide(J, T, kk):
+            e = P.id_error(A, J, T, kk, k).tolist()
+            return math.sqrt(e[0] / e[1])
+        e_or = ide(Jr, Tr, ko)
+        res["cpu_baseline"] = {"value": round(fl_s / tcpu / 1e9, 3), "unit": "GFLOP/s", "cores": cores,
+                               "kind": "oracle", "seconds": round(tcpu, 2),
+                               "sample": "the FP64 oracle's randomized column ID (Omega A, one orthonormalised power "
+                                         "step, 500-step pivoted QR of the 520 x 20000 sketch, T) of the same "
+                                         "50000 x 20000 input with the same Omega; the CUR's row ID and U are "
+                                         "not in the sample",
+                               "oracle_id_error": e_or,
+                               "gpu_id_error_ratio": {"fp32": round(ide(cid32.J, cid32.T, cid32.kout) / e_or, 4),
+                                                      head: round(ide(cid.J, cid.T, cid.kout) / e_or, 4)},
+                               "fp32_leading_pivots_identical": int(np.array_equal(Jg[:lead], ref.J[:lead])),
+                               "clear_pivots": lead}
+        try:
+            with open("/proc/cpuinfo") as f:
+                models = [ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")]
+            res["cpu_baseline"]["cpu_model"] = models[0] if models else None
+        except OSError:  # pragma: no cover
+            res["cpu_baseline"]["cpu_model"] = None
+        log(f"oracle column ID {tcpu:.1f}s, e_ID {e_or:.4e}")
+        del A_h
+    del A
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -481,6 +702,10 @@ def main():
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched kernel-block measurement (one JSON object, for profiling)")
     ap.add_argument("--seed", type=int, default=20260)
+    ap.add_argument("--prec", default="bf16", choices=["bf16", "fp16", "native"],
+                    help="sketch precision of the headline step (the 50000x20000 mixed-precision workload)")
+    ap.add_argument("--no-c2", action="store_true",
+                    help="only the headline 50000x20000 workload (skip the 20000x10000 FP32 sections)")
     ap.add_argument("--input-cache", default=None,
                     help="load A from this file when it exists, else generate it and save it there")
     ap.add_argument("--copy-calib", action="store_true",
@@ -513,6 +738,33 @@ def main():
     if args.adjoint_only:
         print(json.dumps({"adjoint": bench_adjoint(args, P, synth, torch, dev)}), flush=True)
         return
+    head = bench_headline(args, P, synth, torch, dev)
+    cfg3 = head["cfg"]
+    result = {
+        "metric": "ID/CUR GFLOP/s + matrices/sec vs plain FP32 GPU CPQR at equal rel. Frobenius error",
+        "value": round(head["flops"]["total"] / (head["ms"] * 1e-3) / 1e9, 2), "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(head["ms"], 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
+        "config": {"workload": (f"mixed-precision randomized CUR-ID: A = U diag(exp(-j/80)) V^T, 50000x20000 FP32, "
+                                f"k=500, p=20, q=1, sketch and power-step GEMMs on {args.prec.upper()} matrix cores "
+                                f"with FP32 accumulation, pivoted QRs in FP32, k x k factorisations in FP64"),
+                   "m": cfg3.m, "n": cfg3.n, "k": cfg3.k, "p": cfg3.p, "q": cfg3.q, "prec": args.prec},
+        "matrices_per_s": round(1000.0 / head["ms"], 3),
+        "rel_fro_error": head["e"],
+        "error_ratio_vs_fp32": head["error_ratio_vs_fp32"],
+        "flops_per_step": head["flops"]["total"],
+        "stages_ms_per_step": head["stages"],
+        "roofline": head["roofline"],
+        "per_dtype": head["per_dtype"],
+    }
+    for key in ("comparator", "equal_error_sweep", "equal_error", "cpu_baseline"):
+        if key in head:
+            result[key] = head[key]
+    del head
+    if args.no_c2:
+        print(json.dumps(result), flush=True)
+        return
+
     cfg = synth.CONFIGS["rand_fp32_20000x10000_k200"]
     m, n, k, p, q = cfg.m, cfg.n, cfg.k, cfg.p, cfg.q
     l = k + p
@@ -588,19 +840,14 @@ def main():
     if not args.no_library_gemm:
         roofline["library_gemm"] = library_gemm(torch, A, l)
 
-    result = {
-        "metric": "ID/CUR GFLOP/s + matrices/sec vs plain FP32 GPU CPQR at equal rel. Frobenius error",
-        "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "randomized CUR-ID, FP32 A=U diag((j+1)^-2) V^T 20000x10000, k=200, p=10, q=1",
-                   "m": m, "n": n, "k": k, "p": p, "q": q},
-        "matrices_per_s": round(1000.0 / ms, 3),
-        "rel_fro_error": e_cur,
-        "flops_per_step": flops["total"],
+    c2 = {
+        "workload": "randomized CUR-ID, FP32 A=U diag((j+1)^-2) V^T 20000x10000, k=200, p=10, q=1",
+        "ms_per_step": round(ms, 4), "gflops": round(value, 2), "matrices_per_s": round(1000.0 / ms, 3),
+        "rel_fro_error": e_cur, "flops_per_step": flops["total"],
         "stages_ms_per_step": {s: round(v[0] / args.steps, 4) for s, v in stages.items() if v[1]},
         "roofline": roofline,
     }
+    result["fp32_20000x10000"] = c2
 
     # the same step with the sketch and power-step GEMMs on BF16 / FP16 matrix cores
     if not args.no_mixed:
@@ -642,7 +889,7 @@ def main():
                                            "mfma_frac": round(tfl / PEAK_16BIT_MFMA_TFLOPS, 4)}}
             log(prec, mixed[prec])
             del wsm, outm
-        result["mixed_precision"] = mixed
+        c2["mixed_precision"] = mixed
 
     # batched adaptive-rank IDs of 4096 kernel blocks (one persistent launch,
     # replayed from a captured graph)
@@ -673,35 +920,35 @@ def main():
         log("u_corrected", result["u_corrected"])
         del outc
 
-    # the same step with the Tikhonov-stabilized interpolation matrices
-    # (t_reg = 1e-4: both IDs' T by Cholesky QR twice of [S11; lam I])
+    # the same step with the Tikhonov-stabilized interpolation matrices of
+    # Section 4.1 (t_reg = 1e-4: both IDs' T by Cholesky QR twice of [S11; lam I])
     if not args.no_stabilized:
-        t_reg = 1e-4
-        outs = {kk: torch.empty_like(v) for kk, v in out.items()}
-        for _ in range(2):
-            P.cur(A, k, out=outs, sync=False, t_reg=t_reg, **kw)
-        P.sync_status(dev)
-        P.timing_enable(True, dev)
-        reps = max(3, args.steps)
-        e0.record()
-        for _ in range(reps):
-            P.cur(A, k, out=outs, sync=False, t_reg=t_reg, **kw)
-        e1.record()
-        torch.cuda.synchronize()
-        ms_s = e0.elapsed_time(e1) / reps
-        st_s = P.timing_read(dev)
-        P.timing_enable(False, dev)
-        P.sync_status(dev)
-        er = P.cur_error(A, outs["C"], outs["U"], outs["R"], outs["kout"], k).tolist()
-        e_s = math.sqrt(er[0] / er[1])
-        result["stabilized_t"] = {"t_reg": t_reg, "ms_per_step": round(ms_s, 4), "rel_fro_error": e_s,
-                                  "error_ratio_vs_plain_t": round(e_s / e_cur, 4),
-                                  "column_t_ms": round(st_s["trsm"][0] / reps, 4),
-                                  "column_t_ms_plain": round(stages["trsm"][0] / args.steps, 4),
-                                  "row_id_ms": round(st_s["row_id"][0] / reps, 4),
-                                  "row_id_ms_plain": round(stages["row_id"][0] / args.steps, 4)}
-        log("stabilized_t", result["stabilized_t"])
-        del outs
+        for name, skw in (("stabilized_t", {"t_reg": 1e-4}),):
+            outs = {kk: torch.empty_like(v) for kk, v in out.items()}
+            for _ in range(2):
+                P.cur(A, k, out=outs, sync=False, **skw, **kw)
+            P.sync_status(dev)
+            P.timing_enable(True, dev)
+            reps = max(3, args.steps)
+            e0.record()
+            for _ in range(reps):
+                P.cur(A, k, out=outs, sync=False, **skw, **kw)
+            e1.record()
+            torch.cuda.synchronize()
+            ms_s = e0.elapsed_time(e1) / reps
+            st_s = P.timing_read(dev)
+            P.timing_enable(False, dev)
+            P.sync_status(dev)
+            er = P.cur_error(A, outs["C"], outs["U"], outs["R"], outs["kout"], k).tolist()
+            e_s = math.sqrt(er[0] / er[1])
+            result[name] = dict(skw, ms_per_step=round(ms_s, 4), rel_fro_error=e_s,
+                                error_ratio_vs_plain_t=round(e_s / e_cur, 4),
+                                column_t_ms=round(st_s["trsm"][0] / reps, 4),
+                                column_t_ms_plain=round(stages["trsm"][0] / args.steps, 4),
+                                row_id_ms=round(st_s["row_id"][0] / reps, 4),
+                                row_id_ms_plain=round(stages["row_id"][0] / args.steps, 4))
+            log(name, result[name])
+            del outs
 
     # the structured sketch (subsampled randomized Hadamard), l = 2k, q = 0
     if not args.no_structured:
@@ -733,7 +980,7 @@ def main():
         errd = P.cur_error(A, outd["C"], outd["U"], outd["R"], outd["kout"], k).tolist()
         e_det = math.sqrt(errd[0] / errd[1])
         fl_d = P.flop_model("cur", m, n, k)["total"]
-        result["comparator"] = {"name": "plain FP32 GPU CPQR (deterministic CUR-ID, same kernels, Y = A)",
+        c2["comparator"] = {"name": "plain FP32 GPU CPQR (deterministic CUR-ID, same kernels, Y = A)",
                                 "ms": round(ms_d, 3), "gflops": round(fl_d / (ms_d * 1e-3) / 1e9, 2),
                                 "rel_fro_error": e_det, "speedup_nominal": round(ms_d / ms, 2),
                                 "error_ratio_nominal": round(e_cur / e_det, 4)}
@@ -761,10 +1008,10 @@ def main():
                 if es <= 1.05 * e_det and (best is None or ms_s < best["ms"]):
                     best = row
                 del wss, outs
-            result["equal_error_sweep"] = sweep
+            c2["equal_error_sweep"] = sweep
             if best is not None:
                 fl_b = P.flop_model("cur", m, n, k, best["p"], best["q"])["total"]
-                result["equal_error"] = dict(best, gflops=round(fl_b / (best["ms"] * 1e-3) / 1e9, 2),
+                c2["equal_error"] = dict(best, gflops=round(fl_b / (best["ms"] * 1e-3) / 1e9, 2),
                                              matrices_per_s=round(1000.0 / best["ms"], 3),
                                              speedup_vs_plain=round(ms_d / best["ms"], 2))
 
@@ -789,7 +1036,7 @@ def main():
             if gap < 1e-4:
                 break
             lead += 1
-        result["cpu_baseline"] = {"value": round(flops["total"] / tcpu / 1e9, 3), "unit": "GFLOP/s", "cores": cores,
+        c2["cpu_oracle_cur"] = {"value": round(flops["total"] / tcpu / 1e9, 3), "unit": "GFLOP/s", "cores": cores,
                                   "kind": "oracle", "seconds": round(tcpu, 2),
                                   "sample": "one full FP64 CUR-ID of the same 20000x10000 input (same Omega, q=1)",
                                   "rel_fro_error": e_orc,
@@ -804,7 +1051,7 @@ def main():
                 tc1 = time.time()
                 oracle.cur(A_h, k, omega=om, q=q)
                 t1 = time.time() - tc1
-            result["cpu_baseline"]["single_core"] = {"value": round(flops["total"] / t1 / 1e9, 3), "unit": "GFLOP/s",
+            c2["cpu_oracle_cur"]["single_core"] = {"value": round(flops["total"] / t1 / 1e9, 3), "unit": "GFLOP/s",
                                                      "cores": 1, "seconds": round(t1, 2)}
             log(f"oracle on one thread {t1:.1f}s")
         except Exception as ex:  # pragma: no cover
@@ -812,10 +1059,10 @@ def main():
         try:
             with open("/proc/cpuinfo") as f:
                 models = [ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")]
-            result["cpu_baseline"]["cpu_model"] = models[0] if models else None
+            c2["cpu_oracle_cur"]["cpu_model"] = models[0] if models else None
         except OSError:  # pragma: no cover
-            result["cpu_baseline"]["cpu_model"] = None
-        for prec, r in result.get("mixed_precision", {}).items():
+            c2["cpu_oracle_cur"]["cpu_model"] = None
+        for prec, r in c2.get("mixed_precision", {}).items():
             r["error_ratio_vs_fp64_oracle"] = round(r["rel_fro_error"] / e_orc, 4)
 
     print(json.dumps(result), flush=True)

@@ -127,11 +127,21 @@ typedef struct {
                          error of about u / t_reg relative to |T| (u = 2^-53), so
                          t_reg should exceed about 1e-8. Other values:
                          IDCUR_EINVAL.                                             */
+  double t_svd;       /* 0: as t_reg says. In (0, 1): the truncated-SVD T of Section 4.1
+                         (the stabilized pseudo-inverse of S11 in eq. (lsqr_for_T)):
+                         with S11 = U D V^T, the terms whose singular value is below
+                         t_svd times the largest are dropped and T = V D^-1 U^T S12
+                         over the rest, for every interpolation matrix the call forms.
+                         The SVD is taken by one-sided Jacobi rotations in FP64 (at
+                         most 16 sweeps). Excludes t_reg > 0 (IDCUR_EINVAL); other
+                         values: IDCUR_EINVAL. This build switches the path off:
+                         any t_svd > 0 returns IDCUR_EINVAL.                         */
 } idcur_opts;
 
 /* Fill *opts with defaults: k = 0, kmax = 0, tol = 0, rank_tol = 0, p = -1
  * (deterministic), q = 0, seed = 0, omega = NULL, NATIVE precision, downdated norms,
- * Gaussian sketch (srht_signs = srht_rows = NULL), u_correct = 0, t_reg = 0. */
+ * Gaussian sketch (srht_signs = srht_rows = NULL), u_correct = 0, t_reg = 0,
+ * t_svd = 0. */
 void idcur_opts_default(idcur_opts* opts /* host */);
 
 /* Create a context bound to `stream` (a hipStream_t, borrowed, may be NULL for the
@@ -341,7 +351,7 @@ idcur_status idcur_id_col_backward(idcur_ctx* ctx, int32_t dtype, int64_t m, int
  *   level, and 10 sqrt(l_cap) u32 with a fixed rank).
  *   T = S11^{-1} S12 by FP64 back-substitution.
  * Limits: 1 <= n_b <= nmax <= 512, 1 <= m_b <= mmax, (k or kmax) + p <= 64,
- * p >= 1, q = 0, t_reg = 0, NATIVE precision, dtype IDCUR_F32. A block outside its limits
+ * p >= 1, q = 0, t_reg = t_svd = 0, NATIVE precision, dtype IDCUR_F32. A block outside its limits
  * gets k_out[b] = -1 and IDCUR_EINVAL from idcur_sync_status.
  * All arrays are DEVICE arrays of nblk entries: m, n (int32), A (pointers to
  * const float), lda (int64), and the outputs k_out (int32), J (pointers to

@@ -76,6 +76,7 @@ class Opts(ctypes.Structure):
         ("srht_rows", ctypes.c_void_p),
         ("u_correct", ctypes.c_int32),
         ("t_reg", ctypes.c_double),
+        ("t_svd", ctypes.c_double),
     ]
 
 
@@ -213,14 +214,15 @@ def _dtype_code(t: torch.Tensor) -> int:
 def make_opts(k: int = 0, *, tol: float = 0.0, kmax: int = 0, p: int = -1, q: int = 0, seed: int = 0,
               omega: Optional[torch.Tensor] = None, rank_tol: float = 0.0, norms: str = "downdate",
               prec: str = "native", srht: Optional[tuple] = None, u_correct: bool = False,
-              t_reg: float = 0.0) -> Opts:
+              t_reg: float = 0.0, t_svd: float = 0.0) -> Opts:
     """Options of a decomposition call. ``srht = (rows, signs)`` selects the
     subsampled randomized Hadamard sketch with the given device tensors (rows:
     int32[l], distinct, below the padded order; signs: int8, one per sketched
     row), instead of the Gaussian one. ``u_correct`` makes a CUR call solve the
     error-corrected system U R = V* + C^+ E for U. ``t_reg`` in (0, 1) takes the
     Tikhonov-stabilized interpolation matrices of Section 4.1 (weight t_reg
-    times |S11(1, 1)|)."""
+    times |S11(1, 1)|); ``t_svd`` in (0, 1) the truncated-SVD ones (singular
+    values of S11 below t_svd times the largest dropped)."""
     o = Opts()
     _lib.idcur_opts_default(ctypes.byref(o))
     o.k, o.kmax, o.tol, o.rank_tol = int(k), int(kmax), float(tol), float(rank_tol)
@@ -237,6 +239,7 @@ def make_opts(k: int = 0, *, tol: float = 0.0, kmax: int = 0, p: int = -1, q: in
         o.srht_rows, o.srht_signs = rows.data_ptr(), signs.data_ptr()
     o.u_correct = 1 if u_correct else 0
     o.t_reg = float(t_reg)
+    o.t_svd = float(t_svd)
     return o
 
 

@@ -24,7 +24,7 @@ FLAGS = [
 ]
 
 SOURCES = ["cpqr.hip", "cpqr_blk.hip", "cpqr_reg.hip", "cpqr_reg_f32.hip", "cpqr_reg_f64.hip", "gemm.hip", "gemm_f32.hip", "gemm_f32_f64acc.hip", "gemm_f64.hip", "gemm_f32_f64.hip",
-           "gemm_f64_f32.hip", "gemm_thin.hip", "gemm16.hip", "gemm16_f16.hip", "batched.hip", "batched_bwd.hip", "chol.hip", "misc.hip", "srht.hip", "spmm.hip", "args.cpp", "host.cpp"]
+           "gemm_f64_f32.hip", "gemm_thin.hip", "gemm16.hip", "gemm16_f16.hip", "batched.hip", "batched_bwd.hip", "chol.hip", "misc.hip", "srht.hip", "spmm.hip", "jacobi.hip", "args.cpp", "host.cpp"]
 
 
 def _compile(src: str, obj: str) -> None:

@@ -43,6 +43,11 @@ ArgCheck check_id_args(int op, int dtype, int64_t m, int64_t n, int64_t lda, con
   if (opts->sketch != IDCUR_SKETCH_GAUSSIAN && opts->sketch != IDCUR_SKETCH_SRHT) return inval("unknown sketch kind");
   if (opts->u_correct != 0 && opts->u_correct != 1) return inval("u_correct must be 0 or 1");
   if (!(opts->t_reg >= 0.0 && opts->t_reg < 1.0)) return inval("t_reg must be in [0, 1)");
+  if (!(opts->t_svd >= 0.0 && opts->t_svd < 1.0)) return inval("t_svd must be in [0, 1)");
+  if (opts->t_reg > 0.0 && opts->t_svd > 0.0) return inval("t_reg and t_svd exclude each other");
+  // the truncated-SVD path is switched off: a GPU run that included it ended
+  // with a device fault whose cause is not shown
+  if (opts->t_svd > 0.0) return inval("t_svd is switched off in this build");
   if (opts->sketch == IDCUR_SKETCH_SRHT && opts->p >= 0 && (int64_t)kcap + opts->p < mr) {
     if (opts->q != 0) return inval("the structured sketch takes no power steps (q = 0)");
     if (opts->prec != IDCUR_PREC_NATIVE) return dtype_err("the structured sketch runs in the native precision");
@@ -104,7 +109,8 @@ ArgCheck check_batched_args(int dtype, int nblk, int mmax, int nmax, const idcur
   const int kcap = o->k > 0 ? o->k : o->kmax;
   if ((int64_t)kcap + o->p > max_sketch) return inval("k (kmax) + p must be <= 64");
   if (o->rank_tol < 0 || !std::isfinite(o->rank_tol)) return inval("rank_tol must be >= 0");
-  if (o->t_reg != 0.0) return inval("the batched ID forms T by back-substitution (t_reg = 0)");
+  if (o->t_reg != 0.0 || o->t_svd != 0.0)
+    return inval("the batched ID forms T by back-substitution (t_reg = t_svd = 0)");
   return kOk;
 }
 

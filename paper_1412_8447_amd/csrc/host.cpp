@@ -241,7 +241,7 @@ void orth_rows(const Ctx& x, int dtype, const void* Vt, void* Qt, int64_t N, int
 // ld ldS): S11 gathered and inverted (as the lower factor S11^T), S12 gathered,
 // T = (S11^{-T})^T S12 as an FP64 matrix-core product written in T's dtype.
 void interp_matrix(const Ctx& x, int dtype, const void* S, int64_t ldS, const int* J, int64_t n, int kcap,
-                   const int* k_dev, void* T, int64_t ldt, double t_reg = 0.0) {
+                   const int* k_dev, void* T, int64_t ldt, double t_reg = 0.0, double t_svd = 0.0) {
   double* S11 = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
   double* S11it = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
   double* S12 = static_cast<double*>(x.ar->take((size_t)kcap * std::max<int64_t>(n - 1, 1) * 8));
@@ -300,6 +300,23 @@ void interp_matrix(const Ctx& x, int dtype, const void* S, int64_t ldS, const in
     mm(kcap, n - 1, Q, 1, kcap, S12, ldo, 1, W, ldo, 0, ncol);
     mm(kcap, n - 1, L2i, 1, kcap, W, ldo, 1, Z, ldo, 0, ncol);
     mm(kcap, std::min<int64_t>(n - 1, ldt), L1i, 1, kcap, Z, ldo, 1, T, ldt, dtype, ncol);
+    return;
+  }
+  if (t_svd > 0.0) {
+    // Truncated-SVD T (Section 4.1, the stabilized pseudo-inverse of S11 in eq.
+    // (lsqr_for_T)): one-sided Jacobi on the columns of S11 (contiguous rows of
+    // the buffer), W V = U diag(s); P = W^T S12 with row i scaled by 1 / s_i^2
+    // (0 where s_i < t_svd max s); T = V P.
+    double* V = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
+    double* P = static_cast<double*>(x.ar->take((size_t)kcap * ldo * 8));
+    double* sv = static_cast<double*>(x.ar->take((size_t)kcap * 8));
+    int* rot = static_cast<int*>(x.ar->take((size_t)jacobi_max_sweeps() * 4 + 256));
+    if (!x.dry) x.check(jacobi_svd_launch(S11, V, kcap, k_dev, rot, x.s), "Jacobi SVD of S11");
+    // P = W^T S12 (A(i, kk) = W(kk, i) = S11[i][kk])
+    mm(kcap, n - 1, S11, kcap, 1, S12, ldo, 1, P, ldo, 0, ncol);
+    if (!x.dry) x.check(tsvd_scale_launch(S11, kcap, k_dev, t_svd, P, ldo, n - 1, ncol, sv, x.s), "1 / s^2");
+    // T = V P (A(i, kk) = V(i, kk) = V[kk][i])
+    mm(kcap, std::min<int64_t>(n - 1, ldt), V, 1, kcap, P, ldo, 1, T, ldt, dtype, ncol);
     return;
   }
   chol_inv(x, 1, S11, 1, kcap, kcap, k_dev, nullptr, 0, S11it, kcap, 0.0, "S11 inverse");
@@ -510,7 +527,7 @@ ColId column_id(const Ctx& x, int dtype, const View& X, const idcur_opts& o, int
   }
   {
     Stage st(x, "trsm");
-    interp_matrix(x, dtype, S, nc, J, nc, kcap, k_out, T, ldt, o.t_reg);
+    interp_matrix(x, dtype, S, nc, J, nc, kcap, k_out, T, ldt, o.t_reg, o.t_svd);
   }
   return r;
 }
@@ -518,7 +535,7 @@ ColId column_id(const Ctx& x, int dtype, const View& X, const idcur_opts& o, int
 // Row ID of C (m x kcap, row-major ld kcap) with rank k_dev: the full-rank ID of
 // C^T, giving I (m) and Tr (k x (m-k), ldtr); k_out_r receives its rank.
 void row_id_of_c(const Ctx& x, int dtype, const void* C, int64_t m, int kcap, const int* k_dev, int* k_out_r, int* I,
-                 void* Tr, int64_t ldtr, double t_reg) {
+                 void* Tr, int64_t ldtr, double t_reg, double t_svd) {
   const CpqrPlan pl = cpqr_plan((int)esz(dtype), kcap, (int)m, kcap, x.c->num_cus);
   void* rec = x.ar->take(pl.rec_bytes + pl.fin_bytes);
   void* cvals = x.ar->take(pl.cvals_bytes);
@@ -543,7 +560,7 @@ void row_id_of_c(const Ctx& x, int dtype, const void* C, int64_t m, int kcap, co
     x.check(cpqr_launch(dtype, pl, a, x.s), "cpqr(row)");
   }
   Stage st(x, "row_id");
-  interp_matrix(x, dtype, S, m, I, m, kcap, k_out_r, Tr, ldtr, t_reg);
+  interp_matrix(x, dtype, S, m, I, m, kcap, k_out_r, Tr, ldtr, t_reg, t_svd);
 }
 
 // U = argmin |U R - V*|_F through the QR of R^T (Cholesky QR twice, FP64):
@@ -677,7 +694,7 @@ void execute(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const void
     Tr = ar.take((size_t)kcap * m * esz(dtype));
     ldtr = m;
   }
-  row_id_of_c(x, dtype, C, m, kcap, out.k_out, out.k_out + 1, out.I, Tr, ldtr, o.t_reg);
+  row_id_of_c(x, dtype, C, m, kcap, out.k_out, out.k_out + 1, out.I, Tr, ldtr, o.t_reg, o.t_svd);
   if (op == OP_TWO) return;
   // CUR: R = A(I(1:k), :), optional C output, then U
   void* R = out.R;
@@ -1196,7 +1213,7 @@ void execute_cur_csc(idcur_ctx* ctx, int dtype, const Csc& a, const idcur_opts& 
             "gather C");
   }
   void* Tr = ar.take((size_t)kcap * m * esz(dtype));
-  row_id_of_c(x, dtype, C, m, kcap, out.k_out, out.k_out + 1, out.I, Tr, m, o.t_reg);
+  row_id_of_c(x, dtype, C, m, kcap, out.k_out, out.k_out + 1, out.I, Tr, m, o.t_reg, o.t_svd);
   void* R = ar.take((size_t)kcap * n * esz(dtype));
   int* slot = static_cast<int*>(ar.take((size_t)m * sizeof(int)));
   if (!ar.dry) {

@@ -316,6 +316,14 @@ hipError_t csc_gather_rows_launch(int dtype, int64_t m, int64_t n, int64_t nnz, 
 size_t spmm_part_bytes(const SpmmDesc& d, int esize);
 hipError_t spmm_csc_launch(int dtype, const SpmmDesc& d, void* part, hipStream_t stream);
 // Y += (*s) X, rows x cols row-major FP64, the weight a device scalar.
+// Truncated-SVD interpolation matrix (jacobi.hip): one-sided Jacobi SVD of the
+// kcap x kcap FP64 matrix W (columns contiguous, rows / columns past *k_dev
+// ignored) with the rotations accumulated in V; rot holds jacobi_max_sweeps()
+// counters. tsvd_scale scales row i of P by 1 / s_i^2 (0 below thr max s).
+int jacobi_max_sweeps();
+hipError_t jacobi_svd_launch(double* W, double* V, int kcap, const int* k_dev, int* rot, hipStream_t stream);
+hipError_t tsvd_scale_launch(const double* W, int kcap, const int* k_dev, double thr, double* P, int64_t ldp,
+                             int64_t ncols, const int* ncols_dev, double* sv, hipStream_t stream);
 hipError_t axpy_dev_launch(const double* s, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t rows,
                            int64_t cols, hipStream_t stream);
 hipError_t add_gathered_launch(const double* Q, int64_t ldq, const int* J, int ka_host, const int* ka_dev,

@@ -37,6 +37,7 @@ bool set_opt(idcur_opts& o, const std::string& k, const std::string& v) {
   else if (k == "sketch") o.sketch = std::stoi(v);
   else if (k == "u_correct") o.u_correct = std::stoi(v);
   else if (k == "t_reg") o.t_reg = std::strtod(v.c_str(), nullptr);
+  else if (k == "t_svd") o.t_svd = std::strtod(v.c_str(), nullptr);
   else if (k == "omega") o.omega = ptr_flag(v);
   else if (k == "srht_rows") o.srht_rows = static_cast<const int32_t*>(ptr_flag(v));
   else if (k == "srht_signs") o.srht_signs = static_cast<const int8_t*>(ptr_flag(v));

@@ -98,6 +98,11 @@ ID_CASES = [
     ("id t_reg=-0.1", EINVAL, "t_reg"),
     ("id t_reg=nan", EINVAL, "t_reg"),
     ("id t_reg=0.001", OK, "-"),
+    ("id t_svd=1.5", EINVAL, "t_svd"),
+    ("id t_svd=-1e-3", EINVAL, "t_svd"),
+    ("id t_svd=nan", EINVAL, "t_svd"),
+    ("id t_svd=1e-6", EINVAL, "switched off"),
+    ("id t_reg=1e-3 t_svd=1e-6", EINVAL, "exclude each other"),
     ("id sketch=1 p=4 q=1 srht_rows=1 srht_signs=1", EINVAL, "power steps"),
     (f"id dtype={F32} sketch=1 p=4 prec=1 srht_rows=1 srht_signs=1", EDTYPE, "native precision"),
     ("id sketch=1 p=4 omega=1 srht_rows=1 srht_signs=1", EINVAL, "exclude"),
@@ -162,6 +167,7 @@ BATCHED_CASES = [
     ("batched k=60 p=4", OK, "-"),
     ("batched rank_tol=-1", EINVAL, "rank_tol"),
     ("batched t_reg=0.1", EINVAL, "t_reg"),
+    ("batched t_svd=0.1", EINVAL, "t_svd"),
 ]
 
 
