@@ -52,6 +52,7 @@ TRAFFIC = {
     "srht": ("structured_sketch_srht_20000x10000_l400.md", ("srht.hip",), "srht_sources_sha"),
     "g16_c3": ("sketch_gemm16_50000x20000_l520_traffic.md", ("gemm16_kernel.hpp", "gemm16.hip", "gemm16_f16.hip"),
                "gemm16_sources_sha"),
+    "blk_c3": ("cpqr_blk_500x50000_k500_traffic.md", ("cpqr_blk.hip",), "cpqr_blk_sources_sha"),
 }
 
 
@@ -524,10 +525,11 @@ def stage_roofline(stage, st, reps, m, n, k, l, q, prec):
     rows, cols = (l, n) if stage == "cpqr" else (k, m)
     byts = sum(4.0 * (rows - j) * (cols - j) for j in range(k))
     ms_step = tot / reps
-    ach = byts / (ms_step * 1e-3) / 1e9
+    ach = byts / (avg * 1e-3) / 1e9   # one launch per call
     return {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(ach / PEAK_HBM_GBS, 4), "kernel": f"{stage} (pivoted QR of the {rows} x {cols} matrix)",
-            "ms_per_step": round(ms_step, 4), "bytes_per_call": byts,
+            "ms_per_step": round(ms_step, 4), "avg_launch_ms": round(avg, 4),
+            "launches_per_step": round(cnt / reps, 2), "bytes_per_call": byts,
             "note": "algorithmic bytes: one read of the trailing matrix per pivot step (cache-resident: effective rate)"}
 
 
@@ -545,8 +547,16 @@ def bench_headline(args, P, synth, torch, dev):
     sig = cfg.spectrum()
     r = int(np.sum(sig >= 2.0**-60))   # exp(-j/80) below 2^-60 adds nothing in FP32
     t0 = time.time()
-    log(f"generating A {m}x{n} on the GPU (rank {r} terms)")
-    A = synth.lowrank_torch(m, n, sig, seed=args.seed, device=dev, rank=r).to(torch.float32).contiguous()
+    if args.headline_cache and os.path.exists(args.headline_cache):
+        # (profiled runs: torch's QR of the random factors is left out of the trace)
+        log(f"loading A from {args.headline_cache}")
+        A = torch.load(args.headline_cache, weights_only=True).to(dev).contiguous()
+        assert A.shape == (m, n) and A.dtype == torch.float32
+    else:
+        log(f"generating A {m}x{n} on the GPU (rank {r} terms)")
+        A = synth.lowrank_torch(m, n, sig, seed=args.seed, device=dev, rank=r).to(torch.float32).contiguous()
+        if args.headline_cache:
+            torch.save(A.cpu(), args.headline_cache)
     torch.cuda.synchronize()
     log(f"A ready in {time.time() - t0:.1f}s")
     seed = args.seed + 1
@@ -560,12 +570,11 @@ def bench_headline(args, P, synth, torch, dev):
     e_head = cur_err(P, A, out, k)
     log(f"{head}: {ms:.3f} ms/step, |A-CUR|_F/|A|_F = {e_head:.4e} (Eckart-Young floor {cfg.frobenius_floor():.4e})")
     stages = {s_: round(v[0] / args.steps, 4) for s_, v in st.items() if v[1]}
-    dom = max((s_ for s_ in ("sketch_gemm", "cpqr", "row_id") if s_ in stages), key=lambda s_: stages[s_])
+    # the dominant kernel: the sketch / power GEMMs, the pivoted QR of the sketch,
+    # or the row ID's pivoted QR (row_cpqr times its launch alone)
+    dom = max((s_ for s_ in ("sketch_gemm", "cpqr", "row_cpqr") if s_ in stages), key=lambda s_: stages[s_])
     roof = stage_roofline(dom, st, args.steps, m, n, k, l, q, head)
-    if dom == "sketch_gemm":
-        roof["traffic"] = read_traffic("g16_c3")
-    else:
-        roof["traffic"] = None
+    roof["traffic"] = read_traffic({"sketch_gemm": "g16_c3", "row_cpqr": "blk_c3"}[dom]) if dom != "cpqr" else None
     res.update(ms=ms, e=e_head, stages=stages, roofline=roof, flops=flops, cfg=cfg, J=out["J"].clone())
     # the other precisions of the same step
     per = {}
@@ -706,6 +715,8 @@ def main():
                     help="sketch precision of the headline step (the 50000x20000 mixed-precision workload)")
     ap.add_argument("--no-c2", action="store_true",
                     help="only the headline 50000x20000 workload (skip the 20000x10000 FP32 sections)")
+    ap.add_argument("--headline-cache", default=None,
+                    help="file holding the 50000x20000 headline matrix: loaded when present, else written")
     ap.add_argument("--input-cache", default=None,
                     help="load A from this file when it exists, else generate it and save it there")
     ap.add_argument("--copy-calib", action="store_true",

@@ -408,7 +408,45 @@ __global__ __launch_bounds__(kBT) void cpqr_blk_kernel(CpqrArgs a) {
       T av[kNBMax / 4], avn[kNBMax / 4];
       int rt = (j >> 4) + wv;
       vload(rt, av);
-      for (; rt < (lpad >> 4); rt += kBW) {
+      const int nrt = lpad >> 4;
+      if (ntc <= 4) {
+        // at most 64 columns: a row tile is one group of four column tiles, and
+        // the next row tile's slab tiles (and V operand) load while this one's
+        // products run; tiles past the last row tile read zero, stores drop
+        auto tiles = [&](int r, typename Quad<T>::acc (&acc)[4], uint32_t (&e0)[4]) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int cl = u * 16 + li;
+            e0[u] = (r < nrt && u < ntc && cl < ncl) ? (uint32_t)((size_t)cl * lpad + r * 16) : kOOB;
+            acc[u] = Quad<T>::tile_load(rs_wg, e0[u], kq);
+          }
+        };
+        typename Quad<T>::acc acc[4], accn[4];
+        uint32_t e0[4], e0n[4];
+        tiles(rt, acc, e0);
+        for (; rt < nrt; rt += kBW) {
+          vload(rt + kBW, avn);
+          tiles(rt + kBW, accn, e0n);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (u < ntc) {
+              const int cl = u * 16 + li;
+#pragma unroll
+              for (int ks = 0; ks < kNBMax / 4; ++ks)
+                if (ks < nks) acc[u] = Quad<T>::mfma(av[ks], F[cl * nbp + 4 * ks + kq], acc[u]);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            Quad<T>::tile_store(rs_wg, e0[u], kq, acc[u]);
+            acc[u] = accn[u];
+            e0[u] = e0n[u];
+          }
+#pragma unroll
+          for (int ks = 0; ks < kNBMax / 4; ++ks) av[ks] = avn[ks];
+        }
+      } else
+      for (; rt < nrt; rt += kBW) {
         vload(rt + kBW, avn);   // the next row tile's operand, in flight during this one
         // four column tiles at a time: their loads in flight together
         for (int ct0 = 0; ct0 < ntc; ct0 += 4) {
@@ -789,13 +827,16 @@ __global__ __launch_bounds__(kBT) void cpqr_blk_kernel(CpqrArgs a) {
         }
 #pragma unroll
         for (int v = 0; v < U; ++v) {
-          if (u0 + v >= total) break;   // the same on every lane
+          if (u0 + v >= total) continue;   // the same on every lane (the tail of the last batch)
           const int cl = cps * groups + gcol;
           const int qd = qa + rgi + R * ct;
           const double* vq = vsrc + 4 * min(qd, qb - 1) - vbase;   // x is zero past qb
 #pragma unroll
           for (int e2 = 0; e2 < 4; ++e2) dot = fma((double)x[v][e2], vq[e2], dot);
-          if (qd == qj && cl < ncl) y0j[cl] = (double)x[v][jr];
+          if (qd == qj && cl < ncl) {
+            const T xj = jr == 0 ? x[v][0] : (jr == 1 ? x[v][1] : (jr == 2 ? x[v][2] : x[v][3]));
+            y0j[cl] = (double)xj;
+          }
           if (ct == qpl - 1) {
             const double d = group_sum(dot, R);
             if (rgi == 0 && cl < ncl && sel[cl] == -1) dots[cl] += d;

@@ -557,6 +557,7 @@ void row_id_of_c(const Ctx& x, int dtype, const void* C, int64_t m, int kcap, co
     a.S = S; a.ldS = m; a.J = I; a.k_out = k_out_r; a.status = x.c->dstatus;
     a.gslab = gslab; a.rec = rec; a.cvals = cvals;
     a.fin = reinterpret_cast<int*>(static_cast<char*>(rec) + pl.rec_bytes);
+    Stage sk(x, "row_cpqr");   // the pivoted QR launch alone (inside the row_id stage)
     x.check(cpqr_launch(dtype, pl, a, x.s), "cpqr(row)");
   }
   Stage st(x, "row_id");
