@@ -144,7 +144,7 @@ EXPORTED = ("idcur_opts_default", "idcur_create", "idcur_set_stream", "idcur_des
             "idcur_id_col_csc_workspace_bytes", "idcur_id_col_csc", "idcur_id_col_noalloc",
             "idcur_cur_csc_workspace_bytes", "idcur_cur_csc")
 
-STAGES = ("omega", "pack", "sketch_gemm", "orth", "cpqr", "trsm", "gather", "row_id", "u_solve", "error", "backward",
+STAGES = ("omega", "pack", "sketch_gemm", "orth", "cpqr", "trsm", "gather", "row_id", "row_cpqr", "u_solve", "error", "backward",
           "batched", "srht", "spmm")
 
 
