@@ -3,12 +3,14 @@
 // order split-K reduction. BF16 instantiations live here, FP16 ones in
 // gemm16_f16.hip.
 #include "gemm16_kernel.hpp"
+#include "gemm16w_kernel.hpp"
 
 #include <cmath>
 
 namespace idcur {
 namespace g16 {
 hipError_t launch_bf16(int nt, const Args& a, bool akc, hipStream_t s) { return launch_h<false>(nt, a, akc, s); }
+hipError_t launch_wide_bf16(const Args& a, bool akc, int cb, hipStream_t s) { return launch_wide<false>(a, akc, cb, s); }
 }  // namespace g16
 
 namespace {
@@ -126,7 +128,23 @@ __global__ void scale_kernel(const float* part, int nparts, float* scale) {
 
 }  // namespace
 
+// The wide form (gemm16w_kernel.hpp) covers 256 < N <= 576 in one column tile
+// of 80-row stripes, one workgroup per CU, when the operands admit whole
+// vectors: K a multiple of 8 (>= 8), A rows 16-byte aligned (k contiguous) or
+// 8-byte aligned with M even (row index contiguous), B rows 16-byte aligned.
+static bool wide_ok(int64_t M, int64_t N, int64_t K, bool akc, bool vec) {
+  return g16::wide_cb(N) > 0 && vec && K >= 8 && K % 8 == 0 && M >= 2 && (akc || M % 2 == 0);
+}
+
 int gemm16_pick_splitk(int64_t M, int64_t N, int64_t K, int num_cus) {
+  if (g16::wide_cb(N) > 0 && K >= 8 && K % 8 == 0) {
+    // one workgroup per CU: split K only when the stripes leave half the CUs idle
+    const int64_t stripes = ceil_div(M, g16::WBM);
+    if (2 * stripes >= num_cus) return 1;
+    int64_t s = num_cus / stripes;
+    s = std::min<int64_t>(s, std::max<int64_t>(1, K / 1024));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(s, 64));
+  }
   int nt, gy;
   pick_cols(N, &nt, &gy);
   const int64_t stripes = ceil_div(M, BM) * gy;
@@ -163,7 +181,15 @@ hipError_t gemm16_launch(const Gemm16Desc& d, void* part, hipStream_t stream, hi
   a.vec = avec && bvec;
   a.gx = (int)ceil_div(d.M, BM); a.gy = gy; a.gz = splitk;
   if (ev0) (void)hipEventRecord(ev0, stream);
-  hipError_t e = d.fp16 ? g16::launch_fp16(nt, a, akc, stream) : g16::launch_bf16(nt, a, akc, stream);
+  hipError_t e;
+  if (wide_ok(d.M, d.N, d.K, akc, a.vec)) {
+    a.gx = (int)ceil_div(d.M, g16::WBM);
+    a.gy = 1;
+    const int cb = g16::wide_cb(d.N);
+    e = d.fp16 ? g16::launch_wide_fp16(a, akc, cb, stream) : g16::launch_wide_bf16(a, akc, cb, stream);
+  } else {
+    e = d.fp16 ? g16::launch_fp16(nt, a, akc, stream) : g16::launch_bf16(nt, a, akc, stream);
+  }
   if (ev1) (void)hipEventRecord(ev1, stream);
   if (e != hipSuccess || splitk == 1) return e;
   const int64_t total = d.M * d.N;
