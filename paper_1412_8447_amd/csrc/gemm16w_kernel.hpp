@@ -1,13 +1,14 @@
 // Wide form of the 16-bit thin-output GEMM (gemm16_kernel.hpp) for 256 < N <=
-// 576 output columns, the sketch width of rank-500 decompositions (Section 5.1;
+// 640 output columns, the sketch width of rank-500 decompositions (Section 5.1;
 // the power steps of Section 5.3): one workgroup computes an 80-row stripe of C
 // over all columns, so that its stripe of A (FP32, the big operand) is fetched
 // from memory once. With column tiles of at most 256, the same launch would
 // fetch every stripe of A once per tile.
 //
-// Four waves split the columns (CB blocks of 16 each) and share the 80 rows
-// (five row blocks); the accumulators, 5 x CB MFMA blocks per lane, take most of
-// a lane's registers, so the kernel runs one workgroup per CU. Every global load
+// Eight waves split the columns (CB blocks of 16 each) and share the 80 rows
+// (five row blocks), two waves per SIMD, so that one wave's loads are in flight
+// while the other's products run; the B stage of all columns fills most of LDS,
+// so the kernel runs one workgroup per CU. Every global load
 // is unconditional, from a clamped address inside the operand: rows of A past M
 // and columns of B past N only feed outputs that are never stored, and 8-k
 // chunks past the end of the K split are cleared (by select) before they reach
@@ -25,13 +26,16 @@ namespace g16 {
 constexpr int WRB = 5;          // row blocks of 16 in a stripe
 constexpr int WBM = 16 * WRB;   // stripe height
 
+constexpr int WNW = 8;            // waves
+constexpr int WNT = 64 * WNW;     // threads
+
 template <bool H, bool A_KC, int CB, int D>
-__global__ __launch_bounds__(256, 1) void gemm16w_kernel(Args p) {
-  constexpr int BN = 64 * CB;                                  // 4 waves x CB blocks x 16 columns
+__global__ __launch_bounds__(WNT, 1) void gemm16w_kernel(Args p) {
+  constexpr int BN = 16 * WNW * CB;                            // WNW waves x CB blocks x 16 columns
   constexpr int FA = A_KC ? 8 : 16;                            // floats per A chunk
   constexpr int NCA = A_KC ? WBM * 4 : (WBM / 2) * 4;          // A chunks per k-step
-  constexpr int CA = (NCA + 255) / 256;                        // per thread
-  static_assert((BN * 4) % 256 == 0, "B chunks split evenly");
+  constexpr int CA = (NCA + WNT - 1) / WNT;                    // per thread
+  static_assert((BN * 4) % WNT == 0 && BN * 4 / WNT == CB, "B chunks split evenly");
   __shared__ u32x4 As[2][WBM * RS];
   __shared__ u32x4 Bs[2][BN * RS];
 
@@ -48,15 +52,15 @@ __global__ __launch_bounds__(256, 1) void gemm16w_kernel(Args p) {
   const float s_out = p.scale ? p.scale[1] : 1.0f;
   const int64_t mlast = A_KC ? p.M - 1 : p.M - 2;   // last row (pair) of A
 
-  // A chunk c of this thread (q = min(tid + 256 c, NCA - 1)):
+  // A chunk c of this thread (q = min(tid + 512 c, NCA - 1)):
   //   A_KC:  row q / 4, k = 8 (q % 4) .. +7
   //   else:  rows 2 (q % 40), +1, k = 8 (q / 40) .. +7
   auto a_row = [&](int c) {
-    const int q = min(tid + 256 * c, NCA - 1);
+    const int q = min(tid + WNT * c, NCA - 1);
     return A_KC ? q >> 2 : 2 * (q % (WBM / 2));
   };
   auto a_kg = [&](int c) {
-    const int q = min(tid + 256 * c, NCA - 1);
+    const int q = min(tid + WNT * c, NCA - 1);
     return A_KC ? (q & 3) : q / (WBM / 2);
   };
 
@@ -68,24 +72,31 @@ __global__ __launch_bounds__(256, 1) void gemm16w_kernel(Args p) {
     for (int c = 0; c < CA; ++c) {
       const int64_t gi = min(m0 + a_row(c), mlast);
       const int64_t kc = min(k0 + 8 * a_kg(c), ke - 8);
+      // A is read once: non-temporal loads, so that its stream does not push
+      // the thin operand B (read by every stripe) out of L2
+      typedef float nf4 __attribute__((ext_vector_type(4)));
+      typedef float nf2 __attribute__((ext_vector_type(2)));
       if (A_KC) {
         const float* src = p.A + gi * p.sam + kc;
-        const float4 u = *reinterpret_cast<const float4*>(src);
-        const float4 v = *reinterpret_cast<const float4*>(src + 4);
-        fa[c][0] = u.x; fa[c][1] = u.y; fa[c][2] = u.z; fa[c][3] = u.w;
-        fa[c][4] = v.x; fa[c][5] = v.y; fa[c][6] = v.z; fa[c][7] = v.w;
+        const nf4 u = __builtin_nontemporal_load(reinterpret_cast<const nf4*>(src));
+        const nf4 v = __builtin_nontemporal_load(reinterpret_cast<const nf4*>(src + 4));
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          fa[c][e] = u[e];
+          fa[c][4 + e] = v[e];
+        }
       } else {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          const float2 u = *reinterpret_cast<const float2*>(p.A + (kc + e) * p.sak + gi);
-          fa[c][e] = u.x;
-          fa[c][8 + e] = u.y;
+          const nf2 u = __builtin_nontemporal_load(reinterpret_cast<const nf2*>(p.A + (kc + e) * p.sak + gi));
+          fa[c][e] = u[0];
+          fa[c][8 + e] = u[1];
         }
       }
     }
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
-      const int q = tid + 256 * c;
+      const int q = tid + WNT * c;
       const int64_t gj = min((int64_t)(q >> 2), p.N - 1);
       const int64_t kc = min(k0 + 8 * (q & 3), ke - 8);
       rb[c] = *reinterpret_cast<const u32x4*>(p.B + gj * p.ldb + kc);
@@ -94,7 +105,7 @@ __global__ __launch_bounds__(256, 1) void gemm16w_kernel(Args p) {
   auto sstore = [&](int buf, int64_t k0, const float (&fa)[CA][FA], const u32x4 (&rb)[CB]) {
 #pragma unroll
     for (int c = 0; c < CA; ++c) {
-      if (c + 1 < CA || NCA % 256 == 0 || tid + 256 * c < NCA) {
+      if (c + 1 < CA || NCA % WNT == 0 || tid + WNT * c < NCA) {
         const bool kv = k0 + 8 * a_kg(c) < ke;   // whole chunk in the split (K % 8 == 0)
         const int r = a_row(c), g = a_kg(c);
         float f[8];
@@ -110,7 +121,7 @@ __global__ __launch_bounds__(256, 1) void gemm16w_kernel(Args p) {
     }
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
-      const int q = tid + 256 * c;
+      const int q = tid + WNT * c;
       const bool kv = k0 + 8 * (q & 3) < ke;
       Bs[buf][(q >> 2) * RS + (q & 3)] = kv ? rb[c] : u32x4{0u, 0u, 0u, 0u};
     }
@@ -178,19 +189,19 @@ __global__ __launch_bounds__(256, 1) void gemm16w_kernel(Args p) {
 // register stages of the prefetch
 constexpr int kWideStages = 2;
 
-// column blocks per wave for N columns (BN = 64 CB >= N), or 0 when the wide
+// column blocks per wave for N columns (BN = 128 CB >= N), or 0 when the wide
 // form does not apply
-inline int wide_cb(int64_t N) { return N > 256 && N <= 384 ? 6 : (N > 384 && N <= 576 ? 9 : 0); }
+inline int wide_cb(int64_t N) { return N > 256 && N <= 384 ? 3 : (N > 384 && N <= 640 ? 5 : 0); }
 
 template <bool H>
 hipError_t launch_wide(const Args& a, bool akc, int cb, hipStream_t s) {
   const unsigned grid = (unsigned)(8 * (((int64_t)a.gx * a.gz + 7) / 8));
-  if (cb == 6) {
-    if (akc) hipLaunchKernelGGL((gemm16w_kernel<H, true, 6, kWideStages>), dim3(grid), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((gemm16w_kernel<H, false, 6, kWideStages>), dim3(grid), dim3(256), 0, s, a);
+  if (cb == 3) {
+    if (akc) hipLaunchKernelGGL((gemm16w_kernel<H, true, 3, kWideStages>), dim3(grid), dim3(WNT), 0, s, a);
+    else hipLaunchKernelGGL((gemm16w_kernel<H, false, 3, kWideStages>), dim3(grid), dim3(WNT), 0, s, a);
   } else {
-    if (akc) hipLaunchKernelGGL((gemm16w_kernel<H, true, 9, kWideStages>), dim3(grid), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((gemm16w_kernel<H, false, 9, kWideStages>), dim3(grid), dim3(256), 0, s, a);
+    if (akc) hipLaunchKernelGGL((gemm16w_kernel<H, true, 5, kWideStages>), dim3(grid), dim3(WNT), 0, s, a);
+    else hipLaunchKernelGGL((gemm16w_kernel<H, false, 5, kWideStages>), dim3(grid), dim3(WNT), 0, s, a);
   }
   return hipGetLastError();
 }

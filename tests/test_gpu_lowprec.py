@@ -148,3 +148,36 @@ def test_lowprec_rejects_fp64_data():
     A = to_dev(np.ones((64, 48)), torch.float64)
     with pytest.raises(P.IDCurError):
         P.id_col(A, 4, p=4, prec="bf16")
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_lowprec_on_power_spectrum(prec):
+    """sigma_j = (j + 1)^-2 (the 20000 x 10000 workload's spectrum, whose rank-k
+    tail sigma_{k+1} / sigma_1 lies far below the BF16 unit roundoff 2^-8): the
+    device's 16-bit ID (Algorithm 4, q = 0) matches the oracle's ID of the sketch
+    rounded to the same 16-bit format (oracle.lowprec) within 1.05x. The ratio of
+    that error to the FP64 sketch's is the precision's own cost, reported: FP16
+    stays within 1.10x of it on this spectrum, BF16 does not (the reason the
+    headline uses BF16 only where the tail is near its roundoff)."""
+    m, n, k, p = 3000, 2000, 100, 10
+    say(f"16-bit ID on (j+1)^-2, {prec}, {m}x{n} k={k} p={p}")
+    A = synth.lowrank(m, n, synth.sigma_pow(min(m, n), 2.0), seed=51).astype(np.float32)
+    om = synth.gaussian(k + p, m, seed=52).astype(np.float32)
+    A64, om64 = A.astype(np.float64), om.astype(np.float64)
+    Y16 = lowprec.sketch_rounded(A64, om64, prec)
+    ref16 = oracle.id_col(Y16, k)
+    e_16 = rel_err_id(A64, ref16.J, ref16.T)
+    ref64 = oracle.id_col(A64, k, omega=om64, q=0)
+    e_64 = rel_err_id(A64, ref64.J, ref64.T)
+    got = P.id_col(to_dev(A, torch.float32), k, p=p, q=0, omega=to_dev(om, torch.float32), prec=prec)
+    J = got.J.cpu().numpy()
+    check_perm(J, n)
+    c = clear_prefix(ref16.qr.gaps, 1e-4)
+    assert c >= 5
+    assert np.array_equal(J[:c], ref16.J[:c])
+    e_g = rel_err_id(A64, J, got.T.cpu().numpy())
+    say(f"  e_ID device {e_g:.4e}, oracle on the {prec} sketch {e_16:.4e}, FP64 sketch {e_64:.4e}, "
+        f"precision cost {e_16 / e_64:.3f}")
+    assert e_g <= 1.05 * e_16
+    if prec == "fp16":
+        assert e_16 <= 1.10 * e_64
