@@ -50,8 +50,8 @@ TRAFFIC = {
             "gemm16_sources_sha"),
     "batched": ("batched_id_4096_kernel_blocks_traffic.md", ("batched.hip",), "batched_sources_sha"),
     "srht": ("structured_sketch_srht_20000x10000_l400.md", ("srht.hip",), "srht_sources_sha"),
-    "g16_c3": ("sketch_gemm16_50000x20000_l520_traffic.md", ("gemm16_kernel.hpp", "gemm16.hip", "gemm16_f16.hip"),
-               "gemm16_sources_sha"),
+    "g16_c3": ("sketch_gemm16w_50000x20000_l520_traffic.md",
+               ("gemm16w_kernel.hpp", "gemm16_kernel.hpp", "gemm16.hip", "gemm16_f16.hip"), "gemm16w_sources_sha"),
     "blk_c3": ("cpqr_blk_500x50000_k500_traffic.md", ("cpqr_blk.hip",), "cpqr_blk_sources_sha"),
 }
 
