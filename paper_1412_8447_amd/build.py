@@ -23,7 +23,7 @@ FLAGS = [
     "-Wno-unused-result", "-Wno-unused-variable",
 ]
 
-SOURCES = ["cpqr.hip", "cpqr_blk.hip", "cpqr_reg.hip", "cpqr_reg_f32.hip", "cpqr_reg_f64.hip", "gemm.hip", "gemm_f32.hip", "gemm_f32_f64acc.hip", "gemm_f64.hip", "gemm_f32_f64.hip",
+SOURCES = ["cpqr.hip", "cpqr_blk.hip", "cpqr_reg.hip", "cpqr_reg_f32.hip", "cpqr_reg_f64.hip", "cpqr_res.hip", "gemm.hip", "gemm_f32.hip", "gemm_f32_f64acc.hip", "gemm_f64.hip", "gemm_f32_f64.hip",
            "gemm_f64_f32.hip", "gemm_thin.hip", "gemm16.hip", "gemm16_f16.hip", "batched.hip", "batched_bwd.hip", "chol.hip", "misc.hip", "srht.hip", "spmm.hip", "jacobi.hip", "args.cpp", "host.cpp"]
 
 

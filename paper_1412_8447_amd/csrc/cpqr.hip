@@ -435,18 +435,21 @@ static size_t cpqr_lds_bytes(int cols_per_wg, int lpad, int kmax, bool in_lds) {
 }
 
 // Kernel choice: the register-slab kernel when the columns fit in the
-// registers of at most one workgroup per CU, else the blocked kernel (short
+// registers of at most one workgroup per CU, else (FP32) the on-chip-slab
+// kernel when they fit in registers and LDS, else the blocked kernel (short
 // form when its panel of reflectors fits in LDS, else tall), else the
 // unblocked slab kernel below. IDCUR_CPQR_SLAB selects a kernel for testing:
-// 1 the blocked kernel (its own form), 2 its tall form, 3 the unblocked one.
+// 1 the blocked kernel (its own form), 2 its tall form, 3 the unblocked one;
+// IDCUR_CPQR_RESCFG=i the on-chip-slab kernel's configuration i.
 CpqrPlan cpqr_plan(int dtype_size, int l, int n, int kmax, int num_cus) {
   CpqrPlan p{};
   p.reg_cfg = -1;
+  p.res_cfg = -1;
   const char* fs = getenv("IDCUR_CPQR_SLAB");
   const int force = (fs && fs[0] >= '1' && fs[0] <= '3') ? fs[0] - '0' : 0;
   if (force == 0) {
     int G = 0, cpw = 0;
-    const int cfg = cpqr_reg_pick(dtype_size, l, n, num_cus, &G, &cpw);
+    const int cfg = cpqr_res_forced() ? -1 : cpqr_reg_pick(dtype_size, l, n, num_cus, &G, &cpw);
     if (cfg >= 0) {
       p.reg_cfg = cfg;
       p.G = G;
@@ -457,6 +460,21 @@ CpqrPlan cpqr_plan(int dtype_size, int l, int n, int kmax, int num_cus) {
       p.lds_bytes = cpqr_reg_lds_bytes(cfg, kmax, cpw, dtype_size);
       p.rec_bytes = cpqr_reg_rec_bytes(p.G);
       p.cvals_bytes = cpqr_reg_cvals_bytes(cfg, p.G, dtype_size);
+      p.fin_bytes = (size_t)p.G * 16 * sizeof(int);
+      p.gslab_bytes = 0;
+      return p;
+    }
+    const int rcfg = cpqr_res_pick(dtype_size, l, n, kmax, num_cus, &G, &cpw);
+    if (rcfg >= 0) {
+      p.res_cfg = rcfg;
+      p.G = G;
+      p.cols_per_wg = cpw;
+      p.lpad = (int)round_up(std::max(l, 1), 4);
+      p.lanes_per_col = 0;
+      p.in_lds = true;
+      p.lds_bytes = cpqr_res_lds_bytes(rcfg, kmax, cpw);
+      p.rec_bytes = cpqr_reg_rec_bytes(p.G);
+      p.cvals_bytes = cpqr_res_cvals_bytes(rcfg, p.G);
       p.fin_bytes = (size_t)p.G * 16 * sizeof(int);
       p.gslab_bytes = 0;
       return p;
@@ -494,6 +512,11 @@ hipError_t cpqr_launch(int dtype, const CpqrPlan& p, CpqrArgs a, hipStream_t str
   a.cols_per_wg = p.cols_per_wg;
   a.lanes_per_col = p.lanes_per_col;
   if (p.blk > 0) return cpqr_blk_launch(dtype, p, a, stream);
+  if (p.res_cfg >= 0) {
+    hipError_t e = zero_launch(a.cvals, p.cvals_bytes, stream);
+    if (e != hipSuccess) return e;
+    return cpqr_res_launch(p.res_cfg, p.G, a, p.lds_bytes, stream);
+  }
   if (p.reg_cfg >= 0) {
     // exchanged words carry the publish index: clear what an earlier call left
     hipError_t e = zero_launch(a.cvals, p.cvals_bytes, stream);

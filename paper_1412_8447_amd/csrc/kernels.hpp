@@ -48,6 +48,7 @@ struct CpqrPlan {
   int lpad;
   int lanes_per_col;
   int reg_cfg;        // >= 0: register-slab kernel configuration; -1: blocked or slab kernel
+  int res_cfg;        // >= 0: on-chip-slab kernel configuration (registers and LDS); -1: not used
   int blk;            // blocked kernel: 1 short form, 2 tall form; 0: not used
   int nb, rpw, vch;   // blocked kernel geometry
   bool in_lds;
@@ -68,6 +69,12 @@ size_t cpqr_reg_lds_bytes(int cfg, int kmax_host, int cols_per_wg, int dtype_siz
 size_t cpqr_reg_rec_bytes(int G);
 size_t cpqr_reg_cvals_bytes(int cfg, int G, int dtype_size);
 hipError_t cpqr_reg_launch(int dtype, int cfg, int G, CpqrArgs a, size_t lds_bytes, hipStream_t stream);
+// on-chip-slab variant (cpqr_res.hip, FP32): configuration index or -1
+int cpqr_res_pick(int dtype_size, int l, int n, int kmax_host, int num_cus, int* G, int* cols_per_wg);
+bool cpqr_res_forced();
+size_t cpqr_res_lds_bytes(int cfg, int kmax_host, int cols_per_wg);
+size_t cpqr_res_cvals_bytes(int cfg, int G);
+hipError_t cpqr_res_launch(int cfg, int G, CpqrArgs a, size_t lds_bytes, hipStream_t stream);
 
 // ---------------------------------------------------------------------------
 // MFMA GEMM (gemm.hip): C (M x N) = A (M x K) * B (K x N)

@@ -137,8 +137,8 @@ def test_det_fp32_tall(which):
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_short_form_wide(dtype):
     """A 300 x 30000 matrix, k = 250 (deterministic): too many columns per CU
-    for the register kernel, so the short form of the blocked kernel runs (the
-    shape class of the C^T of a rank-500 CUR)."""
+    for the register kernel, the short form of the blocked kernel (forced: FP32
+    slabs of this size otherwise go to the on-chip-slab kernel)."""
     m, n, k = 300, 30000, 250
     say(f"blocked cpqr: short-wide det {dtype} {m}x{n} k={k}")
     A = synth.lowrank(m, n, synth.sigma_exp(m, 60.0), seed=77)
@@ -146,7 +146,8 @@ def test_short_form_wide(dtype):
     A_in = A.astype(npdt)
     A64 = A_in.astype(np.float64)
     ref = oracle.id_col(A64, k)
-    got = P.id_col(to_dev(A_in, dtype), k)
+    with kernel("1"):
+        got = P.id_col(to_dev(A_in, dtype), k)
     J = got.J.cpu().numpy()
     check_perm(J, n)
     thr = 1e-4 if dtype == torch.float32 else 1e-10
