@@ -15,9 +15,9 @@ size_t cpqr_res_lds_bytes(int cfg, int kmax_host, int cols_per_wg) {
   // the winning column, the norms and thresholds, the pivots and column flags
   // (padded to 16 bytes), then the LDS slots of the slab
   const ResCfg c = kResCfgs[cfg];
-  const size_t head = (size_t)16 * c.RPL * sizeof(float) + 2 * (size_t)(c.NC + c.NL) * (kRT / 16) * sizeof(double) +
+  const size_t head = (size_t)16 * c.RPL * sizeof(float) + 2 * (size_t)(c.NC + c.NL) * (c.NTH / 16) * sizeof(double) +
                       ((size_t)kmax_host + (size_t)cols_per_wg) * sizeof(int);
-  return (head + 15) / 16 * 16 + (size_t)c.NL * c.RPL * kRT * sizeof(float);
+  return (head + 15) / 16 * 16 + (size_t)c.NL * c.RPL * c.NTH * sizeof(float);
 }
 
 // IDCUR_CPQR_RESCFG=i restricts the search to table entry i (tests run it on
@@ -30,7 +30,7 @@ int cpqr_res_pick(int dtype_size, int l, int n, int kmax_host, int num_cus, int*
     const ResCfg c = kResCfgs[i];
     if (forced >= 0 && i != forced) continue;
     if (16 * c.RPL < l) continue;
-    const int cp = (kRT / 16) * (c.NC + c.NL);
+    const int cp = (c.NTH / 16) * (c.NC + c.NL);
     const int64_t g = ceil_div(n, cp);
     if (g > num_cus || g < 1) continue;
     if (cpqr_res_lds_bytes(i, kmax_host, cp) > kResLdsCap) continue;
@@ -55,7 +55,7 @@ hipError_t cpqr_res_launch(int cfg, int G, CpqrArgs a, size_t lds_bytes, hipStre
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
   if (e != hipSuccess) return e;
   void* args[] = {&a};
-  return hipLaunchCooperativeKernel(fn, dim3(G), dim3(kRT), args, (unsigned)lds_bytes, stream);
+  return hipLaunchCooperativeKernel(fn, dim3(G), dim3(kResCfgs[cfg].NTH), args, (unsigned)lds_bytes, stream);
 }
 
 }  // namespace idcur

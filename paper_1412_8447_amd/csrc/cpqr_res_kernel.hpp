@@ -25,24 +25,28 @@
 namespace idcur {
 namespace cr {
 
-// EXACT: the exact-norm mode (norms recomputed every step), a template
-// parameter so that the default mode carries no per-slot norm accumulators
-template <int RPL, int NC, int NL, bool EXACT>
-__global__ __launch_bounds__(kRT) void cpqr_res_kernel(CpqrArgs a) {
+// NTH threads per workgroup (256: one wave per SIMD, the register slots may
+// spill into AGPRs; 512: two waves per SIMD, so that one wave's LDS and
+// exchange latencies overlap the other's arithmetic). EXACT: the exact-norm
+// mode (norms recomputed every step), a template parameter so that the
+// default mode carries no per-slot norm accumulators.
+template <int NTH, int RPL, int NC, int NL, bool EXACT>
+__global__ __launch_bounds__(NTH) void cpqr_res_kernel(CpqrArgs a) {
   using T = float;
   constexpr int R = 16;
-  constexpr int NGR = kRT / R;   // column groups per workgroup
+  constexpr int NWV = NTH / 64;   // waves
+  constexpr int NGR = NTH / R;   // column groups per workgroup
   constexpr int NT = NC + NL;    // column slots per group
   static_assert(NC > 0 && NL >= 0, "");
   extern __shared__ __align__(16) unsigned char rsm[];
-  __shared__ double p_v[kRW], p_s[kRW], x_v[kRW], x_s[kRW];
-  __shared__ int p_i[kRW], x_i[kRW], x_t[kRW];
+  __shared__ double p_v[NWV], p_s[NWV], x_v[NWV], x_s[NWV];
+  __shared__ int p_i[NWV], x_i[NWV], x_t[NWV];
   __shared__ int s_vfail;
   __shared__ double s_xnorm;
   // dynamic LDS, by byte offset: the winning column by row (R RPL words), the
   // squared norms and recompute thresholds by slot and group (NT x NGR doubles
   // each), the pivots (kmax_host), the column flags (cols_per_wg), then the LDS
-  // slots of the slab (NL x RPL x kRT words, thread-major, from yoff). Every
+  // slots of the slab (NL x RPL x NTH words, thread-major, from yoff). Every
   // access is a byte offset from rsm, so that it stays an LDS access with the
   // constant part in the instruction's offset field.
   constexpr uint32_t kNuOff = R * RPL * 4;
@@ -53,7 +57,7 @@ __global__ __launch_bounds__(kRT) void cpqr_res_kernel(CpqrArgs a) {
   int* win = reinterpret_cast<int*>(rsm + kWinOff);
   int* act_s = win + a.kmax_host;
   const uint32_t yoff = (kWinOff + 4u * (uint32_t)(a.kmax_host + a.cols_per_wg) + 15u) & ~15u;
-  constexpr uint32_t kSlotBytes = RPL * kRT * 4;
+  constexpr uint32_t kSlotBytes = RPL * NTH * 4;
 
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
@@ -81,11 +85,11 @@ __global__ __launch_bounds__(kRT) void cpqr_res_kernel(CpqrArgs a) {
   // slot u, row slot t of this lane (u and t are constants once unrolled)
   auto yget = [&](int u, int t) -> T {
     if (u < NC) return y[u < NC ? u : 0][t];
-    return f_at(ybase + (uint32_t)(u - NC) * kSlotBytes + (uint32_t)t * (kRT * 4));
+    return f_at(ybase + (uint32_t)(u - NC) * kSlotBytes + (uint32_t)t * (NTH * 4));
   };
   auto yset = [&](int u, int t, T v) {
     if (u < NC) y[u < NC ? u : 0][t] = v;
-    else f_at(ybase + (uint32_t)(u - NC) * kSlotBytes + (uint32_t)t * (kRT * 4)) = v;
+    else f_at(ybase + (uint32_t)(u - NC) * kSlotBytes + (uint32_t)t * (NTH * 4)) = v;
   };
 
   // column of slot u; its squared norm, recompute threshold and active flag
@@ -134,7 +138,7 @@ __global__ __launch_bounds__(kRT) void cpqr_res_kernel(CpqrArgs a) {
 
   // the staged winning column: rows at or past l stay zero (the slab holds
   // zeros there and publishers copy them), so reads of it need no row mask
-  for (int r = tid; r < R * RPL; r += kRT) f_at(4u * (uint32_t)r) = 0.0f;
+  for (int r = tid; r < R * RPL; r += NTH) f_at(4u * (uint32_t)r) = 0.0f;
   if (tid == 0) s_vfail = 0;
   double y0fro2 = 0.0, nu0sq = 0.0;
   int j = 0;
@@ -168,7 +172,7 @@ __global__ __launch_bounds__(kRT) void cpqr_res_kernel(CpqrArgs a) {
     Cand b{p_v[0], p_i[0]};
     double tot = p_s[0];
 #pragma unroll
-    for (int w = 1; w < kRW; ++w) {
+    for (int w = 1; w < NWV; ++w) {
       cand_merge(b, Cand{p_v[w], p_i[w]});
       tot += p_s[w];
     }
@@ -271,7 +275,7 @@ __global__ __launch_bounds__(kRT) void cpqr_res_kernel(CpqrArgs a) {
     double tot = x_s[0];
     int timed_out = x_t[0];
 #pragma unroll
-    for (int q = 1; q < kRW; ++q) {
+    for (int q = 1; q < NWV; ++q) {
       cand_merge(w, Cand{x_v[q], x_i[q]});
       tot += x_s[q];
       timed_out |= x_t[q];
@@ -304,12 +308,12 @@ __global__ __launch_bounds__(kRT) void cpqr_res_kernel(CpqrArgs a) {
           }
         }
       };
-      if (tid == kRT - 1) {
+      if (tid == NTH - 1) {
         uint64_t a0, a1;
         fetch(slot + (uint32_t)(R * RPL) * 8u, a0, a1);
         s_xnorm = __hiloint2double((int)(uint32_t)a0, (int)(uint32_t)a1);
       }
-      for (int q = (j >> 1) + tid; 2 * q < l; q += kRT) {
+      for (int q = (j >> 1) + tid; 2 * q < l; q += NTH) {
         uint64_t a0, a1;
         fetch(slot + (uint32_t)(2 * q) * 8u, a0, a1);
         f_at(8u * (uint32_t)q) = __uint_as_float((uint32_t)a0);
@@ -509,7 +513,7 @@ __global__ __launch_bounds__(kRT) void cpqr_res_kernel(CpqrArgs a) {
   __syncthreads();
   bsum = 0;
   int fin_tmo = 0;
-  for (int q = 0; q < kRW; ++q) {
+  for (int q = 0; q < NWV; ++q) {
     bsum += x_t[q];
     fin_tmo |= p_i[q];
   }
@@ -524,24 +528,27 @@ __global__ __launch_bounds__(kRT) void cpqr_res_kernel(CpqrArgs a) {
       }
   }
   if (g == 0) {
-    for (int t = tid; t < kout; t += kRT) a.J[t] = win[t];
+    for (int t = tid; t < kout; t += NTH) a.J[t] = win[t];
     if (tid == 0) *a.k_out = kout;
   }
 }
 
 struct ResCfg {
-  int RPL, NC, NL;
+  int NTH, RPL, NC, NL;
 };
 // searched in order: the first entry that covers l and n with at most one
-// workgroup per compute unit and fits LDS is taken
-constexpr ResCfg kResCfgs[] = {{32, 9, 2}, {32, 9, 4}};
+// workgroup per compute unit and fits LDS is taken. Two waves per SIMD (512
+// threads, the register slots in plain VGPRs) measured 5.7 ms for the 499 steps
+// of a 500 x 50000 slab against 7.2 ms with one wave per SIMD (9 register and
+// 4 LDS slots per group, part of them in AGPRs).
+constexpr ResCfg kResCfgs[] = {{512, 32, 5, 2}, {512, 33, 4, 2}};
 constexpr int kNumResCfgs = sizeof(kResCfgs) / sizeof(kResCfgs[0]);
 
 template <int I>
 const void* res_kernel_ptr(bool exact) {
   constexpr ResCfg c = kResCfgs[I];
-  return exact ? (const void*)cpqr_res_kernel<c.RPL, c.NC, c.NL, true>
-               : (const void*)cpqr_res_kernel<c.RPL, c.NC, c.NL, false>;
+  return exact ? (const void*)cpqr_res_kernel<c.NTH, c.RPL, c.NC, c.NL, true>
+               : (const void*)cpqr_res_kernel<c.NTH, c.RPL, c.NC, c.NL, false>;
 }
 template <int... I>
 const void* res_kernel_lookup(int i, bool exact, std::integer_sequence<int, I...>) {

@@ -534,7 +534,7 @@ ColId column_id(const Ctx& x, int dtype, const View& X, const idcur_opts& o, int
 
 // Row ID of C (m x kcap, row-major ld kcap) with rank k_dev: the full-rank ID of
 // C^T, giving I (m) and Tr (k x (m-k), ldtr); k_out_r receives its rank.
-void row_id_of_c(const Ctx& x, int dtype, const void* C, int64_t m, int kcap, const int* k_dev, int* k_out_r, int* I,
+void row_id_of_c(const Ctx& x, int dtype, const void* C, int64_t ldc, int64_t m, int kcap, const int* k_dev, int* k_out_r, int* I,
                  void* Tr, int64_t ldtr, double t_reg, double t_svd) {
   const CpqrPlan pl = cpqr_plan((int)esz(dtype), kcap, (int)m, kcap, x.c->num_cus);
   void* rec = x.ar->take(pl.rec_bytes + pl.fin_bytes);
@@ -548,7 +548,7 @@ void row_id_of_c(const Ctx& x, int dtype, const void* C, int64_t m, int kcap, co
     // earlier call in the same memory must not match, so they start at zero
     x.check(zero_launch(cvals, pl.cvals_bytes, x.s), "zero");
     CpqrArgs a{};
-    a.Y = C; a.rs = 1; a.cs = kcap;
+    a.Y = C; a.rs = 1; a.cs = ldc;
     a.l_host = kcap; a.l_dev = k_dev; a.n = (int)m;
     a.kmax_host = kcap; a.kmax_dev = k_dev;
     a.tol = 0.0;
@@ -575,7 +575,7 @@ void row_id_of_c(const Ctx& x, int dtype, const void* C, int64_t m, int kcap, co
 // A^T C accumulated in FP64, so the difference keeps its digits when E is small.
 void solve_u(const Ctx& x, int dtype, const void* R, int64_t ldr, int64_t n, int kcap, const int* kout, const int* J,
              const void* T, int64_t ldt, void* U, int64_t ldu, bool corr = false, const void* A = nullptr,
-             int64_t lda = 0, int64_t m = 0, const void* C = nullptr) {
+             int64_t lda = 0, int64_t m = 0, const void* C = nullptr, int64_t ldc = 0) {
   const int* k_dev = kout;
   const int* kr_dev = kout + 1;
   double* G = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
@@ -618,10 +618,10 @@ void solve_u(const Ctx& x, int dtype, const void* R, int64_t ldr, int64_t n, int
     double* Zt = static_cast<double*>(x.ar->take((size_t)n * kcap * 8));
     double* W1 = static_cast<double*>(x.ar->take((size_t)n * kcap * 8));
     // Gc = C^T C, its factor's inverse
-    prod(kcap, kcap, m, C, 1, kcap, dtype, C, kcap, 1, dtype, Gc, kcap, 0, k_dev, k_dev, nullptr);
+    prod(kcap, kcap, m, C, 1, ldc, dtype, C, ldc, 1, dtype, Gc, kcap, 0, k_dev, k_dev, nullptr);
     chol_inv(x, 0, Gc, kcap, 1, kcap, k_dev, Lc, kcap, Lci, kcap, 0.0, "chol(C)", false);
     // Zt = A^T C (n x k), then Zt -= V Gc
-    prod(n, kcap, m, A, 1, lda, dtype, C, kcap, 1, dtype, Zt, kcap, 0, nullptr, k_dev, nullptr);
+    prod(n, kcap, m, A, 1, lda, dtype, C, ldc, 1, dtype, Zt, kcap, 0, nullptr, k_dev, nullptr);
     GemmDesc g{};
     g.M = n; g.N = kcap; g.K = kcap;
     g.A = V; g.sam = kcap; g.sak = 1; g.a_type = 0;
@@ -683,11 +683,14 @@ void execute(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const void
   }
   column_id(x, dtype, X, o, out.k_out, J, T, ldt, true);
   if (op == OP_COL) return;
-  // C = A(:, J(1:k))
-  void* C = ar.take((size_t)m * kcap * esz(dtype));
+  // C = A(:, J(1:k)), gathered straight into the caller's C when a CUR call
+  // returns one (the row ID and the U solve read it there)
+  const bool c_out = op == OP_CUR && out.C;
+  void* C = c_out ? out.C : ar.take((size_t)m * kcap * esz(dtype));
+  const int64_t ldc = c_out ? out.ldc : kcap;
   if (!ar.dry) {
     Stage st(x, "gather");
-    x.check(gather_cols_launch(dtype, m, A, lda, J, kcap, out.k_out, C, kcap, dtype, x.s), "gather C");
+    x.check(gather_cols_launch(dtype, m, A, lda, J, kcap, out.k_out, C, ldc, dtype, x.s), "gather C");
   }
   void* Tr = out.Tr;
   int64_t ldtr = out.ldtr;
@@ -695,7 +698,7 @@ void execute(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const void
     Tr = ar.take((size_t)kcap * m * esz(dtype));
     ldtr = m;
   }
-  row_id_of_c(x, dtype, C, m, kcap, out.k_out, out.k_out + 1, out.I, Tr, ldtr, o.t_reg, o.t_svd);
+  row_id_of_c(x, dtype, C, ldc, m, kcap, out.k_out, out.k_out + 1, out.I, Tr, ldtr, o.t_reg, o.t_svd);
   if (op == OP_TWO) return;
   // CUR: R = A(I(1:k), :), optional C output, then U
   void* R = out.R;
@@ -707,10 +710,9 @@ void execute(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const void
   if (!ar.dry) {
     Stage st(x, "gather");
     x.check(gather_rows_launch(dtype, n, A, lda, out.I, kcap, out.k_out + 1, R, ldr, dtype, x.s), "gather R");
-    if (out.C) x.check(gather_cols_launch(dtype, m, A, lda, J, kcap, out.k_out, out.C, out.ldc, dtype, x.s), "C out");
   }
   Stage st(x, "u_solve");
-  solve_u(x, dtype, R, ldr, n, kcap, out.k_out, J, T, ldt, out.U, out.ldu, o.u_correct != 0, A, lda, m, C);
+  solve_u(x, dtype, R, ldr, n, kcap, out.k_out, J, T, ldt, out.U, out.ldu, o.u_correct != 0, A, lda, m, C, ldc);
 }
 
 // Error measurement: out[0] = |A - C W|_F^2, out[1] = |A|_F^2 (device doubles).
@@ -1214,7 +1216,7 @@ void execute_cur_csc(idcur_ctx* ctx, int dtype, const Csc& a, const idcur_opts& 
             "gather C");
   }
   void* Tr = ar.take((size_t)kcap * m * esz(dtype));
-  row_id_of_c(x, dtype, C, m, kcap, out.k_out, out.k_out + 1, out.I, Tr, m, o.t_reg, o.t_svd);
+  row_id_of_c(x, dtype, C, kcap, m, kcap, out.k_out, out.k_out + 1, out.I, Tr, m, o.t_reg, o.t_svd);
   void* R = ar.take((size_t)kcap * n * esz(dtype));
   int* slot = static_cast<int*>(ar.take((size_t)m * sizeof(int)));
   if (!ar.dry) {

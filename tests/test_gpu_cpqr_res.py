@@ -30,8 +30,8 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU container
 import paper_1412_8447_amd as P  # noqa: E402
 from gpu_helpers import say, to_dev, clear_prefix, rel_err_id, check_perm  # noqa: E402
 
-# entries of the on-chip kernel's table (cpqr_res_kernel.hpp): (RPL, NC, NL)
-RES_CFGS = [(32, 9, 2), (32, 9, 4)]
+# entries of the on-chip kernel's table (cpqr_res_kernel.hpp): (threads, RPL, NC, NL)
+RES_CFGS = [(512, 32, 5, 2), (512, 33, 4, 2)]
 
 
 @contextlib.contextmanager
@@ -66,6 +66,23 @@ def test_matches_register_kernel(cfg, norms, m, n, k):
         b = P.id_col(dA, k, norms=norms)
     assert a.k == b.k == k
     check_perm(b.J.cpu().numpy(), n)
+    assert torch.equal(a.J, b.J)
+    assert torch.equal(a.T, b.T)
+
+
+@pytest.mark.parametrize("cfg", [1])
+@pytest.mark.parametrize("norms", ["downdate", "exact"])
+@pytest.mark.parametrize("m,n,k", [(520, 6000, 500), (528, 4001, 527), (513, 3000, 200)])
+def test_33_slot_configs_match_register_kernel(cfg, norms, m, n, k):
+    """The entries with 33 row slots (sketches of up to 528 rows, such as the
+    520 x 20000 sketch of the rank-500 workload) against the register kernel."""
+    say(f"on-chip cpqr cfg {cfg} vs register kernel: {m}x{n} k={k} norms={norms}")
+    A = _fp32(m, n, 80.0, seed=m + 5 * n + k)
+    dA = to_dev(A, torch.float32)
+    a = P.id_col(dA, k, norms=norms)
+    with res_cfg(cfg):
+        b = P.id_col(dA, k, norms=norms)
+    assert a.k == b.k == k
     assert torch.equal(a.J, b.J)
     assert torch.equal(a.T, b.T)
 
