@@ -62,7 +62,23 @@ class _Opts(ctypes.Structure):
                 ("rank_tol", ctypes.c_double), ("p", ctypes.c_int32), ("q", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("omega", ctypes.c_void_p), ("prec", ctypes.c_int32),
                 ("norms", ctypes.c_int32), ("sketch", ctypes.c_int32), ("srht_signs", ctypes.c_void_p),
-                ("srht_rows", ctypes.c_void_p), ("u_correct", ctypes.c_int32), ("t_reg", ctypes.c_double)]
+                ("srht_rows", ctypes.c_void_p), ("u_correct", ctypes.c_int32), ("t_reg", ctypes.c_double),
+                ("t_svd", ctypes.c_double)]
+
+
+def _opts_members():
+    """Member names of idcur_opts in declaration order, from the header."""
+    text = re.sub(r"/\*.*?\*/", " ", open(HEADER).read(), flags=re.S)
+    end = re.search(r"\}\s*idcur_opts\s*;", text)
+    assert end, "idcur_opts not found in the header"
+    body = text[text.rindex("{", 0, end.start()) + 1:end.start()]
+    return [m.group(1) for m in re.finditer(r"(\w+)\s*;", body)]
+
+
+def test_opts_mirror_matches_the_header():
+    # idcur_opts_default writes the whole struct: a stale mirror here would let
+    # it write past the Python-side buffer
+    assert [f[0] for f in _Opts._fields_] == _opts_members()
 
 
 def test_opts_default(lib):
@@ -72,6 +88,7 @@ def test_opts_default(lib):
     assert (o.k, o.kmax, o.tol, o.rank_tol, o.p, o.q, o.seed) == (0, 0, 0.0, 0.0, -1, 0, 0)
     assert not o.omega and o.prec == 0 and o.norms == 0
     assert o.sketch == 0 and not o.srht_signs and not o.srht_rows and o.u_correct == 0 and o.t_reg == 0.0
+    assert o.t_svd == 0.0
 
 
 def test_null_context_is_rejected(lib):
