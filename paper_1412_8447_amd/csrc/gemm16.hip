@@ -69,6 +69,24 @@ __global__ __launch_bounds__(256) void pack16_kernel(int64_t rows, int64_t cols,
   }
 }
 
+// Chunk-major packing for the wide kernel: thread w writes the 16-byte word of
+// chunk c = w / npad, column j = w % npad (eight consecutive k rounded to 16
+// bits, the same rounding as pack16_kernel).
+template <bool H>
+__global__ __launch_bounds__(256) void pack16c_kernel(int64_t rows, int64_t cols, const float* in, int64_t sj,
+                                                      int64_t sk, int64_t npad, int64_t words, g16::u32x4* out) {
+  const int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (w >= words) return;
+  const int64_t j = w % npad, c = w / npad;
+  float f[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int64_t k = 8 * c + e;
+    f[e] = (j < rows && k < cols) ? in[j * sj + k * sk] : 0.0f;
+  }
+  out[w] = g16::pack8<H>(f, 1.0f);
+}
+
 // Per-block maximum of |A| over a rows x cols row-major matrix (ld lda).
 __global__ __launch_bounds__(256) void amax_kernel(int64_t rows, int64_t cols, const float* A, int64_t lda,
                                                    float* part) {
@@ -132,15 +150,43 @@ __global__ void scale_kernel(const float* part, int nparts, float* scale) {
 // of 80-row stripes, one workgroup per CU, when the operands admit whole
 // vectors: K a multiple of 8 (>= 8), A rows 16-byte aligned (k contiguous) or
 // 8-byte aligned with M even (row index contiguous), B rows 16-byte aligned.
-static bool wide_ok(int64_t M, int64_t N, int64_t K, bool akc, bool vec) {
-  return g16::wide_cb(N) > 0 && vec && K >= 8 && K % 8 == 0 && M >= 2 && (akc || M % 2 == 0);
+// the wide kernel reads A in 16-byte vectors when k is contiguous, in single
+// words across rows otherwise; B (chunk-major, from pack16c_launch) always in
+// 16-byte vectors
+bool gemm16_wide(int64_t M, int64_t N, int64_t K, const float* A, int64_t sam, int64_t sak) {
+  if (sak != 1 && sam != 1) return false;
+  const bool akc = sak == 1;
+  const bool avec = !akc || ((uintptr_t)A % 16 == 0 && sam % 4 == 0);
+  // the kernel's 32-bit byte offsets within a stripe (k contiguous: 80 rows of
+  // sam) or within a k-step (row index contiguous: 32 k of sak, plus M rows)
+  const bool off32 = akc ? (int64_t)g16::WBM * sam * 4 < (1LL << 31) : (32 * sak + M) * 4 < (1LL << 31);
+  return g16::wide_cb(N) > 0 && avec && off32 && K >= 8 && K % 8 == 0 && M >= 1;
 }
+int64_t gemm16_wide_npad(int64_t N) { return 16 * g16::WNW * (int64_t)g16::wide_cb(N); }
+// every chunk of K, rounded up to a k-step, and one more k-step: a step that
+// starts inside K reads its four chunks without clamping
+int64_t gemm16_wide_kchunks(int64_t K) { return round_up(ceil_div(std::max<int64_t>(K, 1), 8), 4) + 4; }
 
 int gemm16_pick_splitk(int64_t M, int64_t N, int64_t K, int num_cus) {
   if (g16::wide_cb(N) > 0 && K >= 8 && K % 8 == 0) {
-    // one workgroup per CU: split K only when the stripes leave half the CUs idle
+    // one workgroup per CU. With at least half the CUs busy, the split of 1 to 4
+    // with the fewest rounds of workgroups per unit of work, taken only when it
+    // saves more than 5% (the partial sums cost a pass over C): 625 stripes on
+    // 256 CUs run 3 rounds unsplit, 2.5 with K split in two
     const int64_t stripes = ceil_div(M, g16::WBM);
-    if (2 * stripes >= num_cus) return 1;
+    if (2 * stripes >= num_cus) {
+      int best = 1;
+      double bv = (double)ceil_div(stripes, num_cus);
+      for (int s = 2; s <= 4; ++s) {
+        if (K / s < 4096) break;
+        const double v = (double)ceil_div(stripes * s, num_cus) / s;
+        if (v < 0.95 * bv) {
+          bv = v;
+          best = s;
+        }
+      }
+      return best;
+    }
     int64_t s = num_cus / stripes;
     s = std::min<int64_t>(s, std::max<int64_t>(1, K / 1024));
     return (int)std::max<int64_t>(1, std::min<int64_t>(s, 64));
@@ -182,9 +228,13 @@ hipError_t gemm16_launch(const Gemm16Desc& d, void* part, hipStream_t stream, hi
   a.gx = (int)ceil_div(d.M, BM); a.gy = gy; a.gz = splitk;
   if (ev0) (void)hipEventRecord(ev0, stream);
   hipError_t e;
-  if (wide_ok(d.M, d.N, d.K, akc, a.vec)) {
+  const bool wide = gemm16_wide(d.M, d.N, d.K, d.A, d.sam, d.sak);
+  if (wide != (d.b_chunked != 0)) return hipErrorInvalidValue;   // B packed for the other kernel
+  if (wide) {
     a.gx = (int)ceil_div(d.M, g16::WBM);
     a.gy = 1;
+    a.ldb = gemm16_wide_npad(d.N);
+    a.kc8max = gemm16_wide_kchunks(d.K) - 4;
     const int cb = g16::wide_cb(d.N);
     e = d.fp16 ? g16::launch_wide_fp16(a, akc, cb, stream) : g16::launch_wide_bf16(a, akc, cb, stream);
   } else {
@@ -196,6 +246,20 @@ hipError_t gemm16_launch(const Gemm16Desc& d, void* part, hipStream_t stream, hi
   const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(total, 256), 4096);
   hipLaunchKernelGGL(reduce16_kernel, dim3(blocks), dim3(256), 0, stream, static_cast<const float*>(part), splitk, d.M,
                      d.N, d.C, d.ldc);
+  return hipGetLastError();
+}
+
+hipError_t pack16c_launch(int fp16, int64_t rows, int64_t cols, const float* in, int64_t sj, int64_t sk, int64_t npad,
+                          int64_t kchunks, void* out, hipStream_t stream) {
+  const int64_t words = npad * kchunks;
+  if (words <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)ceil_div(words, 256);
+  if (fp16)
+    hipLaunchKernelGGL(pack16c_kernel<true>, dim3(grid), dim3(256), 0, stream, rows, cols, in, sj, sk, npad, words,
+                       static_cast<g16::u32x4*>(out));
+  else
+    hipLaunchKernelGGL(pack16c_kernel<false>, dim3(grid), dim3(256), 0, stream, rows, cols, in, sj, sk, npad, words,
+                       static_cast<g16::u32x4*>(out));
   return hipGetLastError();
 }
 

@@ -41,7 +41,8 @@ constexpr int RS = 5;   // LDS row stride in 16-byte chunks (4 data + 1 pad)
 struct Args {
   int64_t M, N, K;
   const float* A; int64_t sam, sak;
-  const uint16_t* B; int64_t ldb;   // B(k, j) = B[j*ldb + k]
+  const uint16_t* B; int64_t ldb;   // B(k, j) = B[j*ldb + k]; wide kernel: chunk-major, ldb = padded columns
+  int64_t kc8max;                   // wide kernel: last chunk index a k-step may start at
   float* out; int64_t ldo;          // C (direct) or partials (ld N)
   int64_t kps;                      // K per split (multiple of BK)
   int direct;
@@ -52,6 +53,8 @@ struct Args {
 
 __host__ __device__ inline int64_t tiles_total(const Args& p) { return (int64_t)p.gx * p.gy * p.gz; }
 
+// 8 values rounded to the 16-bit format; FP16 values are scaled by s first
+// (BF16 has FP32's exponent range and is never scaled)
 template <bool H>
 __device__ __forceinline__ u32x4 pack8(const float (&f)[8], float s) {
   if constexpr (H) {
@@ -62,7 +65,7 @@ __device__ __forceinline__ u32x4 pack8(const float (&f)[8], float s) {
   } else {
     bf16x8 v;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = (__bf16)(f[e] * s);
+    for (int e = 0; e < 8; ++e) v[e] = (__bf16)f[e];
     return __builtin_bit_cast(u32x4, v);
   }
 }

@@ -7,16 +7,29 @@
 //
 // Eight waves split the columns (CB blocks of 16 each) and share the 80 rows
 // (five row blocks), two waves per SIMD, so that one wave's loads are in flight
-// while the other's products run; the B stage of all columns fills most of LDS,
-// so the kernel runs one workgroup per CU. Every global load
-// is unconditional, from a clamped address inside the operand: rows of A past M
-// and columns of B past N only feed outputs that are never stored, and 8-k
-// chunks past the end of the K split are cleared (by select) before they reach
-// LDS. Nothing in the k loop depends on the step count (steps past the end read
-// cleared chunks), so the D register stages of the prefetch stay in flight
-// together. Requires K % 8 == 0, aligned rows (16 bytes for A with k
-// contiguous, 8 bytes and M even for A with the row index contiguous, 16 bytes
-// for the packed B) and K >= 8.
+// while the other's products run. A, shared by all waves, is rounded to 16 bits
+// on its way into LDS. The thin operand B goes straight from memory into the
+// matrix-core operand registers: each wave multiplies only its own column
+// blocks, so B gains nothing from LDS. B is packed chunk-major (8 consecutive k
+// of all padded columns, then the next 8), so lane L of a wave loads B(k0 + 8
+// (L / 16) .. +7, column 16 c + L % 16), the operand layout of
+// v_mfma_f32_16x16x32, as one 16-byte load at a fixed offset from a base that
+// only the k-step moves: no per-lane address arithmetic. B fragments of step t
+// sit in register stage t % 2 and are reloaded with step t + 2 as soon as step
+// t's products are issued. (With B staged through LDS as well, a 50000x20000
+// launch took 2.90 / 2.80 ms for A^T B / A B against 2.33 / 2.60 ms.)
+//
+// Every global load is unconditional, from a clamped address inside the
+// operand: rows of A past M and columns of B past N only feed outputs that are
+// never stored, and 8-k chunks of A past the end of the K split are cleared (by
+// select) before they reach LDS. B needs no clearing or clamping of columns:
+// its padded columns are zero, its chunks past the end of the split meet those
+// cleared A chunks (B is finite: the packed sketching matrix or basis), and
+// the chunk index is clamped so that no read passes the packed buffer. Nothing
+// in the k loop depends on the step count (steps past the end read cleared
+// chunks), so the register stages of the prefetch stay in flight together.
+// Requires K % 8 == 0, aligned rows (16 bytes for A with k contiguous and for
+// the packed B) and K >= 8.
 #pragma once
 #include "gemm16_kernel.hpp"
 
@@ -31,18 +44,13 @@ constexpr int WNT = 64 * WNW;     // threads
 
 template <bool H, bool A_KC, int CB, int D>
 __global__ __launch_bounds__(WNT, 1) void gemm16w_kernel(Args p) {
-  constexpr int BN = 16 * WNW * CB;                            // WNW waves x CB blocks x 16 columns
-  constexpr int FA = A_KC ? 8 : 16;                            // floats per A chunk
-  constexpr int NCA = A_KC ? WBM * 4 : (WBM / 2) * 4;          // A chunks per k-step
-  constexpr int CA = (NCA + WNT - 1) / WNT;                    // per thread
-  static_assert((BN * 4) % WNT == 0 && BN * 4 / WNT == CB, "B chunks split evenly");
+  // A chunks: one row, 8 consecutive k (WBM rows x 4 chunks per k-step)
+  constexpr int NCA = WBM * 4;
+  constexpr int CA = (NCA + WNT - 1) / WNT;
   __shared__ u32x4 As[2][WBM * RS];
-  __shared__ u32x4 Bs[2][BN * RS];
 
   const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t W = (int64_t)p.gx * p.gz, per = (W + 7) / 8;
-  // tile ranges contiguous per XCD: the stripes running together on one XCD
-  // read the same k-range of B, which L2 then serves
   const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
   if (tile >= W) return;
   const int bx = (int)(tile % p.gx), bz = (int)(tile / p.gx);
@@ -50,80 +58,78 @@ __global__ __launch_bounds__(WNT, 1) void gemm16w_kernel(Args p) {
   const int64_t kb = (int64_t)bz * p.kps, ke = min(p.K, kb + p.kps);
   const float s_in = p.scale ? p.scale[0] : 1.0f;
   const float s_out = p.scale ? p.scale[1] : 1.0f;
-  const int64_t mlast = A_KC ? p.M - 1 : p.M - 2;   // last row (pair) of A
+  const int64_t mlast = p.M - 1;
 
-  // A chunk c of this thread (q = min(tid + 512 c, NCA - 1)):
-  //   A_KC:  row q / 4, k = 8 (q % 4) .. +7
-  //   else:  rows 2 (q % 40), +1, k = 8 (q / 40) .. +7
+  // chunk q of a k-step: with k contiguous, four threads read a row's 32 k
+  // (128 bytes); with the row index contiguous, 80 threads read one k across
+  // the stripe's 80 rows, for each of their 8 k
   auto a_row = [&](int c) {
     const int q = min(tid + WNT * c, NCA - 1);
-    return A_KC ? q >> 2 : 2 * (q % (WBM / 2));
+    return A_KC ? q >> 2 : q % WBM;
   };
   auto a_kg = [&](int c) {
     const int q = min(tid + WNT * c, NCA - 1);
-    return A_KC ? (q & 3) : q / (WBM / 2);
+    return A_KC ? (q & 3) : q / WBM;
   };
+  // B chunk-major: the 16-byte word (chunk c of 8 k, column j) at byte
+  // 16 (c ldb + j), ldb = 128 CB padded columns, zeros past N and past K. This
+  // lane's word of a k-step: chunk k0 / 8 + L / 16, column 16 (CB wv + c) + L % 16,
+  // at a fixed byte offset from the step's (uniform) base; the column blocks
+  // are 256 bytes apart
+  const uint32_t boff = (uint32_t)(16 * ((lane >> 4) * p.ldb + wv * CB * 16 + (lane & 15)));
 
-  float fas[D][CA][FA];
-  u32x4 rbs[D][CB];
+  float fas[D][CA][8];
+  u32x4 rbs[2][CB];
 
-  auto gload = [&](int64_t k0, float (&fa)[CA][FA], u32x4 (&rb)[CB]) {
+  static_assert(CA == 1, "one A chunk per thread and k-step");
+  // A addresses: a uniform base per k-step (scalar arithmetic) plus this lane's
+  // 32-bit byte offset, so that the loads need no per-lane 64-bit arithmetic.
+  // The lane's chunk starts at kc = min(k0 + 8 g, ke - 8) (clamped, like every
+  // chunk past the end of the split, to end at ke). The step's base row is
+  // kbase = max(min(k0, ke - 32), 0) <= kc, so the offset kc - kbase lies in
+  // [0, 24]: the unsigned 32-bit byte offsets never wrap.
+  const int g0 = a_kg(0);
+  const int64_t gi0 = min(m0 + a_row(0), mlast);
+  auto kbase = [&](int64_t k0) { return max<int64_t>(min(k0, ke - 32), 0); };
+  auto aload = [&](int64_t k0, float (&fa)[CA][8]) {
+    const int64_t kb0 = kbase(k0);
+    // kc - kbase = min(8 g + (k0 - kbase), ke - 8 - kbase), both bounds uniform
+    const int ko = min(8 * g0 + (int)min<int64_t>(k0 - kb0, 1 << 20), (int)(ke - 8 - kb0));
+    typedef float nf4 __attribute__((ext_vector_type(4)));
+    if constexpr (A_KC) {
+      // (row gi0, kc .. kc + 7): base A + m0 sam + kbase, offset (gi0 - m0) sam + ko
+      const char* base = reinterpret_cast<const char*>(p.A + m0 * p.sam + kb0);
+      const uint32_t off = (uint32_t)(4 * ((int)(gi0 - m0) * (int)p.sam + ko));
+      const nf4 u = __builtin_nontemporal_load(reinterpret_cast<const nf4*>(base + off));
+      const nf4 v = __builtin_nontemporal_load(reinterpret_cast<const nf4*>(base + off + 16));
 #pragma unroll
-    for (int c = 0; c < CA; ++c) {
-      const int64_t gi = min(m0 + a_row(c), mlast);
-      const int64_t kc = min(k0 + 8 * a_kg(c), ke - 8);
-      // A is read once: non-temporal loads, so that its stream does not push
-      // the thin operand B (read by every stripe) out of L2
-      typedef float nf4 __attribute__((ext_vector_type(4)));
-      typedef float nf2 __attribute__((ext_vector_type(2)));
-      if (A_KC) {
-        const float* src = p.A + gi * p.sam + kc;
-        const nf4 u = __builtin_nontemporal_load(reinterpret_cast<const nf4*>(src));
-        const nf4 v = __builtin_nontemporal_load(reinterpret_cast<const nf4*>(src + 4));
+      for (int e = 0; e < 4; ++e) {
+        fa[0][e] = u[e];
+        fa[0][4 + e] = v[e];
+      }
+    } else {
+      // (kc + e, row gi0): base A + (kbase + e) sak, offset ko sak + gi0
+      const uint32_t off = (uint32_t)(4 * (ko * (int)p.sak + (int)gi0));
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          fa[c][e] = u[e];
-          fa[c][4 + e] = v[e];
-        }
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const nf2 u = __builtin_nontemporal_load(reinterpret_cast<const nf2*>(p.A + (kc + e) * p.sak + gi));
-          fa[c][e] = u[0];
-          fa[c][8 + e] = u[1];
-        }
+      for (int e = 0; e < 8; ++e) {
+        const char* base = reinterpret_cast<const char*>(p.A + (kb0 + e) * p.sak);
+        fa[0][e] = __builtin_nontemporal_load(reinterpret_cast<const float*>(base + off));
       }
     }
-#pragma unroll
-    for (int c = 0; c < CB; ++c) {
-      const int q = tid + WNT * c;
-      const int64_t gj = min((int64_t)(q >> 2), p.N - 1);
-      const int64_t kc = min(k0 + 8 * (q & 3), ke - 8);
-      rb[c] = *reinterpret_cast<const u32x4*>(p.B + gj * p.ldb + kc);
-    }
   };
-  auto sstore = [&](int buf, int64_t k0, const float (&fa)[CA][FA], const u32x4 (&rb)[CB]) {
+  auto bload = [&](int64_t k0, u32x4 (&rb)[CB]) {
+    // steps past the end of K read the last chunks (their A is cleared)
+    const int64_t c8 = min(k0 >> 3, p.kc8max);
+    const char* base = reinterpret_cast<const char*>(p.B) + c8 * p.ldb * 16;
 #pragma unroll
-    for (int c = 0; c < CA; ++c) {
-      if (c + 1 < CA || NCA % WNT == 0 || tid + WNT * c < NCA) {
-        const bool kv = k0 + 8 * a_kg(c) < ke;   // whole chunk in the split (K % 8 == 0)
-        const int r = a_row(c), g = a_kg(c);
-        float f[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) f[e] = kv ? fa[c][e] : 0.0f;
-        As[buf][r * RS + g] = pack8<H>(f, s_in);
-        if (!A_KC) {
-#pragma unroll
-          for (int e = 0; e < 8; ++e) f[e] = kv ? fa[c][8 + e] : 0.0f;
-          As[buf][(r + 1) * RS + g] = pack8<H>(f, s_in);
-        }
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < CB; ++c) {
-      const int q = tid + WNT * c;
-      const bool kv = k0 + 8 * (q & 3) < ke;
-      Bs[buf][(q >> 2) * RS + (q & 3)] = kv ? rb[c] : u32x4{0u, 0u, 0u, 0u};
+    for (int c = 0; c < CB; ++c) rb[c] = *reinterpret_cast<const u32x4*>(base + boff + 256 * c);
+  };
+  auto astore = [&](int buf, int64_t k0, const float (&fa)[CA][8]) {
+    if (NCA % WNT == 0 || tid < NCA) {
+      // the whole chunk lies in the split (K % 8 == 0)
+      const bool kv = 8 * g0 < (int)min<int64_t>(ke - k0, (int64_t)(1 << 30));
+      const u32x4 v = pack8<H>(fa[0], s_in);
+      As[buf][a_row(0) * RS + g0] = kv ? v : u32x4{0u, 0u, 0u, 0u};
     }
   };
 
@@ -135,39 +141,38 @@ __global__ __launch_bounds__(WNT, 1) void gemm16w_kernel(Args p) {
 
   const int64_t nk = ke > kb ? (ke - kb + BK - 1) / BK : 0;
   if (nk > 0) {
-    // k-step s in register stage s % D; k-step t in LDS buffer t % 2 while it
-    // is multiplied; after the products of step t, step t + 1 goes to LDS and
-    // step t + 1 + D is loaded into its stage
+    // A: step s in register stage s % D, LDS buffer s % 2 while multiplied;
+    // B: step s in register stage s % 2
 #pragma unroll
-    for (int s = 0; s < D; ++s) gload(kb + s * BK, fas[s], rbs[s]);
-    sstore(0, kb, fas[0], rbs[0]);
-    gload(kb + D * BK, fas[0], rbs[0]);
+    for (int s = 0; s < D; ++s) aload(kb + s * BK, fas[s]);
+    bload(kb, rbs[0]);
+    bload(kb + BK, rbs[1]);
+    astore(0, kb, fas[0]);
+    aload(kb + D * BK, fas[0]);
     __syncthreads();
-    for (int64_t t0 = 0; t0 < nk; t0 += D) {
+    constexpr int P = D % 2 == 0 ? D : 2 * D;   // unrolled period (a multiple of 2 and D)
+    for (int64_t t0 = 0; t0 < nk; t0 += P) {
 #pragma unroll
-      for (int d = 0; d < D; ++d) {
+      for (int d = 0; d < P; ++d) {
         const int64_t it = t0 + d;
-        const int buf = (int)(it & 1);
+        const int buf = d & 1;
         const u32x4* as = As[buf];
-        const u32x4* bs = Bs[buf];
         u32x4 a[WRB];
 #pragma unroll
         for (int i = 0; i < WRB; ++i) a[i] = as[(i * 16 + (lane & 15)) * RS + (lane >> 4)];
 #pragma unroll
-        for (int c = 0; c < CB; ++c) {
-          const u32x4 b = bs[((wv * CB + c) * 16 + (lane & 15)) * RS + (lane >> 4)];
+        for (int c = 0; c < CB; ++c)
 #pragma unroll
-          for (int i = 0; i < WRB; ++i) acc[i][c] = mfma16<H>(a[i], b, acc[i][c]);
-        }
-        const int sn = (d + 1) % D;   // stage of k-step it + 1 (constant once unrolled)
-        sstore(buf ^ 1, kb + (it + 1) * BK, fas[sn], rbs[sn]);
-        gload(kb + (it + 1 + D) * BK, fas[sn], rbs[sn]);
+          for (int i = 0; i < WRB; ++i) acc[i][c] = mfma16<H>(a[i], rbs[buf][c], acc[i][c]);
+        bload(kb + (it + 2) * BK, rbs[buf]);
+        const int sn = (d + 1) % D;
+        astore(buf ^ 1, kb + (it + 1) * BK, fas[sn]);
+        aload(kb + (it + 1 + D) * BK, fas[sn]);
         __syncthreads();
       }
     }
   }
 
-  // ---- epilogue (C block layout: row 4 (L / 16) + r, column L % 16) -----------------
 #pragma unroll
   for (int i = 0; i < WRB; ++i) {
 #pragma unroll
@@ -186,7 +191,7 @@ __global__ __launch_bounds__(WNT, 1) void gemm16w_kernel(Args p) {
   }
 }
 
-// register stages of the prefetch
+// register stages of A's prefetch (four measured the same as two)
 constexpr int kWideStages = 2;
 
 // column blocks per wave for N columns (BN = 128 CB >= N), or 0 when the wide

@@ -380,22 +380,34 @@ SketchOut sketch(const Ctx& x, int dtype, const View& X, const idcur_opts& o, in
   void* Zt = o.q > 0 ? x.ar->take((size_t)mr * ll * esz(dtype)) : nullptr;
   void* Qyt = o.q > 0 ? x.ar->take((size_t)nc * ll * esz(dtype)) : nullptr;   // orth(Y)^T
   void* Qzt = o.q > 0 ? x.ar->take((size_t)mr * ll * esz(dtype)) : nullptr;   // orth(Z)^T
-  // 16-bit thin operand, packed as B^T (l x K, k contiguous), and the FP16 scale
+  // 16-bit thin operand, packed as B^T (l x K, k contiguous), or chunk-major
+  // (8 k of all padded columns at a time) for the wide kernel; the FP16 scale
   const int64_t ldb16 = round_up(std::max(mr, nc), 8);
-  void* B16 = lowp ? x.ar->take((size_t)l * ldb16 * 2) : nullptr;
+  const size_t b16_bytes =
+      std::max((size_t)l * ldb16 * 2,
+               (size_t)gemm16_wide_npad(l) * gemm16_wide_kchunks(std::max(mr, nc)) * 16);
+  void* B16 = lowp ? x.ar->take(b16_bytes) : nullptr;
   float* scale = (lowp && fp16) ? static_cast<float*>(x.ar->take(2 * sizeof(float))) : nullptr;
   float* spart = (lowp && fp16) ? static_cast<float*>(x.ar->take(kScaleParts * sizeof(float))) : nullptr;
 
-  auto pack = [&](int64_t K, const void* src, int64_t sj, int64_t sk) {
-    if (!x.dry)
-      x.check(pack16_launch(fp16, l, K, static_cast<const float*>(src), sj, sk, l, round_up(K, 8), B16, ldb16, x.s),
+  // Cm = X' * B16^T with X' (M x K) = X or X^T as (sam, sak) say; B16 packed
+  // from src (the K x l thin operand, element (k, j) at src[j*sj + k*sk]) in the
+  // layout of the kernel that gemm16_launch picks for this shape
+  auto gemm_lp = [&](int64_t M, int64_t K, int64_t sam, int64_t sak, const void* src, int64_t sj, int64_t sk,
+                     void* Cm) {
+    const bool wide = gemm16_wide(M, l, K, static_cast<const float*>(X.A), sam, sak);
+    if (!x.dry) {
+      Stage st(x, "pack");
+      const float* in = static_cast<const float*>(src);
+      x.check(wide ? pack16c_launch(fp16, l, K, in, sj, sk, gemm16_wide_npad(l), gemm16_wide_kchunks(K), B16, x.s)
+                   : pack16_launch(fp16, l, K, in, sj, sk, l, round_up(K, 8), B16, ldb16, x.s),
               "pack16");
-  };
-  auto gemm_lp = [&](int64_t M, int64_t K, int64_t sam, int64_t sak, void* Cm) {   // Cm = X' * B16^T
+    }
     Gemm16Desc g{};
     g.M = M; g.N = l; g.K = K;
     g.A = static_cast<const float*>(X.A); g.sam = sam; g.sak = sak;
     g.B = B16; g.ldb = ldb16;
+    g.b_chunked = wide ? 1 : 0;
     g.C = static_cast<float*>(Cm); g.ldc = ll;
     g.fp16 = fp16; g.scale = scale;
     g.splitk = gemm16_pick_splitk(M, l, K, x.c->num_cus);
@@ -411,11 +423,7 @@ SketchOut sketch(const Ctx& x, int dtype, const View& X, const idcur_opts& o, in
   };
   auto mul_t = [&](const void* Bm) {   // Y^T = X^T * Bm   (Bm: mr x l, ld ll)
     if (lowp) {
-      {
-        Stage st(x, "pack");
-        pack(mr, Bm, 1, ll);
-      }
-      gemm_lp(nc, mr, X.xc, X.xr, Yt);
+      gemm_lp(nc, mr, X.xc, X.xr, Bm, 1, ll, Yt);
       return;
     }
     GemmDesc g{};
@@ -438,16 +446,16 @@ SketchOut sketch(const Ctx& x, int dtype, const View& X, const idcur_opts& o, in
               "fp16 scale");
     }
     if (!x.dry) {
-      if (o.omega && lowp)
-        pack(mr, o.omega, mr, 1);
-      else if (o.omega)
+      if (o.omega && lowp) {
+        // packed with the first product below
+      } else if (o.omega)
         x.check(copy2d_launch(dtype, l, mr, o.omega, mr, 1, Omt, 1, ll, x.s), "omega copy");
       else
         x.check(gaussian_launch(dtype, l, mr, o.seed, 0, Omt, 1, ll, x.s), "omega");
     }
   }
   if (o.omega && lowp)
-    gemm_lp(nc, mr, X.xc, X.xr, Yt);
+    gemm_lp(nc, mr, X.xc, X.xr, o.omega, mr, 1, Yt);
   else
     mul_t(Omt);
   for (int it = 0; it < o.q; ++it) {
@@ -456,11 +464,7 @@ SketchOut sketch(const Ctx& x, int dtype, const View& X, const idcur_opts& o, in
       orth_rows(x, dtype, Yt, Qyt, nc, l, ll);
     }
     if (lowp) {   // Z^T = X * orth(Y)^T
-      {
-        Stage st(x, "pack");
-        pack(nc, Qyt, 1, ll);
-      }
-      gemm_lp(mr, nc, X.xr, X.xc, Zt);
+      gemm_lp(mr, nc, X.xr, X.xc, Qyt, 1, ll, Zt);
     } else {
       GemmDesc g{};
       g.M = mr; g.N = l; g.K = nc;

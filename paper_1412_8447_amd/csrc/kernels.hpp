@@ -139,7 +139,20 @@ struct Gemm16Desc {
   int fp16;             // 0: BF16, 1: FP16
   const float* scale;   // device {s, 1/s} or NULL
   int splitk;
+  int b_chunked;        // B packed by pack16c_launch (required exactly when gemm16_wide holds)
 };
+// Whether gemm16_launch runs the wide kernel (256 < N <= 640 output columns,
+// aligned operands) for this shape and A layout; its B is then packed
+// chunk-major by pack16c_launch with gemm16_wide_npad(N) columns and
+// gemm16_wide_kchunks(K) chunks of 8 k.
+bool gemm16_wide(int64_t M, int64_t N, int64_t K, const float* A, int64_t sam, int64_t sak);
+int64_t gemm16_wide_npad(int64_t N);
+int64_t gemm16_wide_kchunks(int64_t K);
+// Chunk-major 16-bit packing: the 16-byte word (c, j) = round16(in(j, 8c .. 8c + 7))
+// at out[16 (c npad + j)] bytes, in(j, k) = in[j*sj + k*sk], zero outside
+// rows x cols; npad columns, kchunks chunks.
+hipError_t pack16c_launch(int fp16, int64_t rows, int64_t cols, const float* in, int64_t sj, int64_t sk, int64_t npad,
+                          int64_t kchunks, void* out, hipStream_t stream);
 int gemm16_pick_splitk(int64_t M, int64_t N, int64_t K, int num_cus);
 size_t gemm16_part_bytes(const Gemm16Desc& d);
 hipError_t gemm16_launch(const Gemm16Desc& d, void* part, hipStream_t stream, hipEvent_t ev0 = nullptr,

@@ -61,7 +61,7 @@ def _check_q0(Yt, B, om, prec):
 @pytest.mark.parametrize("m,n,l,scale", [(1000, 700, 37, 5e-2), (300, 2000, 210, 1.0), (4100, 130, 18, 3e6),
                                          (300, 515, 250, 1e-3),
                                          # sketch widths above 256: the wide form (one column tile), ragged
-                                         # stripes, a K split of four, and an odd row count that falls back
+                                         # stripes, a K split of four, odd row and column counts
                                          (1000, 704, 300, 1.0), (2000, 1504, 520, 2e-2), (5000, 600, 400, 1.0),
                                          (1001, 701, 300, 1.0)])
 def test_sketch_q0_matches_rounded_product(prec, row, m, n, l, scale):
