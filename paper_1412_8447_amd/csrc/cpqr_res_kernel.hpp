@@ -340,7 +340,13 @@ __global__ __launch_bounds__(NTH) void cpqr_res_kernel(CpqrArgs a) {
     // column (rows below j); in slot jt, x0 - alpha at row j, the staged column
     // below it and zero above
     const T vjt = mj ? (T)(x0 - alpha) : (mg ? f_at(4u * (uint32_t)(rgi + R * jt)) : (T)0);
-    auto vget = [&](int t) -> T { return t == jt ? vjt : f_at(4u * (uint32_t)(rgi + R * t)); };
+    // LDS addresses of slot t: the staged column's entry, the LDS column slots
+    auto vaddr = [&](int t) { return 4u * (uint32_t)(rgi + R * t); };
+    auto laddr = [&](int i, int t) { return ybase + (uint32_t)i * kSlotBytes + (uint32_t)t * (NTH * 4); };
+    constexpr int NLA = NL > 0 ? NL : 1;
+    // The two slot passes below load the reflector entry and the LDS columns of
+    // slot t + 1 while slot t's products run (slot jt's come from a run-time
+    // address before the first); the products keep their order.
     if (tid == 0) win[j] = w.i;
     // the winner itself becomes (alpha, 0, ..., 0) below row j and leaves the active set
     if (w.i >= c0 && w.i < c1) {
@@ -365,12 +371,28 @@ __global__ __launch_bounds__(NTH) void cpqr_res_kernel(CpqrArgs a) {
     double dot[NT];
 #pragma unroll
     for (int u = 0; u < NT; ++u) dot[u] = 0.0;
+    {
+      T pv = vjt, pl[NLA];
 #pragma unroll
-    for (int t = 0; t < RPL; ++t) {
-      if (t < jt) continue;
-      const double vt = (double)vget(t);
+      for (int i = 0; i < NL; ++i) pl[i] = f_at(laddr(i, jt));
 #pragma unroll
-      for (int u = 0; u < NT; ++u) dot[u] = fma(vt, (double)yget(u, t), dot[u]);
+      for (int t = 0; t < RPL; ++t) {
+        if (t < jt) continue;
+        const T cv = pv;
+        T cl[NLA];
+#pragma unroll
+        for (int i = 0; i < NL; ++i) cl[i] = pl[i];
+        if (t + 1 < RPL) {
+          pv = f_at(vaddr(t + 1));
+#pragma unroll
+          for (int i = 0; i < NL; ++i) pl[i] = f_at(laddr(i, t + 1));
+        }
+        const double vt = (double)cv;
+#pragma unroll
+        for (int u = 0; u < NC; ++u) dot[u] = fma(vt, (double)y[u][t], dot[u]);
+#pragma unroll
+        for (int i = 0; i < NL; ++i) dot[NC + i] = fma(vt, (double)cl[i], dot[NC + i]);
+      }
     }
     // the update pass reads the LDS slots again: without this the compiler keeps
     // the values the dot products loaded in registers until then
@@ -388,20 +410,35 @@ __global__ __launch_bounds__(NTH) void cpqr_res_kernel(CpqrArgs a) {
       ss[u] = 0.0;
       sj[u] = (T)0;
     }
+    {
+      T pv = vjt, pl[NLA];
 #pragma unroll
-    for (int t = 0; t < RPL; ++t) {
-      if (t < jt) continue;
-      const T vt = vget(t);
-      const bool at = t == jt, after = t > jt;   // the same on every lane
+      for (int i = 0; i < NL; ++i) pl[i] = f_at(laddr(i, jt));
 #pragma unroll
-      for (int u = 0; u < NT; ++u) {
-        const T yn = fmaf(mw[u], vt, yget(u, t));
-        yset(u, t, yn);
-        if constexpr (EXACT) {
-          const double q = (double)yn;
-          ss[u] += after ? q * q : 0.0;
+      for (int t = 0; t < RPL; ++t) {
+        if (t < jt) continue;
+        const T vt = pv;
+        T cl[NLA];
+#pragma unroll
+        for (int i = 0; i < NL; ++i) cl[i] = pl[i];
+        if (t + 1 < RPL) {
+          pv = f_at(vaddr(t + 1));
+#pragma unroll
+          for (int i = 0; i < NL; ++i) pl[i] = f_at(laddr(i, t + 1));
         }
-        sj[u] = at ? yn : sj[u];
+        const bool at = t == jt, after = t > jt;   // the same on every lane
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+          const T yo = u < NC ? y[u < NC ? u : 0][t] : cl[u < NC ? 0 : u - NC];
+          const T yn = fmaf(mw[u], vt, yo);
+          if (u < NC) y[u < NC ? u : 0][t] = yn;
+          else f_at(laddr(u - NC, t)) = yn;
+          if constexpr (EXACT) {
+            const double q = (double)yn;
+            ss[u] += after ? q * q : 0.0;
+          }
+          sj[u] = at ? yn : sj[u];
+        }
       }
     }
     // squared norm below row j of column u, summed over the group
