@@ -55,7 +55,11 @@ TRAFFIC = {
                ("gemm16w_kernel.hpp", "gemm16_kernel.hpp", "gemm16.hip", "gemm16_f16.hip"), "gemm16w_sources_sha"),
     "blk_c3": ("cpqr_blk_500x50000_k500_traffic.md", ("cpqr_blk.hip",), "cpqr_blk_sources_sha"),
     "res_c3": ("cpqr_onchip_500x50000_520x20000_k500_traffic.md",
-               ("cpqr_res_kernel.hpp", "cpqr_res.hip", "cpqr_reg_kernel.hpp", "cpqr_reg_f32.hip"), "cpqr_onchip_sources_sha"),
+               ("cpqr_res_kernel.hpp", "cpqr_res.hip", "cpqr_reg_kernel.hpp", "cpqr_reg_f32.hip"), "cpqr_onchip_sources_sha",
+               "res_traffic_bytes_per_launch"),
+    "reg_c3": ("cpqr_onchip_500x50000_520x20000_k500_traffic.md",
+               ("cpqr_res_kernel.hpp", "cpqr_res.hip", "cpqr_reg_kernel.hpp", "cpqr_reg_f32.hip"), "cpqr_onchip_sources_sha",
+               "reg_traffic_bytes_per_launch"),
 }
 
 
@@ -70,7 +74,8 @@ def source_hash(files):
 def read_traffic(which="fp32"):
     """HBM bytes per launch of a kernel from its committed counter summary, or
     None when the kernel's sources changed since the counters were taken."""
-    fname, sources, key = TRAFFIC[which]
+    fname, sources, key, *field = TRAFFIC[which]
+    field = field[0] if field else "traffic_bytes_per_launch"
     path = os.path.join(ROOT, "profiles", fname)
     if not os.path.exists(path):
         return None
@@ -80,9 +85,9 @@ def read_traffic(which="fp32"):
             m = re.match(r"^\s*(\w+)\s*=\s*(\S+)\s*$", line)
             if m:
                 kv[m.group(1)] = m.group(2)
-    if kv.get(key) != source_hash(sources) or "traffic_bytes_per_launch" not in kv:
+    if kv.get(key) != source_hash(sources) or field not in kv:
         return None
-    return int(float(kv["traffic_bytes_per_launch"]))
+    return int(float(kv[field]))
 
 
 def library_gemm(torch, A, l, reps=5):
@@ -593,7 +598,7 @@ def bench_headline(args, P, synth, torch, dev):
     # or the row ID's pivoted QR (row_cpqr times its launch alone)
     dom = max((s_ for s_ in ("sketch_gemm", "cpqr", "row_cpqr") if s_ in stages), key=lambda s_: stages[s_])
     roof = stage_roofline(dom, st, args.steps, m, n, k, l, q, head)
-    roof["traffic"] = read_traffic({"sketch_gemm": "g16_c3", "row_cpqr": "res_c3", "cpqr": "res_c3"}[dom])
+    roof["traffic"] = read_traffic({"sketch_gemm": "g16_c3", "row_cpqr": "res_c3", "cpqr": "reg_c3"}[dom])
     res.update(ms=ms, e=e_head, stages=stages, roofline=roof, flops=flops, cfg=cfg, J=out["J"].clone())
     # the other precisions of the same step
     per = {}
