@@ -214,7 +214,11 @@ void chol_inv(const Ctx& x, int mode, const double* G, int64_t gr, int64_t gc, i
 // of the row space (the pivoted QR is invariant to which basis), so one pass
 // with a tiny shift s, which rules out breakdown, is enough.
 // Q^T = orth(V^T): V^T and Q^T are N x l with leading dimension ld.
-void orth_rows(const Ctx& x, int dtype, const void* Vt, void* Qt, int64_t N, int l, int64_t ld) {
+// With q32 (FP32 data whose basis is next rounded to 16 bits for a matrix-core
+// product) the last product runs on the FP32 matrix cores with L^{-T} rounded to
+// FP32: its error, a few FP32 units per entry, lies far below the 16-bit
+// rounding that follows; Q stays in the row space of V either way.
+void orth_rows(const Ctx& x, int dtype, const void* Vt, void* Qt, int64_t N, int l, int64_t ld, bool q32 = false) {
   double* G = static_cast<double*>(x.ar->take((size_t)l * l * 8));
   double* L = static_cast<double*>(x.ar->take((size_t)l * l * 8));
   double* Li = static_cast<double*>(x.ar->take((size_t)l * l * 8));
@@ -234,6 +238,14 @@ void orth_rows(const Ctx& x, int dtype, const void* Vt, void* Qt, int64_t N, int
   q.C = Qt; q.ldc = ld;
   q.a_type = dtype; q.b_type = 0; q.acc_type = 0; q.out_type = dtype;
   q.alpha = 1.0; q.beta = 0.0;
+  if (q32 && dtype == IDCUR_F32) {
+    // B(kk, j) = L^{-1}(j, kk) as an l x ld FP32 row-major matrix
+    float* Lt = static_cast<float*>(x.ar->take((size_t)l * ld * 4));
+    if (!x.dry) x.check(f64_to_f32_t_launch(l, l, Li, l, Lt, ld, x.s), "L^{-T} to FP32");
+    q.B = Lt; q.sbk = ld; q.sbn = 1;
+    q.b_rows_padded = true;
+    q.in_type = 1; q.b_type = 1; q.acc_type = 1;
+  }
   gemm(x, q);
 }
 
@@ -461,7 +473,7 @@ SketchOut sketch(const Ctx& x, int dtype, const View& X, const idcur_opts& o, in
   for (int it = 0; it < o.q; ++it) {
     {
       Stage st(x, "orth");
-      orth_rows(x, dtype, Yt, Qyt, nc, l, ll);
+      orth_rows(x, dtype, Yt, Qyt, nc, l, ll, lowp);
     }
     if (lowp) {   // Z^T = X * orth(Y)^T
       gemm_lp(mr, nc, X.xr, X.xc, Qyt, 1, ll, Zt);
@@ -478,7 +490,7 @@ SketchOut sketch(const Ctx& x, int dtype, const View& X, const idcur_opts& o, in
     }
     {
       Stage st(x, "orth");
-      orth_rows(x, dtype, Zt, Qzt, mr, l, ll);
+      orth_rows(x, dtype, Zt, Qzt, mr, l, ll, lowp);
     }
     mul_t(Qzt);
   }
@@ -537,9 +549,11 @@ ColId column_id(const Ctx& x, int dtype, const View& X, const idcur_opts& o, int
 }
 
 // Row ID of C (m x kcap, row-major ld kcap) with rank k_dev: the full-rank ID of
-// C^T, giving I (m) and Tr (k x (m-k), ldtr); k_out_r receives its rank.
+// C^T, giving I (m) and, with want_tr, Tr (k x (m-k), ldtr); k_out_r receives
+// its rank. The CUR needs only the row pivots (R = A(I(1:k), :) and U from the
+// least-squares solve U R = V*), so it skips the interpolation matrix.
 void row_id_of_c(const Ctx& x, int dtype, const void* C, int64_t ldc, int64_t m, int kcap, const int* k_dev, int* k_out_r, int* I,
-                 void* Tr, int64_t ldtr, double t_reg, double t_svd) {
+                 bool want_tr, void* Tr, int64_t ldtr, double t_reg, double t_svd) {
   const CpqrPlan pl = cpqr_plan((int)esz(dtype), kcap, (int)m, kcap, x.c->num_cus);
   void* rec = x.ar->take(pl.rec_bytes + pl.fin_bytes);
   void* cvals = x.ar->take(pl.cvals_bytes);
@@ -564,6 +578,7 @@ void row_id_of_c(const Ctx& x, int dtype, const void* C, int64_t ldc, int64_t m,
     Stage sk(x, "row_cpqr");   // the pivoted QR launch alone (inside the row_id stage)
     x.check(cpqr_launch(dtype, pl, a, x.s), "cpqr(row)");
   }
+  if (!want_tr) return;
   Stage st(x, "row_id");
   interp_matrix(x, dtype, S, m, I, m, kcap, k_out_r, Tr, ldtr, t_reg, t_svd);
 }
@@ -698,11 +713,11 @@ void execute(idcur_ctx* ctx, int op, int dtype, int64_t m, int64_t n, const void
   }
   void* Tr = out.Tr;
   int64_t ldtr = out.ldtr;
-  if (!Tr) {
+  if (!Tr && op == OP_TWO) {
     Tr = ar.take((size_t)kcap * m * esz(dtype));
     ldtr = m;
   }
-  row_id_of_c(x, dtype, C, ldc, m, kcap, out.k_out, out.k_out + 1, out.I, Tr, ldtr, o.t_reg, o.t_svd);
+  row_id_of_c(x, dtype, C, ldc, m, kcap, out.k_out, out.k_out + 1, out.I, op == OP_TWO, Tr, ldtr, o.t_reg, o.t_svd);
   if (op == OP_TWO) return;
   // CUR: R = A(I(1:k), :), optional C output, then U
   void* R = out.R;
@@ -1219,8 +1234,7 @@ void execute_cur_csc(idcur_ctx* ctx, int dtype, const Csc& a, const idcur_opts& 
                                    x.c->dstatus, x.s),
             "gather C");
   }
-  void* Tr = ar.take((size_t)kcap * m * esz(dtype));
-  row_id_of_c(x, dtype, C, kcap, m, kcap, out.k_out, out.k_out + 1, out.I, Tr, m, o.t_reg, o.t_svd);
+  row_id_of_c(x, dtype, C, kcap, m, kcap, out.k_out, out.k_out + 1, out.I, false, nullptr, 0, o.t_reg, o.t_svd);
   void* R = ar.take((size_t)kcap * n * esz(dtype));
   int* slot = static_cast<int*>(ar.take((size_t)m * sizeof(int)));
   if (!ar.dry) {

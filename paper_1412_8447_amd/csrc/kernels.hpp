@@ -266,6 +266,10 @@ hipError_t gaussian_launch(int dtype, int64_t rows, int64_t cols, uint64_t seed,
 // out(r, c) = in(r, c) for an r x c matrix with strides (transpose when swapped).
 hipError_t copy2d_launch(int dtype, int64_t rows, int64_t cols, const void* in, int64_t sir, int64_t sic,
                          void* out, int64_t sor, int64_t soc, hipStream_t stream);
+// out(j, i) = (float) in(i, j) (in: rows x cols, ld ldi; out: cols x ldo with
+// ldo >= rows, columns [rows, ldo) zeroed).
+hipError_t f64_to_f32_t_launch(int64_t rows, int64_t cols, const double* in, int64_t ldi, float* out, int64_t ldo,
+                               hipStream_t stream);
 // Gather columns: out(i, s) = A(i, idx[s]) for s < k (k = *k_dev if set), row-major out.
 hipError_t gather_cols_launch(int dtype, int64_t m, const void* A, int64_t lda, const int* idx, int k_host,
                               const int* k_dev, void* out, int64_t ldo, int out_type, hipStream_t stream);

@@ -51,6 +51,17 @@ __global__ void gaussian_kernel(int64_t rows, int64_t cols, uint64_t seed, uint6
   }
 }
 
+// out(j, i) = (float) in(i, j) for i < rows, j < cols; out is cols x ldo
+// (row-major) and its columns [rows, ldo) are zeroed.
+__global__ void f64_to_f32_t_kernel(int64_t rows, int64_t cols, const double* in, int64_t ldi, float* out,
+                                    int64_t ldo) {
+  const int64_t total = cols * ldo;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = e / ldo, i = e % ldo;
+    out[e] = i < rows ? (float)in[i * ldi + j] : 0.0f;
+  }
+}
+
 template <typename T>
 __global__ void copy2d_kernel(int64_t rows, int64_t cols, const T* in, int64_t sir, int64_t sic, T* out, int64_t sor,
                               int64_t soc) {
@@ -314,6 +325,15 @@ hipError_t copy2d_launch(int dtype, int64_t rows, int64_t cols, const void* in, 
   else
     hipLaunchKernelGGL(copy2d_kernel<double>, dim3(g), dim3(256), 0, stream, rows, cols, static_cast<const double*>(in),
                        sir, sic, static_cast<double*>(out), sor, soc);
+  return hipGetLastError();
+}
+
+hipError_t f64_to_f32_t_launch(int64_t rows, int64_t cols, const double* in, int64_t ldi, float* out, int64_t ldo,
+                               hipStream_t stream) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  if (ldo < rows) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(f64_to_f32_t_kernel, dim3(grid_for(cols * ldo)), dim3(256), 0, stream, rows, cols, in, ldi, out,
+                     ldo);
   return hipGetLastError();
 }
 

@@ -18,7 +18,7 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU container
     pytest.skip("no GPU", allow_module_level=True)
 
 import paper_1412_8447_amd as P  # noqa: E402
-from gpu_helpers import say, to_dev  # noqa: E402
+from gpu_helpers import say, to_dev, clear_prefix, check_perm  # noqa: E402
 
 
 @pytest.mark.parametrize("m,n,k,delta", [(300, 200, 40, 1e-6), (257, 333, 37, 1e-4), (129, 70, 64, 1e-2)])
@@ -104,3 +104,56 @@ def test_full_size_fp32_sketched():
         f"{b.T.abs().max().item():.3g}")
     assert np.isfinite(rb) and rb <= 1.02 * ra
     assert b.T.abs().max().item() <= a.T.abs().max().item() * (1 + 1e-3)
+
+
+def test_full_size_fp32_against_oracle():
+    """The same workload against the FP64 oracle (Section 4.1, the Tikhonov form
+    with t_reg = 1e-4, after Algorithm 4 with one power step of Section 5.3), the
+    sketch matrix drawn on the device and given to both sides:
+    * against the oracle's stabilized ID of the device's own sketch: J identical
+      on the clear-gap prefix (1e-4);
+    * T against the oracle's Tikhonov solve for the device's pivots on the same
+      sketch, within max(1e-3, 50 cond u32) relative Frobenius, cond that of the
+      regularized least-squares system [S11; lam I] (at most about sqrt(k) / t_reg);
+    * the ID error within 1.05x of the oracle's stabilized ID on its own FP64
+      sketch of the same input and sketch matrix."""
+    m, n, k, p, q, treg = 20000, 10000, 200, 10, 1, 1e-4
+    say(f"stabilized T full size fp32 {m}x{n} k={k} against the oracle")
+    sig = (np.arange(min(m, n), dtype=np.float64) + 1.0) ** -2.0
+    A = synth.lowrank_torch(m, n, sig, seed=441, device="cuda").to(torch.float32).contiguous()
+    om = P.gaussian(k + p, m, seed=77, dtype=torch.float32)
+    got = P.id_col(A, k, p=p, q=q, omega=om, t_reg=treg)
+    J = got.J.cpu().numpy()
+    check_perm(J, n)
+    Yt = P.sketch(A, k, p=p, q=q, omega=om).cpu().numpy().astype(np.float64)
+    ref_y = oracle.id_col(Yt.T, k, t_reg=treg)   # the oracle's stabilized ID of the device sketch
+    c = clear_prefix(ref_y.qr.gaps, 1e-4)
+    say(f"  clear pivots {c} of {k}")
+    assert c >= 10
+    assert np.array_equal(J[:c], ref_y.J[:c])
+    # T for the device's own pivots: the oracle's Tikhonov solve (interp_tikhonov)
+    # on S11, S12 from a Householder QR of the sketch's columns J[:k]
+    Y = Yt.T
+    Q1, S11 = np.linalg.qr(Y[:, J[:k]])
+    S12 = Q1.T @ Y[:, J[k:]]
+    T_ref = interp_tikhonov(S11, S12, treg)
+    lam = tikhonov_weight(S11, treg)
+    sv = np.linalg.svd(np.vstack([S11, lam * np.eye(k)]), compute_uv=False)
+    cond = sv[0] / sv[-1]
+    T = got.T.cpu().numpy().astype(np.float64)
+    assert T.shape == T_ref.shape
+    dT = np.linalg.norm(T - T_ref) / np.linalg.norm(T_ref)
+    bound = max(1e-3, 50.0 * cond * 2.0**-24)
+    say(f"  |dT|_F/|T|_F = {dT:.3e} (cond of the regularized system {cond:.3e}, bound {bound:.3e})")
+    assert dT <= bound
+    A64, om64 = A.cpu().numpy().astype(np.float64), om.cpu().numpy().astype(np.float64)
+    ref = oracle.id_col(A64, k, omega=om64, q=q, t_reg=treg)
+    del A64
+    Jr = torch.as_tensor(ref.J.astype(np.int32), device=A.device)
+    Tr = torch.as_tensor(np.ascontiguousarray(ref.T, dtype=np.float32), device=A.device)
+    kout = torch.tensor([k, 0], dtype=torch.int32, device=A.device)
+    eg = P.id_error(A, got.J, got.T, got.kout, k).cpu().numpy()
+    eo = P.id_error(A, Jr, Tr, kout, k).cpu().numpy()
+    e_g, e_o = np.sqrt(eg[0] / eg[1]), np.sqrt(eo[0] / eo[1])
+    say(f"  e_ID device {e_g:.4e}, FP64 oracle {e_o:.4e}")
+    assert e_g <= 1.05 * e_o
