@@ -584,7 +584,9 @@ void row_id_of_c(const Ctx& x, int dtype, const void* C, int64_t ldc, int64_t m,
 }
 
 // U = argmin |U R - V*|_F through the QR of R^T (Cholesky QR twice, FP64):
-// R^T = Q S_R with S_R = L2^T L1^T, so U^T = S_R^{-1} Q^T V = L1^{-T} L2^{-T} Q^T V.
+// R^T = Q S_R with S_R = L2^T L1^T and Q^T = L2^{-1} Q1^T, so
+// U^T = S_R^{-1} Q^T V = L1^{-T} L2^{-T} L2^{-1} (Q1^T V): Q itself is never
+// formed; L2^{-1} is applied to the k x k product Q1^T V instead.
 // Every step is a matrix-core product with the explicit triangular inverses.
 // R: kr x n (row-major ldr), V* from (J, T); k = kout[0] columns, kr = kout[1].
 // With `corr` (A, lda, m and C = A(:, J(1:k)), m x kcap ld kcap given) the right
@@ -603,7 +605,7 @@ void solve_u(const Ctx& x, int dtype, const void* R, int64_t ldr, int64_t n, int
   double* L2 = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
   double* L2i = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
   double* Q1t = static_cast<double*>(x.ar->take((size_t)kcap * n * 8));
-  double* Qt = static_cast<double*>(x.ar->take((size_t)kcap * n * 8));
+  double* B1 = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
   double* V = static_cast<double*>(x.ar->take((size_t)n * kcap * 8));
   double* Bls = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
   double* Y1 = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
@@ -624,11 +626,10 @@ void solve_u(const Ctx& x, int dtype, const void* R, int64_t ldr, int64_t n, int
   chol_inv(x, 0, G, kcap, 1, kcap, kr_dev, L1, kcap, L1i, kcap, 1e-15, "chol(R)", false);
   // Q1^T = L1^{-1} R
   prod(kcap, n, kcap, L1i, kcap, 1, 0, R, ldr, 1, dtype, Q1t, n, 0, kr_dev, nullptr, kr_dev);
-  // G2 = Q1^T Q1, L2 L2^T = G2, Q^T = L2^{-1} Q1^T
+  // G2 = Q1^T Q1, L2 L2^T = G2
   prod(kcap, kcap, n, Q1t, n, 1, 0, Q1t, 1, n, 0, G, kcap, 0, kr_dev, kr_dev, nullptr);
   chol_inv(x, 0, G, kcap, 1, kcap, kr_dev, L2, kcap, L2i, kcap, 0.0, "chol(Q1)", false);
-  prod(kcap, n, kcap, L2i, kcap, 1, 0, Q1t, n, 1, 0, Qt, n, 0, kr_dev, nullptr, kr_dev);
-  // Bls = Q^T V (kr x k)
+  // Bls = Q^T V = L2^{-1} (Q1^T V) (kr x k)
   if (!x.dry) x.check(build_v_launch(dtype, T, ldt, J, n, kcap, k_dev, V, kcap, x.s), "build V");
   if (corr) {
     double* Gc = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
@@ -660,7 +661,8 @@ void solve_u(const Ctx& x, int dtype, const void* R, int64_t ldr, int64_t n, int
     h.n_dev = k_dev; h.k_dev = k_dev;
     gemm(x, h);
   }
-  prod(kcap, kcap, n, Qt, n, 1, 0, V, kcap, 1, 0, Bls, kcap, 0, kr_dev, k_dev, nullptr);
+  prod(kcap, kcap, n, Q1t, n, 1, 0, V, kcap, 1, 0, B1, kcap, 0, kr_dev, k_dev, nullptr);
+  prod(kcap, kcap, kcap, L2i, kcap, 1, 0, B1, kcap, 1, 0, Bls, kcap, 0, kr_dev, k_dev, kr_dev);
   // Y1 = L2^{-T} Bls  (A(i, kk) = L2i[kk][i])
   prod(kcap, kcap, kcap, L2i, 1, kcap, 0, Bls, kcap, 1, 0, Y1, kcap, 0, kr_dev, k_dev, kr_dev);
   // U = Y1^T L1^{-1}  (k x kr): A(i, kk) = Y1[kk][i]
