@@ -77,8 +77,13 @@ size_t gemm_part_bytes(const GemmDesc& d) {
   return (size_t)d.splitk * d.M * d.N * (d.acc_type == 1 ? 4 : 8);
 }
 
-int gemm_pick_splitk(int64_t M, int64_t N, int64_t K, int num_cus, bool acc64) {
-  const int64_t stripes = ceil_div(M, BM) * ceil_div(N, 16 * pick_nt(N, acc64));
+int gemm_pick_splitk(int64_t M, int64_t N, int64_t K, int num_cus, bool acc64, bool lower) {
+  const int64_t gx = ceil_div(M, BM), bn = 16 * pick_nt(N, acc64), gy = ceil_div(N, bn);
+  int64_t stripes = gx * gy;
+  if (lower) {   // tiles that meet the lower triangle
+    stripes = 0;
+    for (int64_t y = 0; y < gy; ++y) stripes += std::max<int64_t>(0, gx - (y * bn) / BM);
+  }
   int s = 1;
   // aim for at least 4 workgroups per CU, keep >= 256 K per split
   while (stripes * s < 4 * num_cus && K / (2 * s) >= 256 && s < 64) s *= 2;
@@ -87,7 +92,7 @@ int gemm_pick_splitk(int64_t M, int64_t N, int64_t K, int num_cus, bool acc64) {
 
 int gemm_pick_splitk_desc(const GemmDesc& d, int num_cus) {
   if (thin_f32_eligible(d)) return thin_f32_pick_splitk(d.M, d.N, d.K, num_cus);
-  return gemm_pick_splitk(d.M, d.N, d.K, num_cus, d.acc_type == 0);
+  return gemm_pick_splitk(d.M, d.N, d.K, num_cus, d.acc_type == 0, d.lower && d.M == d.N);
 }
 
 hipError_t gemm_launch(const GemmDesc& d, void* part, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1) {
@@ -119,6 +124,7 @@ hipError_t gemm_launch(const GemmDesc& d, void* part, hipStream_t stream, hipEve
   k.out_type = d.out_type;
   k.alpha = d.alpha; k.beta = d.beta;
   k.m_dev = d.m_dev; k.n_dev = d.n_dev; k.k_dev = d.k_dev;
+  k.lower = d.lower && d.M == d.N;
   const int ta_ = d.a_type >= 0 ? d.a_type : d.in_type, tb_ = d.b_type >= 0 ? d.b_type : d.in_type;
   auto aligned = [&](const void* p, int64_t other_stride, int t) {
     return ((uintptr_t)p % (4 * (t == 1 ? 4 : 8)) == 0) && (other_stride % 4 == 0);

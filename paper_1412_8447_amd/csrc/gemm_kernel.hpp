@@ -45,6 +45,7 @@ struct KArgs {
   const void* X; int64_t ldx; int x_type; double* rpart;
   const int* k_dev;            // optional device bound on K
   int gx, gy, gz;              // tile grid: row stripes, column tiles, K splits
+  int lower;                   // skip tiles wholly above the diagonal (square C)
 };
 
 // Tiles are numbered t = x + gx*(y + gy*z) (z = K split). The launch is 1-D with
@@ -93,6 +94,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(KArgs p) {
     if (RESID && threadIdx.x == 0) p.rpart[(int64_t)by * p.gx + bx] = 0.0;
     return;
   }
+  if (!RESID && p.lower && n0 >= m0 + BM) return;
   const int64_t Kb = p.k_dev ? min((int64_t)*p.k_dev, p.K) : p.K;
   const int64_t kb = (int64_t)bz * p.kps;
   const int64_t ke = min(Kb, kb + p.kps);

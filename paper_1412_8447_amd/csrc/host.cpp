@@ -154,7 +154,8 @@ void gemm(const Ctx& x, GemmDesc d, const char* stage = nullptr) {
 //   mode 1:  X_pp = inverse of the given factor's diagonal block;
 // then, block row by block row, X(r, 0:o) = -X_rr (F(r, 0:o) X(0:o, 0:o)) with F
 // the lower factor. A device order c_dev is handled by padding G with the
-// identity, whose factor and inverse are the identity.
+// identity, whose factor and inverse are the identity. Only the lower triangle
+// of G is read (its Gram products compute no more).
 constexpr int kCholDirect = 256;
 
 void chol_inv(const Ctx& x, int mode, const double* G, int64_t gr, int64_t gc, int c, const int* c_dev, double* L,
@@ -170,7 +171,7 @@ void chol_inv(const Ctx& x, int mode, const double* G, int64_t gr, int64_t gc, i
   double* sh = (mode == 0 && shift_rel > 0.0) ? static_cast<double*>(x.ar->take(8)) : nullptr;
   if (!x.dry) {
     if (sh) x.check(diag_shift_launch(G, gr, gc, c, c_dev, shift_rel, sh, x.s), what);
-    x.check(pad_square_launch(G, gr, gc, c, c_dev, mode == 1 ? 1 : 0, sh, P, c, x.s), what);
+    x.check(pad_square_launch(G, gr, gc, c, c_dev, 1, sh, P, c, x.s), what);
     if (mode == 0) x.check(zero2d_launch(L, c, c, ldl, x.s), what);
     x.check(zero2d_launch(X, c, c, ldx, x.s), what);
   }
@@ -229,6 +230,7 @@ void orth_rows(const Ctx& x, int dtype, const void* Vt, void* Qt, int64_t N, int
   g.C = G; g.ldc = l;
   g.in_type = dtype; g.acc_type = 0; g.out_type = 0;
   g.alpha = 1.0; g.beta = 0.0;
+  g.lower = true;   // the factorisation reads the lower triangle only
   gemm(x, g);
   chol_inv(x, 0, G, l, 1, l, nullptr, L, l, Li, l, 1e-14, "chol", false);   // only L^{-1} is used
   GemmDesc q{};   // Q^T = V^T L^{-T}
@@ -611,8 +613,9 @@ void solve_u(const Ctx& x, int dtype, const void* R, int64_t ldr, int64_t n, int
   double* Y1 = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
   auto prod = [&](int64_t M, int64_t N, int64_t K, const void* Am, int64_t sam, int64_t sak, int at, const void* Bm,
                   int64_t sbk, int64_t sbn, int bt, void* Cm, int64_t ldc, int ct, const int* md, const int* nd,
-                  const int* kd) {
+                  const int* kd, bool lower = false) {
     GemmDesc g{};
+    g.lower = lower;
     g.M = M; g.N = N; g.K = K;
     g.A = Am; g.sam = sam; g.sak = sak; g.a_type = at;
     g.B = Bm; g.sbk = sbk; g.sbn = sbn; g.b_type = bt;
@@ -622,12 +625,12 @@ void solve_u(const Ctx& x, int dtype, const void* R, int64_t ldr, int64_t n, int
     gemm(x, g);
   };
   // G1 = R R^T, L1 L1^T = G1
-  prod(kcap, kcap, n, R, ldr, 1, dtype, R, 1, ldr, dtype, G, kcap, 0, kr_dev, kr_dev, nullptr);
+  prod(kcap, kcap, n, R, ldr, 1, dtype, R, 1, ldr, dtype, G, kcap, 0, kr_dev, kr_dev, nullptr, true);
   chol_inv(x, 0, G, kcap, 1, kcap, kr_dev, L1, kcap, L1i, kcap, 1e-15, "chol(R)", false);
   // Q1^T = L1^{-1} R
   prod(kcap, n, kcap, L1i, kcap, 1, 0, R, ldr, 1, dtype, Q1t, n, 0, kr_dev, nullptr, kr_dev);
   // G2 = Q1^T Q1, L2 L2^T = G2
-  prod(kcap, kcap, n, Q1t, n, 1, 0, Q1t, 1, n, 0, G, kcap, 0, kr_dev, kr_dev, nullptr);
+  prod(kcap, kcap, n, Q1t, n, 1, 0, Q1t, 1, n, 0, G, kcap, 0, kr_dev, kr_dev, nullptr, true);
   chol_inv(x, 0, G, kcap, 1, kcap, kr_dev, L2, kcap, L2i, kcap, 0.0, "chol(Q1)", false);
   // Bls = Q^T V = L2^{-1} (Q1^T V) (kr x k)
   if (!x.dry) x.check(build_v_launch(dtype, T, ldt, J, n, kcap, k_dev, V, kcap, x.s), "build V");

@@ -102,9 +102,12 @@ struct GemmDesc {
   const int* n_dev; // optional device bound on N
   const int* k_dev; // optional device bound on K
   bool b_rows_padded = false;   // every row of B is allocated up to round_up(N, 4)
+  // C = A A^T-like square result of which only the lower triangle is read: tiles
+  // wholly above the diagonal are skipped and that part of C is left unspecified
+  bool lower = false;
 };
 size_t gemm_part_bytes(const GemmDesc& d);
-int gemm_pick_splitk(int64_t M, int64_t N, int64_t K, int num_cus, bool acc64);
+int gemm_pick_splitk(int64_t M, int64_t N, int64_t K, int num_cus, bool acc64, bool lower = false);
 // Split count for this descriptor (the FP32 thin kernel has its own choice).
 int gemm_pick_splitk_desc(const GemmDesc& d, int num_cus);
 // FP32 thin-output kernel (gemm_thin.hip), used by gemm_launch when eligible.
