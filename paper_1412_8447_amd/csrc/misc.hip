@@ -21,13 +21,18 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 ctr, uint2 key) {
   return ctr;
 }
 
+// Counter g yields elements 4g .. 4g+3 of the row-major rows x cols matrix. With
+// colmajor (cols % 4 == 0, out column-major: sor == 1) consecutive threads take
+// the same four columns of consecutive rows, so that the stores coalesce; the
+// values are the same either way.
 template <typename T>
 __global__ void gaussian_kernel(int64_t rows, int64_t cols, uint64_t seed, uint64_t sid, T* out, int64_t sor,
-                                int64_t soc) {
+                                int64_t soc, int colmajor) {
   const int64_t total = rows * cols;
   const int64_t ngroups = (total + 3) / 4;
   const uint2 key = make_uint2((uint32_t)seed, (uint32_t)(seed >> 32));
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ngroups; g += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ngroups; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = colmajor ? (e % rows) * (cols / 4) + e / rows : e;
     const uint4 x = philox4x32_10(make_uint4((uint32_t)g, (uint32_t)(g >> 32), (uint32_t)sid, 0u), key);
     const uint32_t w[4] = {x.x, x.y, x.z, x.w};
     double z[4];
@@ -295,12 +300,13 @@ hipError_t gaussian_launch(int dtype, int64_t rows, int64_t cols, uint64_t seed,
                            int64_t soc, hipStream_t stream) {
   if (rows <= 0 || cols <= 0) return hipSuccess;
   const unsigned g = grid_for(ceil_div(rows * cols, 4));
+  const int colmajor = sor == 1 && soc != 1 && cols % 4 == 0 && rows > 1;
   if (dtype == 1)
     hipLaunchKernelGGL(gaussian_kernel<float>, dim3(g), dim3(256), 0, stream, rows, cols, seed, sid,
-                       static_cast<float*>(out), sor, soc);
+                       static_cast<float*>(out), sor, soc, colmajor);
   else
     hipLaunchKernelGGL(gaussian_kernel<double>, dim3(g), dim3(256), 0, stream, rows, cols, seed, sid,
-                       static_cast<double*>(out), sor, soc);
+                       static_cast<double*>(out), sor, soc, colmajor);
   return hipGetLastError();
 }
 

@@ -39,6 +39,18 @@ def test_gaussian_matches_oracle_generator():
     assert np.abs(g32 - want32).max() <= 1e-6
 
 
+@pytest.mark.parametrize("m", [400, 402])
+def test_sketch_omega_layout(m):
+    """The sketch draws Omega^T column-major (coalesced stores when m % 4 == 0):
+    the FP64 sketch of the identity is Omega^T exactly, the oracle's Philox draw."""
+    k, p, seed = 30, 6, 4321
+    say(f"sketch of I_{m}: Omega^T layout")
+    Yt = P.sketch(torch.eye(m, dtype=torch.float64, device="cuda"), k, p=p, q=0, seed=seed).cpu().numpy()
+    want = oracle.philox.gaussian_omega(k + p, m, seed=seed)
+    assert np.abs(Yt - want.T).max() <= 1e-12 * max(1.0, np.abs(want).max())
+    assert torch.equal(torch.as_tensor(Yt), P.gaussian(k + p, m, seed=seed, dtype=torch.float64).cpu().T)
+
+
 # ---------------------------------------------------------------------------
 # Deterministic column ID (Algorithm 1)
 # ---------------------------------------------------------------------------
