@@ -219,17 +219,33 @@ __global__ void add_gathered_kernel(const double* Q, int64_t ldq, const int* J, 
   }
 }
 
+// V (n x kcap, ld ldv): row J[p] is e_p for p < k and column p - k of T for
+// p >= k (zeros past k): the rows of [I_k; T^T] in the order J. 64 x 64 tiles of
+// (r, p) pass through LDS, so that T is read along p and V written along r,
+// both coalesced.
 template <typename T>
-__global__ void build_v_kernel(const T* Tm, int64_t ldt, const int* J, int64_t n, int kcap, const int* k_dev, double* V,
-                               int64_t ldv) {
+__global__ __launch_bounds__(256) void build_v_kernel(const T* Tm, int64_t ldt, const int* J, int64_t n, int kcap,
+                                                      const int* k_dev, double* V, int64_t ldv) {
+  __shared__ double tile[64][65];
   const int k = k_dev ? min(*k_dev, kcap) : kcap;
-  const int64_t total = (int64_t)kcap * n;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = e / n, p = e % n;
+  const int64_t p0 = (int64_t)blockIdx.x * 64;
+  const int r0 = (int)blockIdx.y * 64;
+  const int lo = threadIdx.x & 63, hi = threadIdx.x >> 6;
+  for (int i = hi; i < 64; i += 4) {
+    const int r = r0 + i;
+    const int64_t p = p0 + lo;
     double v = 0.0;
-    if (p < k) v = (r == p) ? 1.0 : 0.0;
-    else if (r < k) v = (double)Tm[r * ldt + (p - k)];
-    V[(int64_t)J[p] * ldv + r] = v;
+    if (r < kcap && p < n) {
+      if (p < k) v = (r == p) ? 1.0 : 0.0;
+      else if (r < k) v = (double)Tm[(int64_t)r * ldt + (p - k)];
+    }
+    tile[i][lo] = v;
+  }
+  __syncthreads();
+  for (int i = hi; i < 64; i += 4) {
+    const int64_t p = p0 + i;
+    const int r = r0 + lo;
+    if (p < n && r < kcap) V[(int64_t)J[p] * ldv + r] = tile[lo][i];
   }
 }
 
@@ -412,12 +428,13 @@ hipError_t zero_launch(void* p, size_t bytes, hipStream_t stream) {
 hipError_t build_v_launch(int dtype, const void* T, int64_t ldt, const int* J, int64_t n, int kcap, const int* k_dev,
                           double* V, int64_t ldv, hipStream_t stream) {
   if (n <= 0 || kcap <= 0) return hipSuccess;
-  const unsigned g = grid_for((int64_t)kcap * n);
+  if (ldv < kcap || ceil_div(n, 64) > 0x7fffffff || ceil_div(kcap, 64) > 65535) return hipErrorInvalidValue;
+  const dim3 g((unsigned)ceil_div(n, 64), (unsigned)ceil_div(kcap, 64));
   if (dtype == 1)
-    hipLaunchKernelGGL(build_v_kernel<float>, dim3(g), dim3(256), 0, stream, static_cast<const float*>(T), ldt, J, n, kcap,
+    hipLaunchKernelGGL(build_v_kernel<float>, g, dim3(256), 0, stream, static_cast<const float*>(T), ldt, J, n, kcap,
                        k_dev, V, ldv);
   else
-    hipLaunchKernelGGL(build_v_kernel<double>, dim3(g), dim3(256), 0, stream, static_cast<const double*>(T), ldt, J, n,
+    hipLaunchKernelGGL(build_v_kernel<double>, g, dim3(256), 0, stream, static_cast<const double*>(T), ldt, J, n,
                        kcap, k_dev, V, ldv);
   return hipGetLastError();
 }
