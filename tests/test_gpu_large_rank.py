@@ -1,7 +1,8 @@
 """GPU parity at ranks and sketch widths above 256, where every k x k (and l x l)
 Cholesky factor and triangular inverse runs in the blocked form (diagonal blocks
 on the one-workgroup kernel, the rest as FP64 matrix-core products), against the
-FP64 oracle. FP64 data, so pivots, T and U are compared tightly."""
+FP64 oracle: orders just above 256 (two blocks) up to 520 (three). FP64 data, so
+pivots, T and U are compared tightly."""
 import numpy as np
 import pytest
 
@@ -23,7 +24,7 @@ def _case(m, n, seed, decay):
     return synth.lowrank(m, n, synth.sigma_exp(min(m, n), decay), seed=seed)
 
 
-@pytest.mark.parametrize("m,n,k", [(700, 600, 300), (900, 1100, 520)])
+@pytest.mark.parametrize("m,n,k", [(700, 600, 300), (900, 1100, 520), (700, 600, 280), (650, 700, 288)])
 def test_id_col_det_fp64_large_k(m, n, k):
     say(f"id_col det fp64 {m}x{n} k={k}")
     A = _case(m, n, seed=k, decay=0.4 * k)
@@ -45,9 +46,10 @@ def test_id_col_det_fp64_large_k(m, n, k):
         assert e_g <= (1 + 1e-6) * e_o
 
 
-def test_sketch_wide_orth_q1_fp64():
-    # l = 300 + 20: the orthonormalisation Gram matrices are 320 x 320
-    m, n, k, p, q = 1500, 1000, 300, 20, 1
+@pytest.mark.parametrize("k,p", [(300, 20), (260, 20), (250, 38)])
+def test_sketch_wide_orth_q1_fp64(k, p):
+    # l = k + p: Gram matrices of order 320, 280 and 288
+    m, n, q = 1500, 1000, 1
     say(f"id_col sketch fp64 {m}x{n} k={k} p={p} q={q}")
     A = _case(m, n, seed=7, decay=120.0)
     om = synth.gaussian(k + p, m, seed=8)
@@ -63,8 +65,9 @@ def test_sketch_wide_orth_q1_fp64():
     assert e_g <= (1 + 1e-6) * e_o
 
 
-def test_cur_fp64_k300():
-    m, n, k = 800, 650, 300
+@pytest.mark.parametrize("k", [300, 288, 270])
+def test_cur_fp64_k300(k):
+    m, n = 800, 650
     say(f"cur det fp64 {m}x{n} k={k}")
     A = _case(m, n, seed=12, decay=120.0)
     ref = oracle.cur(A, k)
