@@ -53,6 +53,8 @@ struct CArgs {
   int mode;
   int keep_l;   // mode 0: store the factor to L (else L is only the working matrix)
   int* status;
+  int bsz;      // mode 1 with a grid of several workgroups: workgroup p inverts the
+                // diagonal block [p bsz, min((p + 1) bsz, c))^2 of G into X
 };
 
 // strided read-only view, padded with the identity outside [0, c)^2
@@ -407,6 +409,12 @@ __device__ __noinline__ void item_diag(View A, double* L, int64_t ldl, int q, bo
 }
 
 __global__ __launch_bounds__(kCT) void chol_inv_kernel(CArgs a) {
+  if (gridDim.x > 1) {   // independent diagonal blocks (mode 1, no device order)
+    const int o = (int)blockIdx.x * a.bsz;
+    a.G += (int64_t)o * a.gr + (int64_t)o * a.gc;
+    a.X += (int64_t)o * a.ldx + o;
+    a.c_host = min(a.bsz, a.c_host - o);
+  }
   const int c = a.c_dev ? min(*a.c_dev, a.c_host) : a.c_host;
   if (c <= 0) return;
   const int T = (c + kTS - 1) / kTS;
@@ -500,6 +508,21 @@ hipError_t chol_inv_launch(int mode, const double* G, int64_t gr, int64_t gc, in
   if (e != hipSuccess) return e;
   void* args[] = {&a};
   return hipLaunchKernel((const void*)chol_inv_kernel, dim3(1), dim3(kCT), args, lds, stream);
+}
+
+hipError_t chol_inv_diag_launch(const double* F, int64_t ldf, int c, int bsz, double* X, int64_t ldx, int* status,
+                                hipStream_t stream) {
+  if (c <= 0) return hipSuccess;
+  if (bsz <= 0 || bsz > kMaxC) return hipErrorInvalidValue;
+  CArgs a{};
+  a.G = F; a.gr = ldf; a.gc = 1; a.c_host = c; a.c_dev = nullptr;
+  a.L = nullptr; a.ldl = 0; a.X = X; a.ldx = ldx; a.shift_rel = 0.0; a.mode = 1; a.status = status;
+  a.bsz = bsz;
+  const size_t lds = chol_inv_lds_bytes(bsz);
+  hipError_t e = hipFuncSetAttribute((const void*)chol_inv_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  void* args[] = {&a};
+  return hipLaunchKernel((const void*)chol_inv_kernel, dim3((unsigned)ceil_div(c, bsz)), dim3(kCT), args, lds, stream);
 }
 
 }  // namespace idcur

@@ -186,11 +186,13 @@ void chol_inv(const Ctx& x, int mode, const double* G, int64_t gr, int64_t gc, i
     g.alpha = alpha; g.beta = beta;
     gemm(x, g);
   };
+  // mode 1: the diagonal blocks are independent, one workgroup each in one launch
+  if (mode == 1 && !x.dry) x.check(chol_inv_diag_launch(P, c, c, b, X, ldx, x.c->dstatus, x.s), what);
   for (int p = 0; p < nb; ++p) {
     const int o = p * b, sp = std::min(b, c - o);
-    if (!x.dry)
-      x.check(chol_inv_launch(mode, P + (int64_t)o * c + o, c, 1, sp, nullptr, mode == 0 ? L + (int64_t)o * ldl + o : nullptr,
-                              ldl, X + (int64_t)o * ldx + o, ldx, 0.0, x.c->dstatus, x.s),
+    if (mode == 0 && !x.dry)
+      x.check(chol_inv_launch(mode, P + (int64_t)o * c + o, c, 1, sp, nullptr, L + (int64_t)o * ldl + o, ldl,
+                              X + (int64_t)o * ldx + o, ldx, 0.0, x.c->dstatus, x.s),
               what);
     const int r = c - o - sp;
     if (mode == 0 && r > 0) {

@@ -250,6 +250,11 @@ size_t chol_inv_lds_bytes(int c_host);
 hipError_t chol_inv_launch(int mode, const double* G, int64_t gr, int64_t gc, int c_host, const int* c_dev, double* L,
                            int64_t ldl, double* X, int64_t ldx, double shift_rel, int* status, hipStream_t stream,
                            int keep_l = 1);
+// Mode 1 on the diagonal blocks of order bsz (at most 256, the kernel's limit) of
+// the lower factor F (c x c, row-major ld ldf), one workgroup each, at once:
+// X's diagonal block p = the inverse of F's.
+hipError_t chol_inv_diag_launch(const double* F, int64_t ldf, int c, int bsz, double* X, int64_t ldx, int* status,
+                                hipStream_t stream);
 
 // S11 = S(0:c, J(0:c)) into a dense c x c double matrix (row-major, ld c_host).
 hipError_t gather_s11_launch(int dtype, const void* S, int64_t ldS, const int* J, int c_host,
