@@ -591,11 +591,6 @@ void row_id_of_c(const Ctx& x, int dtype, const void* C, int64_t ldc, int64_t m,
 // R^T = Q S_R with S_R = L2^T L1^T and Q^T = L2^{-1} Q1^T, so
 // U^T = S_R^{-1} Q^T V = L1^{-T} L2^{-T} L2^{-1} (Q1^T V): Q itself is never
 // formed; L2^{-1} is applied to the k x k product Q1^T V instead.
-// FP32 data takes one pass, U^T = L1^{-T} L1^{-1} (R V) with L1 L1^T = R R^T:
-// the products of FP32 entries are exact in FP64, so the FP64 solve errs by
-// about u64 cond(R)^2, below what rounding R and V* to FP32 already costs the
-// least-squares solution (at least u32 cond(R)) for any cond(R) < u32 / u64,
-// about 5e8. FP64 data keeps the second pass (its own error is u64 cond(R)).
 // Every step is a matrix-core product with the explicit triangular inverses.
 // R: kr x n (row-major ldr), V* from (J, T); k = kout[0] columns, kr = kout[1].
 // With `corr` (A, lda, m and C = A(:, J(1:k)), m x kcap ld kcap given) the right
@@ -611,10 +606,9 @@ void solve_u(const Ctx& x, int dtype, const void* R, int64_t ldr, int64_t n, int
   double* G = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
   double* L1 = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
   double* L1i = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
-  const bool two_pass = dtype != IDCUR_F32;
-  double* L2 = two_pass ? static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8)) : nullptr;
-  double* L2i = two_pass ? static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8)) : nullptr;
-  double* Q1t = two_pass ? static_cast<double*>(x.ar->take((size_t)kcap * n * 8)) : nullptr;
+  double* L2 = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
+  double* L2i = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
+  double* Q1t = static_cast<double*>(x.ar->take((size_t)kcap * n * 8));
   double* B1 = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
   double* V = static_cast<double*>(x.ar->take((size_t)n * kcap * 8));
   double* Bls = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
@@ -635,13 +629,12 @@ void solve_u(const Ctx& x, int dtype, const void* R, int64_t ldr, int64_t n, int
   // G1 = R R^T, L1 L1^T = G1
   prod(kcap, kcap, n, R, ldr, 1, dtype, R, 1, ldr, dtype, G, kcap, 0, kr_dev, kr_dev, nullptr, true);
   chol_inv(x, 0, G, kcap, 1, kcap, kr_dev, L1, kcap, L1i, kcap, 1e-15, "chol(R)", false);
-  if (two_pass) {
-    // Q1^T = L1^{-1} R
-    prod(kcap, n, kcap, L1i, kcap, 1, 0, R, ldr, 1, dtype, Q1t, n, 0, kr_dev, nullptr, kr_dev);
-    // G2 = Q1^T Q1, L2 L2^T = G2
-    prod(kcap, kcap, n, Q1t, n, 1, 0, Q1t, 1, n, 0, G, kcap, 0, kr_dev, kr_dev, nullptr, true);
-    chol_inv(x, 0, G, kcap, 1, kcap, kr_dev, L2, kcap, L2i, kcap, 0.0, "chol(Q1)", false);
-  }
+  // Q1^T = L1^{-1} R
+  prod(kcap, n, kcap, L1i, kcap, 1, 0, R, ldr, 1, dtype, Q1t, n, 0, kr_dev, nullptr, kr_dev);
+  // G2 = Q1^T Q1, L2 L2^T = G2
+  prod(kcap, kcap, n, Q1t, n, 1, 0, Q1t, 1, n, 0, G, kcap, 0, kr_dev, kr_dev, nullptr, true);
+  chol_inv(x, 0, G, kcap, 1, kcap, kr_dev, L2, kcap, L2i, kcap, 0.0, "chol(Q1)", false);
+  // Bls = Q^T V = L2^{-1} (Q1^T V) (kr x k)
   if (!x.dry) x.check(build_v_launch(dtype, T, ldt, J, n, kcap, k_dev, V, kcap, x.s), "build V");
   if (corr) {
     double* Gc = static_cast<double*>(x.ar->take((size_t)kcap * kcap * 8));
@@ -673,17 +666,10 @@ void solve_u(const Ctx& x, int dtype, const void* R, int64_t ldr, int64_t n, int
     h.n_dev = k_dev; h.k_dev = k_dev;
     gemm(x, h);
   }
-  if (two_pass) {
-    // Bls = Q^T V = L2^{-1} (Q1^T V) (kr x k)
-    prod(kcap, kcap, n, Q1t, n, 1, 0, V, kcap, 1, 0, B1, kcap, 0, kr_dev, k_dev, nullptr);
-    prod(kcap, kcap, kcap, L2i, kcap, 1, 0, B1, kcap, 1, 0, Bls, kcap, 0, kr_dev, k_dev, kr_dev);
-    // Y1 = L2^{-T} Bls  (A(i, kk) = L2i[kk][i])
-    prod(kcap, kcap, kcap, L2i, 1, kcap, 0, Bls, kcap, 1, 0, Y1, kcap, 0, kr_dev, k_dev, kr_dev);
-  } else {
-    // Y1 = L1^{-1} (R V)
-    prod(kcap, kcap, n, R, ldr, 1, dtype, V, kcap, 1, 0, B1, kcap, 0, kr_dev, k_dev, nullptr);
-    prod(kcap, kcap, kcap, L1i, kcap, 1, 0, B1, kcap, 1, 0, Y1, kcap, 0, kr_dev, k_dev, kr_dev);
-  }
+  prod(kcap, kcap, n, Q1t, n, 1, 0, V, kcap, 1, 0, B1, kcap, 0, kr_dev, k_dev, nullptr);
+  prod(kcap, kcap, kcap, L2i, kcap, 1, 0, B1, kcap, 1, 0, Bls, kcap, 0, kr_dev, k_dev, kr_dev);
+  // Y1 = L2^{-T} Bls  (A(i, kk) = L2i[kk][i])
+  prod(kcap, kcap, kcap, L2i, 1, kcap, 0, Bls, kcap, 1, 0, Y1, kcap, 0, kr_dev, k_dev, kr_dev);
   // U = Y1^T L1^{-1}  (k x kr): A(i, kk) = Y1[kk][i]
   prod(kcap, kcap, kcap, Y1, 1, kcap, 0, L1i, kcap, 1, 0, U, ldu, dtype, k_dev, kr_dev, kr_dev);
 }
