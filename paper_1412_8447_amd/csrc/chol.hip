@@ -437,16 +437,19 @@ __global__ __launch_bounds__(kCT) void chol_inv_kernel(CArgs a) {
       for (int w = 0; w < kWaves; ++w) mx = fmax(mx, sm[kSmax + w]);
       sh = a.shift_rel * mx;
     }
+    // sixteen loads in flight per thread before the stores (which the compiler
+    // keeps behind the loads, not knowing that G and L never overlap)
     const int total = c * c;
-    for (int e0 = 0; e0 < total; e0 += kCT * 4) {
-      double v[4];
+    constexpr int kU = 16;
+    for (int e0 = 0; e0 < total; e0 += kCT * kU) {
+      double v[kU];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kU; ++u) {
         const int e = min(e0 + u * kCT + tid, total - 1);
         v[u] = a.G[(int64_t)(e / c) * a.gr + (int64_t)(e % c) * a.gc];
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kU; ++u) {
         const int e = e0 + u * kCT + tid;
         if (e < total) {
           const int i = e / c, j = e % c;
