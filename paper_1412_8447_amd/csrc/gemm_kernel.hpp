@@ -271,8 +271,17 @@ __global__ __launch_bounds__(256) void splitk_reduce(const TAcc* part, int split
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = e / N, j = e % N;
     if (i >= Mb || j >= Nb) continue;
+    // the partial sums in split order, eight loads in flight at a time
     double s = 0.0;
-    for (int z = 0; z < splitk; ++z) s += (double)part[(int64_t)z * total + e];
+    int z = 0;
+    for (; z + 8 <= splitk; z += 8) {
+      TAcc v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(z + u) * total + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += (double)v[u];
+    }
+    for (; z < splitk; ++z) s += (double)part[(int64_t)z * total + e];
     if (out_type == 1) {
       float* c = static_cast<float*>(C) + i * ldc + j;
       *c = (float)(alpha * s + (beta != 0.0 ? beta * (double)*c : 0.0));
