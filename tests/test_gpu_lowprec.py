@@ -181,3 +181,19 @@ def test_lowprec_on_power_spectrum(prec):
     assert e_g <= 1.05 * e_16
     if prec == "fp16":
         assert e_16 <= 1.10 * e_64
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_cur_lowprec_bitwise_repeat(prec):
+    """Two 16-bit CUR calls on the same input and seed give identical J, I, C, U
+    and R: the wide kernel's K splits, the Gram products' splits and every other
+    reduction are summed in a fixed order (sketch width 320, wide form)."""
+    m, n, k, p, q = 4000, 3000, 300, 20, 1
+    say(f"cur {prec} bitwise repeat {m}x{n} k={k} p={p} q={q}")
+    A = synth.lowrank(m, n, synth.sigma_exp(min(m, n), 40.0), seed=61).astype(np.float32)
+    dA = to_dev(A, torch.float32)
+    a = P.cur(dA, k, p=p, q=q, seed=62, prec=prec)
+    b = P.cur(dA, k, p=p, q=q, seed=62, prec=prec)
+    assert a.k == b.k and a.k_row == b.k_row
+    for x, y in ((a.J, b.J), (a.I, b.I), (a.C, b.C), (a.U, b.U), (a.R, b.R)):
+        assert torch.equal(x, y)
